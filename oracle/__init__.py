@@ -1,0 +1,258 @@
+"""ctypes binding of the FP64 CPU oracle (``oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may use it; the GPU library never does.  Inputs are the float32 arrays of
+``paper_2412_20720_amd.scenes`` promoted to float64, so input rounding is not counted as error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.cpp")
+
+# Renderer settings (readings of the paper where it is silent; see the oracle header) and the
+# parity margins within which a discrete decision is marked as legitimately ambiguous between
+# FP32 and FP64.
+DEFAULT_SETTINGS: Dict[str, float] = dict(
+    near_z=0.2, marginal_min=1.0 / 255.0, cutoff_sigma=3.0, blur=0.3, jacobian_margin=0.15,
+    alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, color_offset=0.5, color_min=0.0,
+    time_period=1.0,
+    margin_d2=2e-4, margin_alpha=1e-3, margin_T=1e-3, margin_depth=2e-5, margin_cull=1e-4,
+)
+
+# Smooth settings for finite differences: the jumps left are at most exp(-12.5) per pixel.
+SMOOTH_SETTINGS = dict(DEFAULT_SETTINGS, cutoff_sigma=5.0, alpha_min=1e-6, T_min=1e-8,
+                       marginal_min=1e-8)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with g++ (-O2, OpenMP)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH + ".tmp",
+           SRC_PATH]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class _Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("t_degree", C.c_int32),
+                ("mean4", C.POINTER(C.c_double)), ("scale4", C.POINTER(C.c_double)),
+                ("rot_l", C.POINTER(C.c_double)), ("rot_r", C.POINTER(C.c_double)),
+                ("opacity", C.POINTER(C.c_double)), ("sh", C.POINTER(C.c_double))]
+
+
+class _View(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("world_to_cam", C.c_double * 12), ("t", C.c_double),
+                ("background", C.c_double * 3)]
+
+
+_SETTING_NAMES = ["near_z", "marginal_min", "cutoff_sigma", "blur", "jacobian_margin",
+                  "alpha_min", "alpha_max", "T_min", "color_offset", "color_min", "time_period",
+                  "margin_d2", "margin_alpha", "margin_T", "margin_depth", "margin_cull"]
+
+
+class _Settings(C.Structure):
+    _fields_ = [(k, C.c_double) for k in _SETTING_NAMES]
+
+
+class _Grads(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in
+                ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")]
+
+
+SPLAT_DTYPE = np.dtype([("alive", np.int32), ("optional", np.int32), ("depth", np.float64),
+                        ("mean2d", np.float64, 2), ("cov2d", np.float64, 3),
+                        ("conic", np.float64, 3), ("p_t", np.float64), ("opt", np.float64),
+                        ("color", np.float64, 3), ("mean3", np.float64, 3),
+                        ("cov3", np.float64, 6)])
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_rotation.argtypes = [dp, dp, dp]
+        L.orc_slice.argtypes = [dp, dp, dp, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_legendre.argtypes = [C.c_int, C.c_int, C.c_double]
+        L.orc_legendre.restype = C.c_double
+        L.orc_sh_basis.argtypes = [C.c_int, dp, dp]
+        L.orc_frame_new.argtypes = [C.POINTER(_Gaussians), C.POINTER(_View),
+                                    C.POINTER(_Settings), C.c_int]
+        L.orc_frame_new.restype = C.c_void_p
+        L.orc_frame_free.argtypes = [C.c_void_p]
+        L.orc_frame_splats.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_frame_render.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_frame_variants.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_void_p, C.c_void_p]
+        L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Grads)]
+        L.orc_frame_backward_splat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32), dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def rotation(q_l, q_r) -> np.ndarray:
+    """4x4 rotation L(q_l/|q_l|) R(q_r/|q_r|) (float64 inputs taken as given)."""
+    ql = np.ascontiguousarray(q_l, np.float64)
+    qr = np.ascontiguousarray(q_r, np.float64)
+    R = np.zeros(16)
+    lib().orc_rotation(_dp(ql), _dp(qr), _dp(R))
+    return R.reshape(4, 4)
+
+
+def slice_gaussian(mean4, scale4, q_l, q_r, t):
+    """(Sigma4, conditional mean, conditional covariance, p(t)) in float64."""
+    args = [np.ascontiguousarray(x, np.float64) for x in (mean4, scale4, q_l, q_r)]
+    cov4, mu, cov3, pt = np.zeros(16), np.zeros(3), np.zeros(9), np.zeros(1)
+    lib().orc_slice(*[_dp(a) for a in args], float(t), _dp(cov4), _dp(mu), _dp(cov3), _dp(pt))
+    return cov4.reshape(4, 4), mu, cov3.reshape(3, 3), float(pt[0])
+
+
+def legendre(l: int, m: int, x: float) -> float:
+    return float(lib().orc_legendre(l, m, float(x)))
+
+
+def sh_basis(deg: int, direction) -> np.ndarray:
+    d = np.ascontiguousarray(direction, np.float64)
+    Y = np.zeros((deg + 1) ** 2)
+    lib().orc_sh_basis(deg, _dp(d), _dp(Y))
+    return Y
+
+
+class Frame:
+    """All Gaussians of a scene preprocessed in FP64 for one view."""
+
+    def __init__(self, arrays: Dict[str, np.ndarray], sh_degree: int, t_degree: int, view: Dict,
+                 settings: Optional[Dict[str, float]] = None, use_bins: bool = True,
+                 exact_f64: bool = False):
+        st = dict(DEFAULT_SETTINGS)
+        if settings:
+            st.update(settings)
+        conv = (lambda a: np.ascontiguousarray(a, np.float64)) if exact_f64 else _f64
+        self._arrays = {k: conv(arrays[k]) for k in
+                        ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")}
+        self.n = int(self._arrays["mean4"].shape[0])
+        self.sh_degree, self.t_degree = int(sh_degree), int(t_degree)
+        assert self._arrays["sh"].size == self.n * (t_degree + 1) * (sh_degree + 1) ** 2 * 3
+        self.view = view
+        self.width, self.height = int(view["width"]), int(view["height"])
+        g = _Gaussians(self.n, self.sh_degree, self.t_degree,
+                       *[_dp(self._arrays[k]) for k in
+                         ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
+        conv_s = (lambda x: float(x)) if exact_f64 else (lambda x: float(np.float32(x)))
+        v = _View(self.width, self.height, conv_s(view["fx"]), conv_s(view["fy"]),
+                  conv_s(view["cx"]), conv_s(view["cy"]),
+                  (C.c_double * 12)(*[conv_s(x) for x in np.asarray(view["world_to_cam"]).ravel()]),
+                  conv_s(view["t"]),
+                  (C.c_double * 3)(*[conv_s(x) for x in np.asarray(view["background"]).ravel()]))
+        s = _Settings(*[float(st[k]) for k in _SETTING_NAMES])
+        self.settings = st
+        self._h = lib().orc_frame_new(C.byref(g), C.byref(v), C.byref(s), int(use_bins))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().orc_frame_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def splats(self) -> np.ndarray:
+        out = np.zeros(self.n, SPLAT_DTYPE)
+        lib().orc_frame_splats(self._h, out.ctypes.data)
+        return out
+
+    def render(self, xy: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+        """Render the listed pixels (int (x, y) pairs) or, with xy=None, the whole image."""
+        if xy is None:
+            n = self.width * self.height
+            xyp = None
+        else:
+            xyp = np.ascontiguousarray(xy, np.int32).reshape(-1, 2)
+            n = xyp.shape[0]
+        rgb = np.zeros((n, 3))
+        T = np.zeros(n)
+        nc = np.zeros(n, np.int32)
+        nm = np.zeros(n, np.int32)
+        ne = np.zeros(n, np.int64)
+        lib().orc_frame_render(self._h, n, None if xyp is None else xyp.ctypes.data,
+                               rgb.ctypes.data, T.ctypes.data, nc.ctypes.data, nm.ctypes.data,
+                               ne.ctypes.data)
+        out = dict(rgb=rgb, T=T, n_contrib=nc, n_marks=nm, n_evals=ne)
+        if xy is None:
+            H, W = self.height, self.width
+            out = dict(rgb=rgb.reshape(H, W, 3).transpose(2, 0, 1).copy(), T=T.reshape(H, W),
+                       n_contrib=nc.reshape(H, W), n_marks=nm.reshape(H, W),
+                       n_evals=ne.reshape(H, W))
+        return out
+
+    def variants(self, x: int, y: int, max_marks: int = 4):
+        """All admissible (rgb, T) of pixel (x, y), or None if it has too many marked decisions."""
+        cap = 1 << max_marks
+        rgb = np.zeros((cap, 3))
+        T = np.zeros(cap)
+        nv = lib().orc_frame_variants(self._h, int(x), int(y), max_marks, cap, rgb.ctypes.data,
+                                      T.ctypes.data)
+        if nv < 0:
+            return None
+        return rgb[:nv], T[:nv]
+
+    def backward(self, dL_drgb: np.ndarray, grads: Optional[Dict[str, np.ndarray]] = None):
+        """Accumulate d<dL_drgb, image>/d(params) into ``grads`` (float64; created if None)."""
+        if grads is None:
+            grads = {k: np.zeros_like(a) for k, a in self._arrays.items()}
+        g = np.ascontiguousarray(dL_drgb, np.float64).reshape(3, self.height, self.width)
+        gs = _Grads(*[_dp(grads[k]) for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
+        lib().orc_frame_backward(self._h, g.ctypes.data, C.byref(gs))
+        return grads
+
+    def backward_splat(self, dL_drgb: np.ndarray) -> np.ndarray:
+        """Per-Gaussian gradient of (u, v, conic a, b, c, opacity*p_t, r, g, b): [n, 9]."""
+        g = np.ascontiguousarray(dL_drgb, np.float64).reshape(3, self.height, self.width)
+        out = np.zeros((self.n, 9))
+        lib().orc_frame_backward_splat(self._h, g.ctypes.data, out.ctypes.data)
+        return out
+
+
+def render_scene_view(scene, view_index: int = 0, settings=None, xy=None, use_bins=True):
+    """Convenience: oracle render of one view of a ``scenes.Scene``."""
+    st = dict(settings or {})
+    st.setdefault("time_period", scene.time_period)
+    with Frame(scene.arrays(), scene.sh_degree, scene.t_degree, scene.views[view_index], st,
+               use_bins=use_bins) as f:
+        return f.render(xy)
