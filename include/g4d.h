@@ -1,0 +1,172 @@
+/* g4d: differentiable render of native 4D Gaussians on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "4D Gaussian Splatting: Modeling Dynamic Scenes with Native 4D Primitives"
+ * (arXiv 2412.20720).  A pixel (u, v) of a view with extrinsic E, intrinsic K and time t is
+ *   I(u, v, t) = sum_i p_i(t) p_i(u, v | t) alpha_i c_i(d, dt) prod_{j<i} (1 - p_j(t) p_j(u, v | t) alpha_j)
+ * (Sec. 3.2, eq:4dblending), where p_i(t) is the temporal marginal and p_i(u, v | t) the EWA
+ * splat (Sec. 3.1, eq:meansplatting / eq:covsplatting) of the conditional 3D Gaussian of the
+ * 4D Gaussian i at time t (Sec. 3.2, conditional mean and covariance), whose covariance is
+ * R S S^T R^T with R = L(q_l) R(q_r) built from two rotors (Sec. 3.2, 4D rotation), and
+ * c_i is a 4D spherindrical-harmonic color (Sec. 3.2).
+ *
+ * Conventions of this ABI:
+ *   - Pointers are device pointers (hipMalloc / PyTorch CUDA tensors) unless marked (host).
+ *   - Arrays are float32, row-major, structure of arrays.  Nothing is ever freed or kept by
+ *     the library beyond the call except inside the context.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default stream).
+ *   - Errors are returned as g4d_status; no exception crosses the ABI.  The message of the last
+ *     error is g4d_last_error(ctx).  One context must not be used by two threads at once.
+ */
+#ifndef G4D_H
+#define G4D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define G4D_VERSION 1
+/* Floats per (view, Gaussian) record written by g4d_preprocess (layout below). */
+#define G4D_RECORD_FLOATS 12
+/* Maximum views in one call, maximum image side, and maximum SH / Fourier degrees. */
+#define G4D_MAX_VIEWS 256
+#define G4D_MAX_SIDE 8192
+#define G4D_MAX_SH_DEGREE 3
+#define G4D_MAX_T_DEGREE 2
+
+typedef struct g4d_ctx g4d_ctx;
+
+typedef enum {
+  G4D_OK = 0,
+  G4D_EINVAL = -1,    /* an argument failed a host-side check; nothing was enqueued */
+  G4D_ENOMEM = -2,    /* a device allocation failed */
+  G4D_ECAPACITY = -3, /* the device found more (Gaussian, tile) pairs than the fixed capacity */
+  G4D_EHIP = -4,      /* a HIP runtime call failed */
+  G4D_ESTATE = -5     /* backward without a matching forward in this context */
+} g4d_status;
+
+/* A set of N 4D Gaussians (Sec. 3.2, "Representation of 4D Gaussian"):
+ *   mean4   [N,4]  (mu_x, mu_y, mu_z, mu_t)
+ *   scale4  [N,4]  (s_x, s_y, s_z, s_t) > 0, already activated
+ *   rot_l   [N,4]  left rotor (a, b, c, d); any nonzero length, normalized inside
+ *   rot_r   [N,4]  right rotor (p, q, r, s); any nonzero length, normalized inside
+ *   opacity [N]    in [0, 1], already activated
+ *   sh      [N, t_degree+1, (sh_degree+1)^2, 3]  4DSH coefficients k[n, l*l+l+m, channel]
+ *           (Sec. 3.2, Z = cos(2 pi n dt / T) Y_l^m; real Y without Condon-Shortley phase).
+ * sh_degree in 0..3, t_degree in 0..2, N >= 0. */
+typedef struct {
+  int32_t n, sh_degree, t_degree;
+  const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+} g4d_gaussians;
+
+/* Gradients, same shapes as g4d_gaussians; overwritten (not accumulated) with the sum over
+ * the call's views.  Any pointer may be NULL to skip that group (sh only if sh is NULL). */
+typedef struct {
+  float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+} g4d_grads;
+
+/* (host) One view: pinhole intrinsics K = (fx, fy, cx, cy), extrinsic world->camera
+ * E = [R | tau] row-major 3x4 with OpenCV axes (x right, y down, z forward), time t and
+ * background color (Sec. 3.1 "given a pixel (u, v) in view I with extrinsic E and intrinsic K";
+ * Sec. 3.2 adds the timestamp t).  Pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float world_to_cam[12];
+  float t;
+  float background[3];
+} g4d_view;
+
+/* (host) Render settings.  The paper leaves these unstated except the marginal filter
+ * (p(t) threshold, Sec. 4.1.1 implementation details); g4d_default_settings fills in:
+ *   near_z 0.2        cull when the camera-space depth of the sliced mean is <= near_z
+ *   marginal_min 1/255 cull when p(t) < marginal_min (the paper quotes 0.05)
+ *   cutoff_sigma 3    a splat covers pixels with Mahalanobis distance <= cutoff_sigma
+ *   blur 0.3          EWA low-pass: added to both diagonal entries of the 2D covariance (px^2)
+ *   jacobian_margin 0.15  the perspective Jacobian is evaluated at x/z, y/z clamped to the
+ *                     image widened by this fraction on each side
+ *   alpha_min 1/255   contributions with alpha below this are skipped
+ *   alpha_max 0.99    alpha = min(alpha_max, opacity p(t) p(u, v | t))
+ *   T_min 1e-4        a pixel stops before the Gaussian that would take T below T_min
+ *   color_offset 0.5, color_min 0   c = max(color_min, color_offset + 4DSH sum)
+ *   time_period 1     the period T of the Fourier basis of the 4DSH
+ *   tile_size 16      screen tile side in pixels (8, 16 or 32)
+ *   lds_batch 0       records staged per wave (0 = library choice) */
+typedef struct {
+  float near_z, marginal_min, cutoff_sigma, blur, jacobian_margin;
+  float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
+  int32_t tile_size, lds_batch;
+} g4d_settings;
+
+/* Work counters of the last forward (host). */
+typedef struct {
+  int64_t n_slots;      /* N * n_views */
+  int64_t n_visible;    /* (view, Gaussian) slots that survived every cull and touch a tile */
+  int64_t n_pairs;      /* (Gaussian, tile) pairs sorted */
+  int64_t n_tiles;      /* screen tiles over all views */
+  int64_t n_pixels;     /* pixels over all views */
+  int64_t pair_capacity;
+} g4d_stats;
+
+/* Fill *s with the defaults listed above.  Returns G4D_EINVAL if s is NULL. */
+g4d_status g4d_default_settings(g4d_settings *s);
+
+/* Create a context on HIP device `device`.  The context owns all scratch memory (grown on
+ * demand) and the state a forward leaves for its backward.  *out is NULL on failure. */
+g4d_status g4d_create(g4d_ctx **out, int device);
+
+/* Free the context and everything it owns (synchronizes its device first). */
+g4d_status g4d_destroy(g4d_ctx *ctx);
+
+/* Message of the last error on this context (never NULL; "" if none). */
+const char *g4d_last_error(const g4d_ctx *ctx);
+
+/* Per-(view, Gaussian) slice and splat only (Sec. 3.2 conditional Gaussian and marginal p(t);
+ * Sec. 3.1 eq:meansplatting, eq:covsplatting; 4DSH color).  Writes
+ *   records [n_views][N][G4D_RECORD_FLOATS]:
+ *     0 u, 1 v (screen mean, px), 2..4 conic (a, b, c) = inverse 2D covariance,
+ *     5 opacity * p(t), 6..8 rgb, 9..10 half extents of the cutoff ellipse box (px),
+ *     11 camera-space depth;
+ *   tiles [n_views][N] int32: number of screen tiles the splat's box covers, 0 if culled.
+ * Either output may be NULL. */
+g4d_status g4d_preprocess(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                          int32_t n_views, const g4d_settings *s, float *records, int32_t *tiles,
+                          void *stream);
+
+/* Forward render of n_views views in one batch (Sec. 3.2, eq:4dblending with the tile-based
+ * rasterizer of Sec. 3.2 "adapt the highly efficient tile-based rasterizer"):
+ *   out_rgb: per view planar [3][H][W], views concatenated in order;
+ *   out_T:   per view [H][W] final transmittance (may be NULL).
+ * Saves the state its backward needs in ctx. */
+g4d_status g4d_render_forward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                              int32_t n_views, const g4d_settings *s, float *out_rgb,
+                              float *out_T, void *stream);
+
+/* Backward of the last forward on this context with the same g, views and settings
+ * (else G4D_ESTATE): given dL/d(out_rgb) in the out_rgb layout, writes dL/d(parameters),
+ * summed over the views, into *out (derivative of eq:4dblending through the splat, the
+ * slice, the rotors and their normalization, and the 4DSH color; discrete decisions frozen). */
+g4d_status g4d_render_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                               int32_t n_views, const g4d_settings *s, const float *dL_drgb,
+                               const g4d_grads *out, void *stream);
+
+/* Wait for the context's work on `stream` and report errors found on the device
+ * (G4D_ECAPACITY when the pair capacity was exceeded; outputs are then undefined). */
+g4d_status g4d_sync_status(g4d_ctx *ctx, void *stream);
+
+/* Counters of the last forward; synchronizes `stream`. */
+g4d_status g4d_get_stats(g4d_ctx *ctx, g4d_stats *out, void *stream);
+
+/* Per-pixel evaluation counters: the number of (Gaussian, pixel) pairs whose Mahalanobis
+ * distance passes the cutoff and that the pixel visits before its transmittance stop (the
+ * algorithmic work of eq:4dblending).  enable = 1 makes later forwards count them (a small
+ * extra store per pixel), 0 stops counting.  If `out` (device, [total pixels] uint32, views
+ * concatenated) is not NULL, the counters of the last counted forward are copied there
+ * (G4D_ESTATE if there is none). */
+g4d_status g4d_eval_counters(g4d_ctx *ctx, int enable, uint32_t *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* G4D_H */

@@ -174,7 +174,9 @@ class Frame:
                   (C.c_double * 12)(*[conv_s(x) for x in np.asarray(view["world_to_cam"]).ravel()]),
                   conv_s(view["t"]),
                   (C.c_double * 3)(*[conv_s(x) for x in np.asarray(view["background"]).ravel()]))
-        s = _Settings(*[float(st[k]) for k in _SETTING_NAMES])
+        # Thresholds reach the GPU as float32; the oracle takes the same rounded values.
+        s = _Settings(*[float(st[k]) if (exact_f64 or k.startswith("margin_"))
+                        else float(np.float32(st[k])) for k in _SETTING_NAMES])
         self.settings = st
         self._h = lib().orc_frame_new(C.byref(g), C.byref(v), C.byref(s), int(use_bins))
 

@@ -1,0 +1,64 @@
+"""Parity checks of GPU results against the FP64 oracle (test infrastructure only).
+
+Images: every channel within `tol` of the oracle.  A pixel that misses is accepted only if the
+oracle marked one of its discrete decisions as within the FP32/FP64 margin (cutoff membership,
+alpha_min skip, transmittance stop, depth order of two contributors, a cull) and the GPU value
+matches one of the results of taking those decisions either way (at most `max_marks` of them;
+more is reported as unverified).
+
+Gradients: relative L2 error per parameter group.
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional
+
+import numpy as np
+
+
+def check_image(gpu_rgb: np.ndarray, frame, tol: float = 1e-4, xy: Optional[np.ndarray] = None,
+                max_marks: int = 4, ref=None) -> Dict:
+    """gpu_rgb: [3, H, W] (full image) or [n, 3] at the pixels xy."""
+    if ref is None:
+        ref = frame.render(xy)
+    if xy is None:
+        g = np.asarray(gpu_rgb, np.float64).reshape(3, -1).T
+        r = ref["rgb"].reshape(3, -1).T
+        marks = ref["n_marks"].reshape(-1)
+        W = frame.width
+        coords = np.stack([np.arange(g.shape[0]) % W, np.arange(g.shape[0]) // W], 1)
+    else:
+        g = np.asarray(gpu_rgb, np.float64).reshape(-1, 3)
+        r = ref["rgb"]
+        marks = ref["n_marks"]
+        coords = np.asarray(xy).reshape(-1, 2)
+    err = np.abs(g - r).max(1)
+    bad = np.nonzero(err > tol)[0]
+    resolved, unverified, failures = 0, 0, []
+    for p in bad:
+        if marks[p] == 0:
+            failures.append((int(coords[p][0]), int(coords[p][1]), float(err[p]), "unmarked"))
+            continue
+        var = frame.variants(int(coords[p][0]), int(coords[p][1]), max_marks)
+        if var is None:
+            unverified += 1
+            continue
+        if (np.abs(var[0] - g[p]).max(1) <= tol).any():
+            resolved += 1
+        else:
+            failures.append((int(coords[p][0]), int(coords[p][1]), float(err[p]), "no variant"))
+    ok = np.ones(len(err), bool)
+    ok[bad] = False
+    return dict(n=len(err), max_err=float(err.max()) if len(err) else 0.0,
+                max_err_agreeing=float(err[ok].max()) if ok.any() else 0.0,
+                n_marked=int((marks > 0).sum()), n_bad=int(len(bad)), n_resolved=resolved,
+                n_unverified=unverified, failures=failures[:20], n_failures=len(failures))
+
+
+def grad_rel_errors(gpu: Dict[str, np.ndarray], ref: Dict[str, np.ndarray]) -> Dict[str, float]:
+    out = {}
+    for k, r in ref.items():
+        g = np.asarray(gpu[k], np.float64).reshape(-1)
+        r = np.asarray(r, np.float64).reshape(-1)
+        nr = np.linalg.norm(r)
+        out[k] = float(np.linalg.norm(g - r) / nr) if nr > 0 else float(np.linalg.norm(g))
+    return out

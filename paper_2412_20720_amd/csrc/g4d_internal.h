@@ -1,0 +1,85 @@
+// Internal launchers shared by the runtime and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "g4d_device.h"
+
+namespace g4d {
+
+constexpr int kScanItems = 4096;  // items per workgroup in scans and radix-sort passes
+constexpr int kSortThreads = 256;
+
+// p[0..n) = v (a kernel, not a memset node, so that captured graphs replay it correctly).
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+
+// Scratch needed by scan_* for up to `n` items (bytes).
+size_t scan_scratch_bytes(int64_t n);
+
+// Stream compaction of visible slots: for every slot with tiles[slot] > 0, in slot order,
+// writes (depth key, slot) to (out_key, out_val); the count goes to *n_out (device).
+void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
+                     uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
+                     hipStream_t st);
+
+// offsets[i] = sum_{k<i} tiles[val[k]] for i < *n_dev (exclusive); total to *total (device).
+void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_dev,
+                  int64_t n_cap, uint32_t* offsets, uint32_t* total, void* scratch,
+                  hipStream_t st);
+
+// Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
+// n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.
+size_t radix_scratch_bytes(int64_t n_cap);
+int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
+               int bits, void* scratch, hipStream_t st);
+
+// One (tile id, slot) pair per covered tile, records visited in depth order.
+void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
+            const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval, uint32_t* overflow,
+            hipStream_t st);
+
+// ranges[tile] = [first, last+1) of the tile's pairs in the sorted key array.
+void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
+                 int64_t n_tiles, uint2* ranges, hipStream_t st);
+
+// Derive camera centres and Jacobian clamps of the views on the device.
+void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st);
+
+struct GaussPtrs {
+  int n, sh_degree, t_degree;
+  const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+};
+struct GradPtrs {
+  float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+};
+
+void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
+                        float* rec, uint32_t* tiles, uint32_t* dkey, hipStream_t st);
+void preprocess_backward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
+                         const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                         hipStream_t st);
+
+struct RasterArgs {
+  const float* rec;
+  const uint32_t* pval;
+  const uint2* ranges;
+  const DView* views;
+  const int32_t* tile_base;  // n_views + 1 prefix of tiles per view
+  int n_views;
+  int n_tiles;
+  DSettings S;
+  float* out_rgb;
+  float* out_T;
+  float* px_T;
+  int32_t* px_last;
+  uint32_t* px_evals;        // optional per-pixel evaluation counter
+  const float* dL;           // backward
+  float* grad2d;             // backward
+};
+
+void raster_forward(const RasterArgs& a, hipStream_t st);
+void raster_backward(const RasterArgs& a, hipStream_t st);
+
+}  // namespace g4d

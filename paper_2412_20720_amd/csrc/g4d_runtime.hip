@@ -1,0 +1,518 @@
+// Host runtime behind the C ABI of include/g4d.h: argument checks, per-batch planning (tile
+// grids and pixel offsets of every view), device scratch management and the launch sequence
+//   view setup -> preprocess -> compaction -> depth sort -> pair offsets -> key generation
+//   -> tile sort -> tile ranges -> raster            (forward)
+//   raster backward -> preprocess backward           (backward)
+// All arithmetic of the render happens in the kernels; the host only does integer planning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/g4d.h"
+#include "g4d_internal.h"
+
+using namespace g4d;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct SavedKey {
+  int32_t n = -1, sh_degree = 0, t_degree = 0, n_views = 0;
+  const void* ptrs[6] = {};
+  std::vector<g4d_view> views;
+  g4d_settings s{};
+};
+
+}  // namespace
+
+struct g4d_ctx {
+  int device = 0;
+  std::string err;
+  DevBuf views, tile_base, rec, tiles, dkey, vk[2], vv[2], voff, pk[2], pv[2], scan_tmp,
+      sort_tmp, ranges, px_T, px_last, px_evals, grad2d, counters;
+  uint32_t* h_counters = nullptr;  // pinned: visible, pairs, overflow
+  DView* h_views = nullptr;        // pinned staging
+  int32_t* h_tile_base = nullptr;  // pinned staging
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+  int64_t pair_cap = 0;
+  // state left by the last forward
+  bool saved = false;
+  SavedKey key;
+  int vis_buf = 0, pair_buf = 0;
+  int64_t n_tiles = 0, n_pixels = 0;
+  g4d_stats stats{};
+  bool count_evals = false;
+};
+
+namespace {
+
+g4d_status fail(g4d_ctx* c, g4d_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define G4D_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, G4D_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
+  if (bytes == 0) bytes = 256;
+  if (bytes <= b.cap) return G4D_OK;
+  const size_t want = std::max(bytes, (size_t)((double)bytes * grow));
+  if (b.p) {
+    G4D_HIP(hipDeviceSynchronize());
+    G4D_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, G4D_ENOMEM, "hipMalloc of %zu bytes failed", want);
+  }
+  b.cap = want;
+  return G4D_OK;
+}
+
+template <class T>
+T* P(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                        int32_t n_views, const g4d_settings* s) {
+  if (!ctx) return G4D_EINVAL;
+  if (!g || !views || !s) return fail(ctx, G4D_EINVAL, "null gaussians, views or settings");
+  if (g->n < 0) return fail(ctx, G4D_EINVAL, "n = %d < 0", g->n);
+  if (g->sh_degree < 0 || g->sh_degree > G4D_MAX_SH_DEGREE)
+    return fail(ctx, G4D_EINVAL, "sh_degree %d outside 0..%d", g->sh_degree, G4D_MAX_SH_DEGREE);
+  if (g->t_degree < 0 || g->t_degree > G4D_MAX_T_DEGREE)
+    return fail(ctx, G4D_EINVAL, "t_degree %d outside 0..%d", g->t_degree, G4D_MAX_T_DEGREE);
+  if (g->n > 0 && (!g->mean4 || !g->scale4 || !g->rot_l || !g->rot_r || !g->opacity || !g->sh))
+    return fail(ctx, G4D_EINVAL, "null Gaussian parameter array");
+  if (n_views < 1 || n_views > G4D_MAX_VIEWS)
+    return fail(ctx, G4D_EINVAL, "n_views %d outside 1..%d", n_views, G4D_MAX_VIEWS);
+  if ((int64_t)g->n * n_views > (int64_t)INT32_MAX)
+    return fail(ctx, G4D_EINVAL, "n * n_views = %lld exceeds 2^31-1", (long long)g->n * n_views);
+  for (int v = 0; v < n_views; ++v) {
+    const g4d_view& V = views[v];
+    if (V.width < 1 || V.height < 1 || V.width > G4D_MAX_SIDE || V.height > G4D_MAX_SIDE)
+      return fail(ctx, G4D_EINVAL, "view %d: size %dx%d outside 1..%d", v, V.width, V.height,
+                  G4D_MAX_SIDE);
+    if (!(V.fx > 0.f) || !(V.fy > 0.f) || !finite(V.fx) || !finite(V.fy) || !finite(V.cx) ||
+        !finite(V.cy) || !finite(V.t))
+      return fail(ctx, G4D_EINVAL, "view %d: bad intrinsics or time", v);
+    for (int k = 0; k < 12; ++k)
+      if (!finite(V.world_to_cam[k])) return fail(ctx, G4D_EINVAL, "view %d: bad extrinsic", v);
+  }
+  if (!(s->cutoff_sigma > 0.f) || !(s->alpha_max > 0.f) || !(s->alpha_max <= 1.f) ||
+      !(s->alpha_min >= 0.f) || !(s->T_min >= 0.f) || !(s->time_period > 0.f) ||
+      !(s->blur >= 0.f) || !(s->jacobian_margin >= 0.f) || !finite(s->near_z) ||
+      !finite(s->marginal_min) || !finite(s->color_offset) || std::isnan(s->color_min))
+    return fail(ctx, G4D_EINVAL, "invalid settings");
+  if (s->tile_size != 8 && s->tile_size != 16 && s->tile_size != 32)
+    return fail(ctx, G4D_EINVAL, "tile_size %d not in {8, 16, 32}", s->tile_size);
+  return G4D_OK;
+}
+
+DSettings device_settings(const g4d_settings* s) {
+  DSettings d{};
+  d.near_z = s->near_z;
+  d.marginal_min = s->marginal_min;
+  d.cutoff = s->cutoff_sigma;
+  d.cut2 = s->cutoff_sigma * s->cutoff_sigma;
+  d.blur = s->blur;
+  d.jac_margin = s->jacobian_margin;
+  d.alpha_min = s->alpha_min;
+  d.alpha_max = s->alpha_max;
+  d.T_min = s->T_min;
+  d.color_offset = s->color_offset;
+  d.color_min = s->color_min;
+  d.time_period = s->time_period;
+  d.tile = s->tile_size;
+  d.tile_shift = s->tile_size == 8 ? 3 : (s->tile_size == 16 ? 4 : 5);
+  return d;
+}
+
+GaussPtrs gauss_ptrs(const g4d_gaussians* g) {
+  return GaussPtrs{g->n, g->sh_degree, g->t_degree, g->mean4, g->scale4, g->rot_l, g->rot_r,
+                   g->opacity, g->sh};
+}
+
+// Plan tile grids and offsets, upload the view table and derive per-view constants.
+g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const g4d_settings* s,
+                        hipStream_t st) {
+  if (ctx->staging_pending) {
+    G4D_HIP(hipEventSynchronize(ctx->staging_done));
+    ctx->staging_pending = false;
+  }
+  const int T = s->tile_size;
+  int64_t tile_base = 0, pix_base = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const g4d_view& in = views[v];
+    DView& d = ctx->h_views[v];
+    std::memset(&d, 0, sizeof d);
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) d.W[3 * r + c] = in.world_to_cam[4 * r + c];
+      d.tau[r] = in.world_to_cam[4 * r + 3];
+    }
+    d.fx = in.fx;
+    d.fy = in.fy;
+    d.cx = in.cx;
+    d.cy = in.cy;
+    d.t = in.t;
+    for (int c = 0; c < 3; ++c) d.bg[c] = in.background[c];
+    d.width = in.width;
+    d.height = in.height;
+    d.tiles_x = (in.width + T - 1) / T;
+    d.tiles_y = (in.height + T - 1) / T;
+    d.tile_base = (int32_t)tile_base;
+    d.pix_base = (int32_t)pix_base;
+    ctx->h_tile_base[v] = (int32_t)tile_base;
+    tile_base += (int64_t)d.tiles_x * d.tiles_y;
+    pix_base += (int64_t)in.width * in.height;
+    if (pix_base > INT32_MAX || tile_base > INT32_MAX)
+      return fail(ctx, G4D_EINVAL, "total pixels of the batch exceed 2^31-1");
+  }
+  ctx->h_tile_base[n_views] = (int32_t)tile_base;
+  ctx->n_tiles = tile_base;
+  ctx->n_pixels = pix_base;
+  g4d_status r;
+  if ((r = ensure(ctx, ctx->views, sizeof(DView) * n_views)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->tile_base, sizeof(int32_t) * (n_views + 1))) != G4D_OK) return r;
+  G4D_HIP(hipMemcpyAsync(ctx->views.p, ctx->h_views, sizeof(DView) * n_views,
+                         hipMemcpyHostToDevice, st));
+  G4D_HIP(hipMemcpyAsync(ctx->tile_base.p, ctx->h_tile_base, sizeof(int32_t) * (n_views + 1),
+                         hipMemcpyHostToDevice, st));
+  G4D_HIP(hipEventRecord(ctx->staging_done, st));
+  ctx->staging_pending = true;
+  view_setup(P<DView>(ctx->views), n_views, s->jacobian_margin, st);
+  G4D_HIP(hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
+                          const g4d_settings* s, hipStream_t st, bool zero_records = false) {
+  const int64_t slots = (int64_t)g->n * n_views;
+  g4d_status r;
+  if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
+  if (zero_records) G4D_HIP(hipMemsetAsync(ctx->rec.p, 0, sizeof(float) * kRec * slots, st));
+  if ((r = ensure(ctx, ctx->tiles, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+  preprocess_forward(gauss_ptrs(g), P<DView>(ctx->views), n_views, device_settings(s),
+                     P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
+  G4D_HIP(hipGetLastError());
+  return G4D_OK;
+}
+
+bool same_key(const SavedKey& k, const g4d_gaussians* g, const g4d_view* views, int n_views,
+              const g4d_settings* s) {
+  if (k.n != g->n || k.sh_degree != g->sh_degree || k.t_degree != g->t_degree ||
+      k.n_views != n_views)
+    return false;
+  const void* p[6] = {g->mean4, g->scale4, g->rot_l, g->rot_r, g->opacity, g->sh};
+  for (int i = 0; i < 6; ++i)
+    if (p[i] != k.ptrs[i]) return false;
+  if (std::memcmp(k.views.data(), views, sizeof(g4d_view) * n_views) != 0) return false;
+  return std::memcmp(&k.s, s, sizeof(g4d_settings)) == 0;
+}
+
+int bits_for(int64_t n) {
+  int b = 0;
+  while (b < 32 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+g4d_status g4d_default_settings(g4d_settings* s) {
+  if (!s) return G4D_EINVAL;
+  s->near_z = 0.2f;
+  s->marginal_min = 1.f / 255.f;
+  s->cutoff_sigma = 3.f;
+  s->blur = 0.3f;
+  s->jacobian_margin = 0.15f;
+  s->alpha_min = 1.f / 255.f;
+  s->alpha_max = 0.99f;
+  s->T_min = 1e-4f;
+  s->color_offset = 0.5f;
+  s->color_min = 0.f;
+  s->time_period = 1.f;
+  s->tile_size = 16;
+  s->lds_batch = 0;
+  return G4D_OK;
+}
+
+g4d_status g4d_create(g4d_ctx** out, int device) {
+  if (!out) return G4D_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return G4D_EHIP;
+  }
+  g4d_ctx* ctx = new g4d_ctx;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_counters, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_views, sizeof(DView) * G4D_MAX_VIEWS, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_tile_base, sizeof(int32_t) * (G4D_MAX_VIEWS + 1), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    g4d_destroy(ctx);
+    return G4D_EHIP;
+  }
+  *out = ctx;
+  return G4D_OK;
+}
+
+g4d_status g4d_destroy(g4d_ctx* ctx) {
+  if (!ctx) return G4D_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->dkey,
+                    &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->voff,
+                    &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
+                    &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
+                    &ctx->grad2d, &ctx->counters};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+  if (ctx->h_views) (void)hipHostFree(ctx->h_views);
+  if (ctx->h_tile_base) (void)hipHostFree(ctx->h_tile_base);
+  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  delete ctx;
+  return G4D_OK;
+}
+
+const char* g4d_last_error(const g4d_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+g4d_status g4d_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                          int32_t n_views, const g4d_settings* s, float* records, int32_t* tiles,
+                          void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  if ((r = upload_views(ctx, views, n_views, s, st)) != G4D_OK) return r;
+  const int64_t slots = (int64_t)g->n * n_views;
+  if (slots == 0) return G4D_OK;
+  ctx->saved = false;  // the scratch records are overwritten
+  // The kernel writes visible slots only, so clearing the scratch first leaves culled rows 0.
+  if ((r = run_preprocess(ctx, g, n_views, s, st, records != nullptr)) != G4D_OK) return r;
+  if (records)
+    G4D_HIP(hipMemcpyAsync(records, ctx->rec.p, sizeof(float) * kRec * slots,
+                           hipMemcpyDeviceToDevice, st));
+  if (tiles)
+    G4D_HIP(hipMemcpyAsync(tiles, ctx->tiles.p, sizeof(uint32_t) * slots, hipMemcpyDeviceToDevice,
+                           st));
+  return G4D_OK;
+}
+
+g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                              int32_t n_views, const g4d_settings* s, float* out_rgb,
+                              float* out_T, void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  if (!out_rgb) return fail(ctx, G4D_EINVAL, "null out_rgb");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  ctx->saved = false;
+  if ((r = upload_views(ctx, views, n_views, s, st)) != G4D_OK) return r;
+  const int64_t slots = (int64_t)g->n * n_views;
+  const DSettings DS = device_settings(s);
+  if ((r = ensure(ctx, ctx->counters, 4 * sizeof(uint32_t))) != G4D_OK) return r;
+  uint32_t* cnt = P<uint32_t>(ctx->counters);  // [0] visible, [1] pairs, [2] overflow
+  G4D_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(uint32_t), st));
+  if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->ranges, sizeof(uint2) * ctx->n_tiles, 1.1)) != G4D_OK) return r;
+  if (ctx->count_evals &&
+      (r = ensure(ctx, ctx->px_evals, sizeof(uint32_t) * ctx->n_pixels, 1.1)) != G4D_OK)
+    return r;
+
+  int64_t n_vis = 0, n_pairs = 0;
+  int pb = 0;
+  if (slots > 0) {
+    if ((r = run_preprocess(ctx, g, n_views, s, st)) != G4D_OK) return r;
+    for (int b = 0; b < 2; ++b) {
+      if ((r = ensure(ctx, ctx->vk[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+      if ((r = ensure(ctx, ctx->vv[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+    }
+    if ((r = ensure(ctx, ctx->voff, sizeof(uint32_t) * (slots + 1), 1.1)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
+    compact_visible(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), slots, P<uint32_t>(ctx->vk[0]),
+                    P<uint32_t>(ctx->vv[0]), cnt + 0, ctx->scan_tmp.p, st);
+    uint32_t* vk[2] = {P<uint32_t>(ctx->vk[0]), P<uint32_t>(ctx->vk[1])};
+    uint32_t* vv[2] = {P<uint32_t>(ctx->vv[0]), P<uint32_t>(ctx->vv[1])};
+    const int vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
+    ctx->vis_buf = vb;
+    pair_offsets(P<uint32_t>(ctx->tiles), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->voff), cnt + 1,
+                 ctx->scan_tmp.p, st);
+    G4D_HIP(hipGetLastError());
+    G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    G4D_HIP(hipStreamSynchronize(st));
+    n_vis = ctx->h_counters[0];
+    n_pairs = ctx->h_counters[1];
+    if (n_pairs > 0) {
+      if (n_pairs > (int64_t)UINT32_MAX - 1)
+        return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^32-2", (long long)n_pairs);
+      for (int b = 0; b < 2; ++b) {
+        if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
+        if ((r = ensure(ctx, ctx->pv[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
+      }
+      ctx->pair_cap = (int64_t)(ctx->pk[0].cap / sizeof(uint32_t));
+      if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
+          G4D_OK)
+        return r;
+      keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, n_vis, cnt + 1,
+             ctx->pair_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->pk[0]),
+             P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+      uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
+      uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
+      pb = radix_sort(pk, pv, cnt + 1, n_pairs, bits_for(ctx->n_tiles), ctx->sort_tmp.p, st);
+      G4D_HIP(hipGetLastError());
+    }
+  }
+  ctx->pair_buf = pb;
+  if (n_pairs > 0) {
+    tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 1, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges), st);
+  } else {
+    G4D_HIP(hipMemsetAsync(ctx->ranges.p, 0, sizeof(uint2) * ctx->n_tiles, st));
+  }
+  RasterArgs a{};
+  a.rec = P<float>(ctx->rec);
+  a.pval = n_pairs > 0 ? P<uint32_t>(ctx->pv[pb]) : nullptr;
+  a.ranges = P<uint2>(ctx->ranges);
+  a.views = P<DView>(ctx->views);
+  a.tile_base = P<int32_t>(ctx->tile_base);
+  a.n_views = n_views;
+  a.n_tiles = (int)ctx->n_tiles;
+  a.S = DS;
+  a.out_rgb = out_rgb;
+  a.out_T = out_T;
+  a.px_T = P<float>(ctx->px_T);
+  a.px_last = P<int32_t>(ctx->px_last);
+  a.px_evals = ctx->count_evals ? P<uint32_t>(ctx->px_evals) : nullptr;
+  raster_forward(a, st);
+  G4D_HIP(hipGetLastError());
+
+  ctx->stats.n_slots = slots;
+  ctx->stats.n_visible = n_vis;
+  ctx->stats.n_pairs = n_pairs;
+  ctx->stats.n_tiles = ctx->n_tiles;
+  ctx->stats.n_pixels = ctx->n_pixels;
+  ctx->stats.pair_capacity = ctx->pair_cap;
+  SavedKey& k = ctx->key;
+  k.n = g->n;
+  k.sh_degree = g->sh_degree;
+  k.t_degree = g->t_degree;
+  k.n_views = n_views;
+  const void* p[6] = {g->mean4, g->scale4, g->rot_l, g->rot_r, g->opacity, g->sh};
+  for (int i = 0; i < 6; ++i) k.ptrs[i] = p[i];
+  k.views.assign(views, views + n_views);
+  k.s = *s;
+  ctx->saved = true;
+  return G4D_OK;
+}
+
+g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                               int32_t n_views, const g4d_settings* s, const float* dL_drgb,
+                               const g4d_grads* out, void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  if (!dL_drgb || !out) return fail(ctx, G4D_EINVAL, "null dL_drgb or grads");
+  if (!ctx->saved || !same_key(ctx->key, g, views, n_views, s))
+    return fail(ctx, G4D_ESTATE, "backward without a matching forward on this context");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  const int64_t slots = (int64_t)g->n * n_views;
+  if (slots == 0) return G4D_OK;
+  const DSettings DS = device_settings(s);
+  if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
+  G4D_HIP(hipMemsetAsync(ctx->grad2d.p, 0, sizeof(float) * kGrad2d * slots, st));
+  if (ctx->stats.n_pairs > 0) {
+    RasterArgs a{};
+    a.rec = P<float>(ctx->rec);
+    a.pval = P<uint32_t>(ctx->pv[ctx->pair_buf]);
+    a.ranges = P<uint2>(ctx->ranges);
+    a.views = P<DView>(ctx->views);
+    a.tile_base = P<int32_t>(ctx->tile_base);
+    a.n_views = n_views;
+    a.n_tiles = (int)ctx->n_tiles;
+    a.S = DS;
+    a.px_T = P<float>(ctx->px_T);
+    a.px_last = P<int32_t>(ctx->px_last);
+    a.dL = dL_drgb;
+    a.grad2d = P<float>(ctx->grad2d);
+    raster_backward(a, st);
+    G4D_HIP(hipGetLastError());
+  }
+  GradPtrs gp{out->mean4, out->scale4, out->rot_l, out->rot_r, out->opacity, out->sh};
+  preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
+                      P<float>(ctx->grad2d), gp, st);
+  G4D_HIP(hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status g4d_sync_status(g4d_ctx* ctx, void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  G4D_HIP(hipSetDevice(ctx->device));
+  G4D_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  if (ctx->counters.p) {
+    uint32_t flag = 0;
+    G4D_HIP(hipMemcpy(&flag, P<uint32_t>(ctx->counters) + 2, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)ctx->pair_cap);
+  }
+  return G4D_OK;
+}
+
+g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, void* stream) {
+  if (!ctx || !out) return G4D_EINVAL;
+  G4D_HIP(hipSetDevice(ctx->device));
+  G4D_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  *out = ctx->stats;
+  return G4D_OK;
+}
+
+// Per-pixel evaluation counters (Gaussian-pixel pairs within the cutoff visited before the
+// stop) of later forwards: enable = 1 turns them on, 0 off.  `out` (device, may be NULL)
+// receives the counters of the last forward, pixels of all views concatenated.
+g4d_status g4d_eval_counters(g4d_ctx* ctx, int enable, uint32_t* out, void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  G4D_HIP(hipSetDevice(ctx->device));
+  if (out) {
+    if (!ctx->count_evals || !ctx->px_evals.p || !ctx->saved)
+      return fail(ctx, G4D_ESTATE, "no counted forward on this context");
+    G4D_HIP(hipMemcpyAsync(out, ctx->px_evals.p, sizeof(uint32_t) * ctx->n_pixels,
+                           hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  }
+  ctx->count_evals = enable != 0;
+  return G4D_OK;
+}
+
+}  // extern "C"

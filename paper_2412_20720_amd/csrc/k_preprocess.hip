@@ -1,0 +1,181 @@
+// Per-(Gaussian, view) slice, splat and color (forward), and their adjoint (backward).
+//
+// One thread per Gaussian loops over all views of the batch: the rotors, the 4D covariance
+// factor M = R S and the 4DSH coefficients are read and built once per batch and reused for
+// every view (Sec. 3.2: the covariance and color parameters are view-independent; only the
+// slice time t and the camera change).  Records are written view-major (slot = view * N + g)
+// so that a wave's 64 consecutive Gaussians store 64 consecutive records.
+#include <hip/hip_runtime.h>
+
+#include "g4d_internal.h"
+
+namespace g4d {
+namespace {
+
+template <int DS, int DT>
+__global__ __launch_bounds__(256) void k_preprocess(
+    int n, int n_views, const float4* __restrict__ mean4, const float4* __restrict__ scale4,
+    const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
+    const float* __restrict__ opacity, const float* __restrict__ sh,
+    const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
+    uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey) {
+  constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  Geom g;
+  geom_forward(rot_l[gi], rot_r[gi], scale4[gi], g);
+  const float4 mean = mean4[gi];
+  const float op = opacity[gi];
+  float shc[NSH];
+  const float* shp = sh + (size_t)gi * NSH;
+#pragma unroll
+  for (int k = 0; k < NSH; ++k) shc[k] = shp[k];
+  for (int v = 0; v < n_views; ++v) {
+    const DView& V = views[v];
+    const size_t slot = (size_t)v * n + gi;
+    ViewFwd f;
+    uint32_t cnt = 0;
+    if (view_forward(g, mean, V, S, f)) {
+      color_forward<DS, DT>(shc, S, f);
+      float ex, ey;
+      cutoff_extent(f, S, ex, ey);
+      int x0, x1, y0, y1;
+      if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1)) {
+        cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        float4* r = reinterpret_cast<float4*>(rec + slot * kRec);
+        r[0] = make_float4(f.u, f.v, f.conic[0], f.conic[1]);
+        r[1] = make_float4(f.conic[2], op * f.pt, f.color[0], f.color[1]);
+        r[2] = make_float4(f.color[2], ex, ey, f.x[2]);
+        dkey[slot] = __float_as_uint(f.x[2]);
+      }
+    }
+    tiles[slot] = cnt;
+  }
+}
+
+template <int DS, int DT>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(
+    int n, int n_views, const float4* __restrict__ mean4, const float4* __restrict__ scale4,
+    const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
+    const float* __restrict__ opacity, const float* __restrict__ sh,
+    const DView* __restrict__ views, DSettings S, const uint32_t* __restrict__ tiles,
+    const float* __restrict__ grad2d, GradPtrs out) {
+  constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  const float4 sc = scale4[gi];
+  Geom g;
+  geom_forward(rot_l[gi], rot_r[gi], sc, g);
+  const float4 mean = mean4[gi];
+  const float op = opacity[gi];
+  float shc[NSH], gsh[NSH];
+  const float* shp = sh + (size_t)gi * NSH;
+#pragma unroll
+  for (int k = 0; k < NSH; ++k) {
+    shc[k] = shp[k];
+    gsh[k] = 0.f;
+  }
+  float gM[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gM[i][j] = 0.f;
+  float gmean[4] = {0.f, 0.f, 0.f, 0.f};
+  float gop = 0.f;
+  for (int v = 0; v < n_views; ++v) {
+    const size_t slot = (size_t)v * n + gi;
+    if (tiles[slot] == 0u) continue;
+    const float4* gp = reinterpret_cast<const float4*>(grad2d + slot * kGrad2d);
+    const float4 q0 = gp[0], q1 = gp[1], q2 = gp[2];
+    const float q[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
+    const DView& V = views[v];
+    ViewFwd f;
+    view_forward<false>(g, mean, V, S, f);
+    color_forward<DS, DT>(shc, S, f);
+    view_backward<DS, DT>(g, mean, op, shc, V, S, f, q, gM, gmean, gop, gsh);
+  }
+  float gs[4], gql[4], gqr[4];
+  geom_backward(g, sc, gM, gs, gql, gqr);
+  if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = make_float4(gmean[0], gmean[1], gmean[2], gmean[3]);
+  if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = make_float4(gs[0], gs[1], gs[2], gs[3]);
+  if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = make_float4(gql[0], gql[1], gql[2], gql[3]);
+  if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = make_float4(gqr[0], gqr[1], gqr[2], gqr[3]);
+  if (out.opacity) out.opacity[gi] = gop;
+  if (out.sh) {
+    float* o = out.sh + (size_t)gi * NSH;
+#pragma unroll
+    for (int k = 0; k < NSH; ++k) o[k] = gsh[k];
+  }
+}
+
+template <int DS, int DT>
+void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S, float* rec,
+                uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+  const int blocks = (gp.n + 255) / 256;
+  hipLaunchKernelGGL((k_preprocess<DS, DT>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
+                     reinterpret_cast<const float4*>(gp.mean4),
+                     reinterpret_cast<const float4*>(gp.scale4),
+                     reinterpret_cast<const float4*>(gp.rot_l),
+                     reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S, rec,
+                     tiles, dkey);
+}
+
+template <int DS, int DT>
+void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
+                const uint32_t* tiles, const float* grad2d, const GradPtrs& out, hipStream_t st) {
+  const int blocks = (gp.n + 255) / 256;
+  hipLaunchKernelGGL((k_preprocess_bwd<DS, DT>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
+                     reinterpret_cast<const float4*>(gp.mean4),
+                     reinterpret_cast<const float4*>(gp.scale4),
+                     reinterpret_cast<const float4*>(gp.rot_l),
+                     reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
+                     tiles, grad2d, out);
+}
+
+template <int DS>
+void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S, float* rec,
+                    uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+  switch (gp.t_degree) {
+    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, dkey, st); break;
+    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, dkey, st); break;
+    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, dkey, st); break;
+  }
+}
+
+template <int DS>
+void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S,
+                    const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                    hipStream_t st) {
+  switch (gp.t_degree) {
+    case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, grad2d, out, st); break;
+    case 1: launch_bwd<DS, 1>(gp, views, nv, S, tiles, grad2d, out, st); break;
+    default: launch_bwd<DS, 2>(gp, views, nv, S, tiles, grad2d, out, st); break;
+  }
+}
+
+}  // namespace
+
+void preprocess_forward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
+                        float* rec, uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+  if (gp.n == 0) return;
+  switch (gp.sh_degree) {
+    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+  }
+}
+
+void preprocess_backward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
+                         const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                         hipStream_t st) {
+  if (gp.n == 0) return;
+  switch (gp.sh_degree) {
+    case 0: dispatch_bwd_t<0>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    case 1: dispatch_bwd_t<1>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    case 2: dispatch_bwd_t<2>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    default: dispatch_bwd_t<3>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+  }
+}
+
+}  // namespace g4d

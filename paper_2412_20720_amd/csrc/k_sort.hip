@@ -1,0 +1,445 @@
+// Binning kernels: stream compaction of visible (view, Gaussian) slots, device-wide scans,
+// key generation, an LDS-staged wavefront LSD radix sort and tile-range detection.
+//
+// Binning follows the tile-based rasterizer the paper adopts (Sec. 3.2): every splat is
+// listed in each screen tile its cutoff box touches, and each tile's list is ordered by
+// camera depth (Sec. 3.1, "sorted according to their depth").  Here the depth order is made
+// once per visible splat (a 32-bit depth sort of the compacted slots); the (tile, splat)
+// pairs are then emitted in depth order and stably sorted by tile id alone, so each tile's
+// list inherits the depth order (ties keep the slot order, i.e. the Gaussian index).
+#include <hip/hip_runtime.h>
+
+#include "g4d_internal.h"
+
+namespace g4d {
+namespace {
+
+constexpr int kThreads = kSortThreads;          // 4 waves of 64
+constexpr int kItems = kScanItems;              // 16 items per thread
+constexpr int kPerThread = kItems / kThreads;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block; also returns the total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, uint32_t* lds4) {
+  const uint32_t inc = wave_incl_scan(x);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) lds4[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t s = lds4[k];
+    pre += (k < w) ? s : 0u;
+    total += s;
+  }
+  __syncthreads();
+  return pre + inc - x;
+}
+
+// ------------------------------------------------------------------------------------------
+// Generic three-phase exclusive scan: per-block sums, a one-block scan of the sums, and a
+// per-block scan that hands (index, exclusive prefix, value) to an output functor.
+// ------------------------------------------------------------------------------------------
+struct InFlag {
+  const uint32_t* p;
+  __device__ uint32_t operator()(int64_t i) const { return p[i] > 0u ? 1u : 0u; }
+};
+struct InGather {
+  const uint32_t* cnt;
+  const uint32_t* idx;
+  __device__ uint32_t operator()(int64_t i) const { return cnt[idx[i]]; }
+};
+struct InPlain {
+  const uint32_t* p;
+  __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct OutStore {
+  uint32_t* out;
+  __device__ void operator()(int64_t i, uint32_t excl, uint32_t) const { out[i] = excl; }
+};
+struct OutCompact {
+  const uint32_t* dkey;
+  uint32_t* okey;
+  uint32_t* oval;
+  __device__ void operator()(int64_t i, uint32_t excl, uint32_t v) const {
+    if (v) {
+      okey[excl] = dkey[i];
+      oval[excl] = (uint32_t)i;
+    }
+  }
+};
+
+__device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_host) {
+  return n_dev ? (int64_t)*n_dev : n_host;
+}
+
+template <class In>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(In in, const uint32_t* n_dev,
+                                                          int64_t n_host, uint32_t* sums) {
+  __shared__ uint32_t lds[4];
+  const int64_t n = count_of(n_dev, n_host);
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  uint32_t acc = 0;
+  if (base < n) {
+#pragma unroll 4
+    for (int r = 0; r < kPerThread; ++r) {
+      const int64_t i = base + r * kThreads + threadIdx.x;
+      if (i < n) acc += in(i);
+    }
+  }
+  uint32_t total;
+  block_excl_scan(acc, total, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of `count` sums in place; writes the grand total.
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* sums, int count, uint32_t* total) {
+  __shared__ uint32_t lds[16];
+  uint32_t carry = 0;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int base = 0; base < count; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t x = (i < count) ? sums[i] : 0u;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      pre += (k < w) ? lds[k] : 0u;
+      tot += lds[k];
+    }
+    if (i < count) sums[i] = carry + pre + inc - x;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class In, class Out>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(In in, Out out, const uint32_t* n_dev,
+                                                         int64_t n_host, const uint32_t* sums) {
+  __shared__ uint32_t lds[4];
+  const int64_t n = count_of(n_dev, n_host);
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  if (base >= n) return;
+  uint32_t carry = sums[blockIdx.x];
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    const uint32_t v = (i < n) ? in(i) : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(v, total, lds);
+    if (i < n) out(i, carry + ex, v);
+    carry += total;
+    if (base + (r + 1) * kThreads >= n) break;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v);
+
+template <class In, class Out>
+void scan_generic(In in, Out out, const uint32_t* n_dev, int64_t n_cap, uint32_t* total,
+                  void* scratch, hipStream_t st) {
+  const int64_t blocks = (n_cap + kItems - 1) / kItems;
+  if (blocks == 0) {
+    if (total) fill_u32(total, 1, 0u, st);
+    return;
+  }
+  uint32_t* sums = static_cast<uint32_t*>(scratch);
+  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((unsigned)blocks), dim3(kThreads), 0, st, in, n_dev,
+                     n_cap, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, (int)blocks, total);
+  hipLaunchKernelGGL((k_scan_apply<In, Out>), dim3((unsigned)blocks), dim3(kThreads), 0, st, in,
+                     out, n_dev, n_cap, sums);
+}
+
+// ------------------------------------------------------------------------------------------
+// Radix sort pass: digit histogram per block, scan of the (digit, block) table, and a
+// stable scatter.  Each wave owns a contiguous 1024-item run of its block; ranks inside a
+// wave come from ballot-based digit matching, so equal digits keep their input order.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ key,
+                                                         const uint32_t* n_dev, int shift,
+                                                         uint32_t mask, uint32_t* hist,
+                                                         int nblocks) {
+  __shared__ uint32_t wh[4][kRadix];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < 4 * kRadix; d += kThreads) (&wh[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t n = *n_dev;
+  const int64_t base = (int64_t)blockIdx.x * kItems + w * (kItems / 4);
+#pragma unroll 4
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    if (i < n) atomicAdd(&wh[w][(key[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kThreads)
+    hist[(int64_t)d * nblocks + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+}
+
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
+  uint64_t peers = valid;
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* n_dev, int shift, uint32_t mask,
+    const uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t wcount[4][kRadix];
+  __shared__ uint32_t bstart[kRadix];
+  __shared__ uint32_t goff[kRadix];
+  __shared__ uint32_t sk[kItems];
+  __shared__ uint32_t sv[kItems];
+  __shared__ uint32_t lds4[4];
+  const int64_t n = *n_dev;
+  const int64_t bbase = (int64_t)blockIdx.x * kItems;
+  if (bbase >= n) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < 4 * kRadix; d += kThreads) (&wcount[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t base = bbase + w * (kItems / 4);
+  const uint64_t lt = lanemask_lt();
+  uint32_t k[kPerThread], v[kPerThread], rank[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    const bool valid = i < n;
+    k[r] = valid ? kin[i] : 0u;
+    v[r] = valid ? vin[i] : 0u;
+    const uint32_t d = (k[r] >> shift) & mask;
+    const uint64_t peers = match_digit(d, __ballot(valid));
+    const uint32_t before = wcount[w][d];
+    rank[r] = before + (uint32_t)__popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lt) == 0ull) wcount[w][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // Per-digit totals, exclusive prefix over waves (in place) and over digits (bstart).
+  {
+    const int d = threadIdx.x;  // kThreads == kRadix
+    uint32_t c0 = wcount[0][d], c1 = wcount[1][d], c2 = wcount[2][d], c3 = wcount[3][d];
+    wcount[0][d] = 0;
+    wcount[1][d] = c0;
+    wcount[2][d] = c0 + c1;
+    wcount[3][d] = c0 + c1 + c2;
+    uint32_t tot;
+    bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, tot, lds4);
+    goff[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (k[r] >> shift) & mask;
+      const uint32_t pos = bstart[d] + wcount[w][d] + rank[r];
+      sk[pos] = k[r];
+      sv[pos] = v[r];
+    }
+  }
+  __syncthreads();
+  const int cnt = (int)((n - bbase) < kItems ? (n - bbase) : kItems);
+  for (int p = threadIdx.x; p < cnt; p += kThreads) {
+    const uint32_t kk = sk[p];
+    const uint32_t d = (kk >> shift) & mask;
+    const uint32_t dst = goff[d] + ((uint32_t)p - bstart[d]);
+    kout[dst] = kk;
+    vout[dst] = sv[p];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Key generation: each wave takes 64 consecutive visible splats (in depth order) and writes
+// their (tile, slot) pairs cooperatively, one pair per lane per step, so that a splat that
+// covers thousands of tiles does not serialize one thread.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_keygen(
+    const float* __restrict__ rec, const uint32_t* __restrict__ vval,
+    const uint32_t* __restrict__ voff, const uint32_t* n_vis_dev, const uint32_t* n_pairs_dev,
+    int64_t pair_cap, int n_per_view, const DView* __restrict__ views, DSettings S,
+    uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* overflow) {
+  __shared__ uint32_t s_start[4][65];
+  __shared__ int32_t s_x0[4][64], s_y0[4][64], s_w[4][64], s_tx[4][64], s_tb[4][64];
+  __shared__ uint32_t s_slot[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n_vis = *n_vis_dev;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + w) * 64;
+  if (first >= n_vis) return;
+  const int64_t r = first + lane;
+  const bool valid = r < n_vis;
+  const int64_t last = (n_vis - first < 64 ? n_vis : first + 64) - 1;
+  const uint32_t off0 = voff[first];
+  const uint32_t off_end = (last + 1 < n_vis) ? voff[last + 1] : *n_pairs_dev;
+  const uint32_t total = off_end - off0;
+  if (valid) {
+    const uint32_t slot = vval[r];
+    const int v = (int)(slot / (uint32_t)n_per_view);
+    const DView& V = views[v];
+    const float* p = rec + (size_t)slot * kRec;
+    int x0, x1, y0, y1;
+    tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], V, S.tile_shift, x0, x1, y0, y1);
+    s_start[w][lane] = voff[r] - off0;
+    s_x0[w][lane] = x0;
+    s_y0[w][lane] = y0;
+    s_w[w][lane] = x1 - x0 + 1;
+    s_tx[w][lane] = V.tiles_x;
+    s_tb[w][lane] = V.tile_base;
+    s_slot[w][lane] = slot;
+  } else {
+    s_start[w][lane] = total;
+  }
+  if (lane == 0) s_start[w][64] = total;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint32_t k = lane; k < total; k += 64) {
+    // largest j with s_start[j] <= k
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_start[w][mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t rel = k - s_start[w][lo];
+    const int ww = s_w[w][lo];
+    const int ty = s_y0[w][lo] + (int)(rel / (uint32_t)ww);
+    const int tx = s_x0[w][lo] + (int)(rel % (uint32_t)ww);
+    const int64_t dst = (int64_t)off0 + k;
+    if (dst < pair_cap) {
+      pkey[dst] = (uint32_t)(s_tb[w][lo] + ty * s_tx[w][lo] + tx);
+      pval[dst] = s_slot[w][lo];
+    } else {
+      *overflow = 1u;
+    }
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev, int64_t cap,
+                         uint2* ranges) {
+  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = key[i];
+  if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
+  if (i == n - 1 || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_view_setup(DView* views, int n_views, float m) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_views) return;
+  DView& V = views[v];
+  for (int j = 0; j < 3; ++j)
+    V.C[j] = -(V.W[j] * V.tau[0] + V.W[3 + j] * V.tau[1] + V.W[6 + j] * V.tau[2]);
+  V.xlo = (-m * (float)V.width - V.cx) / V.fx;
+  V.xhi = ((1.f + m) * (float)V.width - V.cx) / V.fx;
+  V.ylo = (-m * (float)V.height - V.cy) / V.fy;
+  V.yhi = ((1.f + m) * (float)V.height - V.cy) / V.fy;
+}
+
+}  // namespace
+
+// Plain fill kernel (used instead of memset nodes so that the sequence can be graph-captured).
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+size_t scan_scratch_bytes(int64_t n) {
+  return sizeof(uint32_t) * (size_t)((n + kItems - 1) / kItems + 1);
+}
+
+void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
+                     uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
+                     hipStream_t st) {
+  scan_generic(InFlag{tiles}, OutCompact{dkey, out_key, out_val}, nullptr, n_slots, n_out, scratch,
+               st);
+}
+
+void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_dev,
+                  int64_t n_cap, uint32_t* offsets, uint32_t* total, void* scratch,
+                  hipStream_t st) {
+  scan_generic(InGather{tiles, val}, OutStore{offsets}, n_dev, n_cap, total, scratch, st);
+}
+
+size_t radix_scratch_bytes(int64_t n_cap) {
+  const int64_t blocks = (n_cap + kItems - 1) / kItems;
+  const int64_t table = blocks * kRadix;
+  return sizeof(uint32_t) * (size_t)(table + 16) + scan_scratch_bytes(table);
+}
+
+int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+               void* scratch, hipStream_t st) {
+  const int64_t blocks = (n_cap + kItems - 1) / kItems;
+  if (blocks == 0 || bits <= 0) return 0;
+  uint32_t* hist = static_cast<uint32_t*>(scratch);
+  void* scan_tmp = hist + blocks * kRadix + 16;
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const int nb = (bits - shift) < kRadixBits ? (bits - shift) : kRadixBits;
+    const uint32_t mask = (1u << nb) - 1u;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur], n_dev,
+                       shift, mask, hist, (int)blocks);
+    scan_generic(InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr, scan_tmp, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur],
+                       val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
+                       (int)blocks);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
+            const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval, uint32_t* overflow,
+            hipStream_t st) {
+  const int64_t waves = (n_vis_cap + 63) / 64;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_keygen, dim3((unsigned)blocks), dim3(kThreads), 0, st, rec, vval, voff, n_vis,
+                     n_pairs, pair_cap, n_slots_per_view, views, S, pkey, pval, overflow);
+}
+
+void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
+                 uint2* ranges, hipStream_t st) {
+  fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
+  const int64_t blocks = (pair_cap + 255) / 256;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs, pair_cap,
+                     ranges);
+}
+
+void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st) {
+  hipLaunchKernelGGL(k_view_setup, dim3((n_views + 63) / 64), dim3(64), 0, st, views, n_views,
+                     jac_margin);
+}
+
+}  // namespace g4d

@@ -1,0 +1,84 @@
+"""Helpers of the GPU tests: run the HIP library on a scene and bring results back as numpy."""
+from __future__ import annotations
+
+import sys
+from typing import Dict, List, Optional
+
+import numpy as np
+
+PARAMS = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def device_params(scene, dev):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in scene.arrays().items()}
+
+
+def settings_for(scene, **kw):
+    from paper_2412_20720_amd import _binding as B
+    kw.setdefault("time_period", scene.time_period)
+    return B.default_settings(**kw)
+
+
+class GpuRun:
+    """Forward (and optionally backward) of a scene's views in one batched call."""
+
+    def __init__(self, renderer, scene, views=None, settings=None, **kw):
+        import torch
+        from paper_2412_20720_amd.frontend import Renderer
+        self.r = renderer
+        self.scene = scene
+        self.views = list(views if views is not None else scene.views)
+        self.settings = settings if settings is not None else settings_for(scene, **kw)
+        self.dev = renderer.device
+        self.p = device_params(scene, self.dev)
+        self.g = renderer.gaussians(*[self.p[k] for k in PARAMS], scene.sh_degree, scene.t_degree)
+        npix = Renderer.pixel_count(self.views)
+        self.rgb = torch.empty(3 * npix, device=self.dev)
+        self.T = torch.empty(npix, device=self.dev)
+
+    def forward(self):
+        import torch
+        self.r.forward(self.g, self.views, self.settings, self.rgb, self.T)
+        self.r.sync()
+        torch.cuda.synchronize()
+        return self
+
+    def images(self) -> List[np.ndarray]:
+        out, off = [], 0
+        rgb = self.rgb.cpu().numpy()
+        for v in self.views:
+            h, w = int(v["height"]), int(v["width"])
+            out.append(rgb[off:off + 3 * h * w].reshape(3, h, w))
+            off += 3 * h * w
+        return out
+
+    def transmittance(self) -> List[np.ndarray]:
+        out, off = [], 0
+        T = self.T.cpu().numpy()
+        for v in self.views:
+            h, w = int(v["height"]), int(v["width"])
+            out.append(T[off:off + h * w].reshape(h, w))
+            off += h * w
+        return out
+
+    def backward(self, dl_list: List[np.ndarray]) -> Dict[str, np.ndarray]:
+        import torch
+        dL = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dl_list]).astype(np.float32)).to(self.dev)
+        grads = {k: torch.empty_like(self.p[k]) for k in PARAMS}
+        self.r.backward(self.g, self.views, self.settings, dL, grads)
+        self.r.sync()
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in grads.items()}
+
+
+def oracle_frame(scene, view, **settings):
+    import oracle
+    st = dict(time_period=scene.time_period)
+    st.update(settings)
+    return oracle.Frame(scene.arrays(), scene.sh_degree, scene.t_degree, view, st)
