@@ -1,0 +1,185 @@
+"""Benchmark: batched forward + backward of the differentiable 4D Gaussian render on one GPU.
+
+A step is one pass of the whole hot path over one batch of views: preprocess (slice, splat,
+4DSH color) of every (Gaussian, view), visible compaction, depth sort, key generation, tile
+sort, tile ranges, forward raster, backward raster and preprocess backward, with a fixed
+synthetic upstream gradient dL/dimage.  The default workload is 300k Gaussians rendered in
+16 views (8 ring cameras x 2 times, 1352x1014 and 800x800).  Inputs are resident in HBM
+before timing starts.  One JSON line is printed (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpix/s at 300k 4D Gaussians, 1352x1014; batched vs per-view launch"
+PEAK_FP32_VALU = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
+PEAK_HBM = 8.0e12           # MI355X HBM3E (B/s)
+# Algorithmic FP32 work per (Gaussian, pixel) pair, counted from the per-pair arithmetic:
+# forward 21 flops per evaluated pair (distance, exp, alpha, transmittance, color);
+# backward 62 flops per composited pair (transmittance rebuild, dL/dalpha, color behind,
+# the nine screen-space partials and their reduction).
+FWD_FLOPS_PER_PAIR = 21
+BWD_FLOPS_PER_PAIR = 62
+WORKLOAD_KEYS = {"0": 0, "1": 1, "2": 2, "2b": "2b", "3": 3, "4": 4}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="2", choices=sorted(WORKLOAD_KEYS))
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2412_20720_amd import _binding as B
+    from paper_2412_20720_amd import scenes
+    from paper_2412_20720_amd.frontend import Renderer
+
+    dev = torch.device("cuda", 0)
+    sc = scenes.make_workload(WORKLOAD_KEYS[args.workload])
+    log(f"bench: workload {sc.name}: N={sc.n}, {len(sc.views)} views, {sc.pixels / 1e6:.2f} Mpix")
+    r = Renderer(0)
+    p = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in sc.arrays().items()}
+    names = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
+    g = r.gaussians(*[p[k] for k in names], sc.sh_degree, sc.t_degree)
+    settings = B.default_settings(time_period=sc.time_period, tile_size=args.tile)
+    views = B.make_views(sc.views)
+    npix = sc.pixels
+    rgb = torch.empty(3 * npix, device=dev)
+    T = torch.empty(npix, device=dev)
+    dL = torch.from_numpy(np.concatenate([d.reshape(-1) for d in scenes.make_dl_dimage(sc)])).to(dev)
+    grads = {k: torch.empty_like(p[k]) for k in names}
+
+    def step():
+        r.forward(g, views, settings, rgb, T)
+        r.backward(g, views, settings, dL, grads)
+
+    # Work counts of this workload (untimed, counted by the forward kernel itself).
+    r.eval_counters(True)
+    r.forward(g, views, settings, rgb, T)
+    cnt = r.eval_counters(False, npix).cpu().numpy().astype(np.int64)
+    stats = r.stats()
+    evals = int((cnt & 0xFFFF).sum())
+    contrib = int((cnt >> 16).sum())
+    log(f"bench: visible {stats['n_visible']}, pairs {stats['n_pairs']}, evaluated pairs {evals}, "
+        f"composited pairs {contrib}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    r.profile(True, collect=True, reset=True)   # start stage timing from zero
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stages = r.profile(False, collect=True, reset=True)
+    r.sync()
+    value = npix / dt / 1e6
+    log(f"bench: batched {dt * 1e3:.3f} ms/step, {value:.1f} Mpix/s")
+    stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
+    for k, v in stage_ms.items():
+        log(f"  {k:15s} {v:8.3f} ms/launch")
+
+    per_view = None
+    if not args.no_per_view:
+        single = [B.make_views([v]) for v in sc.views]
+        offs = np.cumsum([0] + [v["width"] * v["height"] for v in sc.views])
+
+        def step_pv():
+            for k, va in enumerate(single):
+                a, b = int(offs[k]), int(offs[k + 1])
+                r.forward(g, va, settings, rgb[3 * a:3 * b], T[a:b])
+                r.backward(g, va, settings, dL[3 * a:3 * b], grads)
+
+        for _ in range(args.warmup):
+            step_pv()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_pv()
+        torch.cuda.synchronize()
+        dpv = (time.perf_counter() - t0) / args.steps
+        per_view = dict(value=npix / dpv / 1e6, ms_per_step=dpv * 1e3,
+                        batched_speedup=dpv / dt)
+        log(f"bench: per-view {dpv * 1e3:.3f} ms/step, {npix / dpv / 1e6:.1f} Mpix/s")
+
+    # Roofline of the dominant kernel (largest time per step), from the live HIP events.
+    dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
+    flops = (BWD_FLOPS_PER_PAIR * contrib) if dom == "raster_bwd" else (FWD_FLOPS_PER_PAIR * evals)
+    achieved = flops / (stage_ms[dom] * 1e-3)
+    roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=None,
+                    units=contrib if dom == "raster_bwd" else evals,
+                    flops_per_unit=BWD_FLOPS_PER_PAIR if dom == "raster_bwd" else FWD_FLOPS_PER_PAIR,
+                    ms_per_launch=stage_ms[dom])
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc, args.cpu_views)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": sc.name, "gaussians": sc.n, "views": len(sc.views),
+                   "pixels": npix, "sh_degree": sc.sh_degree, "t_degree": sc.t_degree,
+                   "tile": args.tile},
+        "per_view": per_view,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
+                 "evaluated_pairs": evals, "composited_pairs": contrib},
+        "stages_ms": stage_ms,
+    }
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
+def cpu_baseline(sc, n_views):
+    """The FP64 oracle, as it stands, on a bounded sample: forward + backward of the first
+    n_views views of the workload, on all host threads."""
+    import oracle
+    from paper_2412_20720_amd import scenes
+    dls = scenes.make_dl_dimage(sc)
+    t0 = time.perf_counter()
+    px = 0
+    for k in range(n_views):
+        v = sc.views[k]
+        with oracle.Frame(sc.arrays(), sc.sh_degree, sc.t_degree, v,
+                          dict(time_period=sc.time_period)) as fr:
+            fr.render()
+            fr.backward(dls[k])
+        px += v["width"] * v["height"]
+    dt = time.perf_counter() - t0
+    log(f"bench: oracle {px / 1e6:.2f} Mpix fwd+bwd in {dt:.1f} s on {oracle.num_threads()} threads")
+    return dict(value=px / dt / 1e6, unit="Mpix/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"forward+backward of the first {n_views} view(s) of {sc.name} "
+                       f"({px} pixels), FP64, OpenMP", seconds=dt)
+
+
+if __name__ == "__main__":
+    main()

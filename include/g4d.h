@@ -92,7 +92,8 @@ typedef struct {
  *   color_offset 0.5, color_min 0   c = max(color_min, color_offset + 4DSH sum)
  *   time_period 1     the period T of the Fourier basis of the 4DSH
  *   tile_size 16      screen tile side in pixels (8, 16 or 32)
- *   lds_batch 0       records staged per wave (0 = library choice) */
+ *   lds_batch 0       list entries a wave stages in LDS at a time: 32, 64 or 128
+ *                     (0 = library default, 64) */
 typedef struct {
   float near_z, marginal_min, cutoff_sigma, blur, jacobian_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
@@ -158,13 +159,27 @@ g4d_status g4d_sync_status(g4d_ctx *ctx, void *stream);
 /* Counters of the last forward; synchronizes `stream`. */
 g4d_status g4d_get_stats(g4d_ctx *ctx, g4d_stats *out, void *stream);
 
-/* Per-pixel evaluation counters: the number of (Gaussian, pixel) pairs whose Mahalanobis
- * distance passes the cutoff and that the pixel visits before its transmittance stop (the
- * algorithmic work of eq:4dblending).  enable = 1 makes later forwards count them (a small
- * extra store per pixel), 0 stops counting.  If `out` (device, [total pixels] uint32, views
- * concatenated) is not NULL, the counters of the last counted forward are copied there
- * (G4D_ESTATE if there is none). */
+/* Per-pixel work counters of eq:4dblending: bits 0-15 hold the number of (Gaussian, pixel)
+ * pairs whose Mahalanobis distance passes the cutoff and that the pixel visits before its
+ * transmittance stop, bits 16-31 the number of those that were composited (both saturate at
+ * 65535).  enable = 1 makes later forwards count them (one extra store per pixel), 0 stops.
+ * If `out` (device, [total pixels] uint32, views concatenated) is not NULL, the counters of
+ * the last counted forward are copied there (G4D_ESTATE if there is none). */
 g4d_status g4d_eval_counters(g4d_ctx *ctx, int enable, uint32_t *out, void *stream);
+
+/* Pipeline stages timed by g4d_profile (index: name). */
+#define G4D_NUM_STAGES 11
+/* Stage timing with HIP events recorded on the call's stream around each kernel group:
+ *   0 preprocess, 1 compact, 2 depth_sort, 3 pair_offsets, 4 keygen, 5 tile_sort,
+ *   6 tile_ranges, 7 raster_fwd, 8 clear_grad, 9 raster_bwd, 10 preprocess_bwd.
+ * enable = 1 starts recording for later calls, 0 stops.  If ms / launches are not NULL
+ * (host arrays of G4D_NUM_STAGES), the context's device is synchronized, every recorded
+ * interval is added in and the totals since the last reset are returned; reset = 1 then
+ * clears the totals. */
+g4d_status g4d_profile(g4d_ctx *ctx, int enable, double *ms, int64_t *launches, int reset);
+
+/* Name of a stage index of g4d_profile ("" if out of range). */
+const char *g4d_stage_name(int stage);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "G4D_OK", -1: "G4D_EINVAL", -2: "G4D_ENOMEM", -3: "G4D_ECAPAC
 
 EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error",
             "g4d_preprocess", "g4d_render_forward", "g4d_render_backward", "g4d_sync_status",
-            "g4d_get_stats", "g4d_eval_counters"]
+            "g4d_get_stats", "g4d_eval_counters", "g4d_profile", "g4d_stage_name"]
+G4D_NUM_STAGES = 11
 
 
 class g4d_gaussians(C.Structure):
@@ -78,8 +79,11 @@ def lib() -> C.CDLL:
     L.g4d_sync_status.argtypes = [vp, vp]
     L.g4d_get_stats.argtypes = [vp, C.POINTER(g4d_stats), vp]
     L.g4d_eval_counters.argtypes = [vp, C.c_int, vp, vp]
+    L.g4d_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    L.g4d_stage_name.argtypes = [C.c_int]
+    L.g4d_stage_name.restype = C.c_char_p
     for name in EXPORTED:
-        if name != "g4d_last_error":
+        if name not in ("g4d_last_error", "g4d_stage_name"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

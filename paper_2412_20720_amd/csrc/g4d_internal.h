@@ -69,6 +69,7 @@ struct RasterArgs {
   const int32_t* tile_base;  // n_views + 1 prefix of tiles per view
   int n_views;
   int n_tiles;
+  int blocks_per_xcd;        // set by the launcher
   DSettings S;
   float* out_rgb;
   float* out_T;

@@ -53,6 +53,13 @@ struct g4d_ctx {
   int64_t n_tiles = 0, n_pixels = 0;
   g4d_stats stats{};
   bool count_evals = false;
+  // stage profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_free;
+  struct Interval { int stage; hipEvent_t a, b; };
+  std::vector<Interval> pending;
+  double stage_ms[G4D_NUM_STAGES] = {};
+  int64_t stage_n[G4D_NUM_STAGES] = {};
 };
 
 namespace {
@@ -92,6 +99,45 @@ g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
   b.cap = want;
   return G4D_OK;
 }
+
+const char* const kStageNames[G4D_NUM_STAGES] = {
+    "preprocess", "compact", "depth_sort", "pair_offsets", "keygen", "tile_sort",
+    "tile_ranges", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
+
+hipEvent_t take_event(g4d_ctx* c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Records a HIP event pair around one kernel group on the call's stream when profiling.
+struct Stage {
+  g4d_ctx* c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Stage(g4d_ctx* c_, int s_, hipStream_t st_) : c(c_), stage(s_), st(st_) {
+    if (c->profiling && (a = take_event(c))) (void)hipEventRecord(a, st);
+  }
+  ~Stage() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) {
+      c->ev_free.push_back(a);
+      return;
+    }
+    (void)hipEventRecord(b, st);
+    c->pending.push_back({stage, a, b});
+  }
+};
 
 template <class T>
 T* P(DevBuf& b) {
@@ -133,6 +179,8 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     return fail(ctx, G4D_EINVAL, "invalid settings");
   if (s->tile_size != 8 && s->tile_size != 16 && s->tile_size != 32)
     return fail(ctx, G4D_EINVAL, "tile_size %d not in {8, 16, 32}", s->tile_size);
+  if (s->lds_batch != 0 && s->lds_batch != 32 && s->lds_batch != 64 && s->lds_batch != 128)
+    return fail(ctx, G4D_EINVAL, "lds_batch %d not in {0, 32, 64, 128}", s->lds_batch);
   return G4D_OK;
 }
 
@@ -152,6 +200,7 @@ DSettings device_settings(const g4d_settings* s) {
   d.time_period = s->time_period;
   d.tile = s->tile_size;
   d.tile_shift = s->tile_size == 8 ? 3 : (s->tile_size == 16 ? 4 : 5);
+  d.lds_batch = s->lds_batch == 0 ? 64 : s->lds_batch;
   return d;
 }
 
@@ -220,8 +269,11 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
   if (zero_records) G4D_HIP(hipMemsetAsync(ctx->rec.p, 0, sizeof(float) * kRec * slots, st));
   if ((r = ensure(ctx, ctx->tiles, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
-  preprocess_forward(gauss_ptrs(g), P<DView>(ctx->views), n_views, device_settings(s),
-                     P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
+  {
+    Stage t(ctx, 0, st);
+    preprocess_forward(gauss_ptrs(g), P<DView>(ctx->views), n_views, device_settings(s),
+                       P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
+  }
   G4D_HIP(hipGetLastError());
   return G4D_OK;
 }
@@ -304,6 +356,11 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->h_views) (void)hipHostFree(ctx->h_views);
   if (ctx->h_tile_base) (void)hipHostFree(ctx->h_tile_base);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  for (auto& iv : ctx->pending) {
+    (void)hipEventDestroy(iv.a);
+    (void)hipEventDestroy(iv.b);
+  }
+  for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
   delete ctx;
   return G4D_OK;
 }
@@ -365,14 +422,24 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
     if ((r = ensure(ctx, ctx->voff, sizeof(uint32_t) * (slots + 1), 1.1)) != G4D_OK) return r;
     if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
     if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
-    compact_visible(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), slots, P<uint32_t>(ctx->vk[0]),
-                    P<uint32_t>(ctx->vv[0]), cnt + 0, ctx->scan_tmp.p, st);
+    {
+      Stage t(ctx, 1, st);
+      compact_visible(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), slots,
+                      P<uint32_t>(ctx->vk[0]), P<uint32_t>(ctx->vv[0]), cnt + 0, ctx->scan_tmp.p, st);
+    }
     uint32_t* vk[2] = {P<uint32_t>(ctx->vk[0]), P<uint32_t>(ctx->vk[1])};
     uint32_t* vv[2] = {P<uint32_t>(ctx->vv[0]), P<uint32_t>(ctx->vv[1])};
-    const int vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
+    int vb;
+    {
+      Stage t(ctx, 2, st);
+      vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
+    }
     ctx->vis_buf = vb;
-    pair_offsets(P<uint32_t>(ctx->tiles), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->voff), cnt + 1,
-                 ctx->scan_tmp.p, st);
+    {
+      Stage t(ctx, 3, st);
+      pair_offsets(P<uint32_t>(ctx->tiles), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->voff),
+                   cnt + 1, ctx->scan_tmp.p, st);
+    }
     G4D_HIP(hipGetLastError());
     G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     G4D_HIP(hipStreamSynchronize(st));
@@ -389,20 +456,29 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
       if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
           G4D_OK)
         return r;
-      keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, n_vis, cnt + 1,
-             ctx->pair_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->pk[0]),
-             P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+      {
+        Stage t(ctx, 4, st);
+        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, n_vis, cnt + 1,
+               ctx->pair_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->pk[0]),
+               P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+      }
       uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
       uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
-      pb = radix_sort(pk, pv, cnt + 1, n_pairs, bits_for(ctx->n_tiles), ctx->sort_tmp.p, st);
+      {
+        Stage t(ctx, 5, st);
+        pb = radix_sort(pk, pv, cnt + 1, n_pairs, bits_for(ctx->n_tiles), ctx->sort_tmp.p, st);
+      }
       G4D_HIP(hipGetLastError());
     }
   }
   ctx->pair_buf = pb;
-  if (n_pairs > 0) {
-    tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 1, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges), st);
-  } else {
-    G4D_HIP(hipMemsetAsync(ctx->ranges.p, 0, sizeof(uint2) * ctx->n_tiles, st));
+  {
+    Stage t(ctx, 6, st);
+    if (n_pairs > 0)
+      tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 1, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
+                  st);
+    else
+      fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
   }
   RasterArgs a{};
   a.rec = P<float>(ctx->rec);
@@ -418,7 +494,10 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   a.px_T = P<float>(ctx->px_T);
   a.px_last = P<int32_t>(ctx->px_last);
   a.px_evals = ctx->count_evals ? P<uint32_t>(ctx->px_evals) : nullptr;
-  raster_forward(a, st);
+  {
+    Stage t(ctx, 7, st);
+    raster_forward(a, st);
+  }
   G4D_HIP(hipGetLastError());
 
   ctx->stats.n_slots = slots;
@@ -454,7 +533,10 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   if (slots == 0) return G4D_OK;
   const DSettings DS = device_settings(s);
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
-  G4D_HIP(hipMemsetAsync(ctx->grad2d.p, 0, sizeof(float) * kGrad2d * slots, st));
+  {
+    Stage t(ctx, 8, st);
+    fill_u32(P<uint32_t>(ctx->grad2d), kGrad2d * slots, 0u, st);
+  }
   if (ctx->stats.n_pairs > 0) {
     RasterArgs a{};
     a.rec = P<float>(ctx->rec);
@@ -469,12 +551,16 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     a.px_last = P<int32_t>(ctx->px_last);
     a.dL = dL_drgb;
     a.grad2d = P<float>(ctx->grad2d);
+    Stage t(ctx, 9, st);
     raster_backward(a, st);
     G4D_HIP(hipGetLastError());
   }
   GradPtrs gp{out->mean4, out->scale4, out->rot_l, out->rot_r, out->opacity, out->sh};
-  preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
-                      P<float>(ctx->grad2d), gp, st);
+  {
+    Stage t(ctx, 10, st);
+    preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
+                        P<float>(ctx->grad2d), gp, st);
+  }
   G4D_HIP(hipGetLastError());
   return G4D_OK;
 }
@@ -513,6 +599,37 @@ g4d_status g4d_eval_counters(g4d_ctx* ctx, int enable, uint32_t* out, void* stre
   }
   ctx->count_evals = enable != 0;
   return G4D_OK;
+}
+
+g4d_status g4d_profile(g4d_ctx* ctx, int enable, double* ms, int64_t* launches, int reset) {
+  if (!ctx) return G4D_EINVAL;
+  G4D_HIP(hipSetDevice(ctx->device));
+  if (ms || launches || reset) {
+    G4D_HIP(hipDeviceSynchronize());
+    for (auto& iv : ctx->pending) {
+      float t = 0.f;
+      G4D_HIP(hipEventElapsedTime(&t, iv.a, iv.b));
+      ctx->stage_ms[iv.stage] += t;
+      ctx->stage_n[iv.stage] += 1;
+      ctx->ev_free.push_back(iv.a);
+      ctx->ev_free.push_back(iv.b);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < G4D_NUM_STAGES; ++k) {
+      if (ms) ms[k] = ctx->stage_ms[k];
+      if (launches) launches[k] = ctx->stage_n[k];
+      if (reset) {
+        ctx->stage_ms[k] = 0.0;
+        ctx->stage_n[k] = 0;
+      }
+    }
+  }
+  ctx->profiling = enable != 0;
+  return G4D_OK;
+}
+
+const char* g4d_stage_name(int stage) {
+  return (stage >= 0 && stage < G4D_NUM_STAGES) ? kStageNames[stage] : "";
 }
 
 }  // extern "C"

@@ -87,12 +87,20 @@ struct WaveTile {
   uint2 range;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b mod 8), and each XCD
+// has its own L2.  Block b is given logical block (b mod 8) * per + b / 8, so that every XCD
+// works through a contiguous run of tiles whose large splats it shares in its L2.  The grid
+// is padded to 8 * per blocks; logical blocks past the end do nothing.
+__device__ __forceinline__ int xcd_logical_block(int per) {
+  return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+}
+
 template <int TILE>
 __device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
   constexpr int QX = TILE / 8, QPT = QX * QX;
   t.lane = threadIdx.x & 63;
   t.w = threadIdx.x >> 6;
-  const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + t.w);
+  const int gw = __builtin_amdgcn_readfirstlane(xcd_logical_block(a.blocks_per_xcd) * 4 + t.w);
   t.tile = gw / QPT;
   if (t.tile >= a.n_tiles) return false;
   const int q = gw - t.tile * QPT;
@@ -129,30 +137,45 @@ __device__ __forceinline__ bool fetch_entry(const RasterArgs& a, const WaveTile&
   return keep;
 }
 
-template <int TILE>
+// Stage up to BATCH list entries starting at `base` (fetch rounds of 64 lanes) into `st`,
+// keeping only those that can reach the wave's block; returns how many were kept.
+template <int BATCH>
+__device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& t, int base,
+                                           int end, Staged* st) {
+  int n = 0;
+#pragma unroll
+  for (int r = 0; r < (BATCH + 63) / 64; ++r) {
+    const int j = base + r * 64 + t.lane;
+    const bool in = (BATCH >= 64 || t.lane < BATCH) && j < end;
+    Staged s;
+    const bool keep = fetch_entry(a, t, (uint32_t)j, in, s);
+    const uint64_t mask = __ballot(keep);
+    if (keep) {
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+      st[n + pos] = s;
+    }
+    n += __popcll(mask);
+  }
+  return n;
+}
+
+template <int TILE, int BATCH>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
-  __shared__ Staged stage[4][64];
+  __shared__ Staged stage[4][BATCH];
   WaveTile t;
   if (!wave_tile<TILE>(a, t)) return;
   const DView& V = a.views[t.v];
   const DSettings& S = a.S;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   int last = -1;
-  uint32_t evals = 0;
+  uint32_t evals = 0, contrib = 0;
   bool done = !t.inside;
   Staged* st = stage[t.w];
-  for (uint32_t base = t.range.x; base < t.range.y; base += 64) {
+  const int end = (int)t.range.y;
+  for (int base = (int)t.range.x; base < end; base += BATCH) {
     if (__ballot(!done) == 0ull) break;
-    const uint32_t j = base + t.lane;
-    Staged s;
-    const bool keep = fetch_entry(a, t, j, j < t.range.y, s);
-    const uint64_t mask = __ballot(keep);
-    const int n = __popcll(mask);
-    if (keep) {
-      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-      st[pos] = s;
-    }
+    const int n = stage_batch<BATCH>(a, t, base, end, st);
     G4D_WAVE_SYNC();
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
@@ -174,6 +197,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
               C2 = fmaf(wgt, e2.x, C2);
               T = Tn;
               last = __float_as_int(e2.y);
+              ++contrib;
             }
           }
         }
@@ -193,13 +217,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     if (a.out_T) a.out_T[gp] = T;
     a.px_T[gp] = T;
     a.px_last[gp] = last;
-    if (a.px_evals) a.px_evals[gp] = evals;
+    if (a.px_evals) a.px_evals[gp] = min(evals, 65535u) | (min(contrib, 65535u) << 16);
   }
 }
 
-template <int TILE>
+template <int TILE, int BATCH>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
-  __shared__ Staged stage[4][64];
+  __shared__ Staged stage[4][BATCH];
   WaveTile t;
   if (!wave_tile<TILE>(a, t)) return;
   const DView& V = a.views[t.v];
@@ -222,18 +246,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   float R0 = V.bg[0], R1 = V.bg[1], R2 = V.bg[2];
   Staged* st = stage[t.w];
   const int lo_list = (int)t.range.x;
-  for (int hi = hi_last + 1; hi > lo_list; hi -= 64) {
-    const int lo = max(lo_list, hi - 64);
-    const int j = lo + t.lane;
-    Staged s;
-    const bool keep = fetch_entry(a, t, (uint32_t)j, j < hi, s);
-    const uint64_t mask = __ballot(keep);
-    const int n = __popcll(mask);
-    if (keep) {
-      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-      st[pos] = s;
-    }
+  for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
+    const int lo = max(lo_list, hi - BATCH);
+    const int n = stage_batch<BATCH>(a, t, lo, hi, st);
     G4D_WAVE_SYNC();
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
@@ -290,23 +305,35 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   }
 }
 
-template <int TILE>
+template <int TILE, int BATCH>
 void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
   constexpr int QPT = (TILE / 8) * (TILE / 8);
   const int64_t waves = (int64_t)a.n_tiles * QPT;
-  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  const int64_t blocks = (waves + 3) / 4;
   if (blocks == 0) return;
+  RasterArgs b = a;
+  b.blocks_per_xcd = (int)((blocks + 7) / 8);
+  const unsigned grid = 8u * (unsigned)b.blocks_per_xcd;
   if (backward)
-    hipLaunchKernelGGL(k_raster_bwd<TILE>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH>), dim3(grid), dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL(k_raster_fwd<TILE>, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH>), dim3(grid), dim3(256), 0, st, b);
+}
+
+template <int TILE>
+void dispatch_batch(const RasterArgs& a, hipStream_t st, bool backward) {
+  switch (a.S.lds_batch) {
+    case 32: launch_raster<TILE, 32>(a, st, backward); break;
+    case 128: launch_raster<TILE, 128>(a, st, backward); break;
+    default: launch_raster<TILE, 64>(a, st, backward); break;
+  }
 }
 
 void dispatch(const RasterArgs& a, hipStream_t st, bool backward) {
   switch (a.S.tile) {
-    case 8: launch_raster<8>(a, st, backward); break;
-    case 32: launch_raster<32>(a, st, backward); break;
-    default: launch_raster<16>(a, st, backward); break;
+    case 8: dispatch_batch<8>(a, st, backward); break;
+    case 32: dispatch_batch<32>(a, st, backward); break;
+    default: dispatch_batch<16>(a, st, backward); break;
   }
 }
 

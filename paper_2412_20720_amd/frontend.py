@@ -110,6 +110,17 @@ class Renderer:
         return out
 
 
+    def profile(self, enable: bool, collect: bool = True, reset: bool = True):
+        """Stage timing (HIP events on the call's stream): returns {stage: (ms, launches)}."""
+        ms = (C.c_double * B.G4D_NUM_STAGES)()
+        n = (C.c_int64 * B.G4D_NUM_STAGES)()
+        B.check(B.lib().g4d_profile(self._ctx, int(enable), ms if collect else None,
+                                    n if collect else None, int(reset)), self._ctx)
+        if not collect:
+            return None
+        return {B.lib().g4d_stage_name(k).decode(): (ms[k], n[k]) for k in range(B.G4D_NUM_STAGES)}
+
+
 class _Render4D(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, mean4, scale4,

@@ -53,12 +53,22 @@ def test_w0_full_image(renderer, w0, marginal_min):
     assert np.abs(T - ref["T"])[ok].max() <= TOL
 
 
-def test_w0_tile_size_does_not_change_the_image(renderer, w0):
-    imgs = {}
+def test_w0_tile_and_batch_do_not_change_the_result(renderer, w0):
+    # Tiles and LDS batches only decide which records a wave looks at, never which pass the
+    # per-pixel cutoff: images are bit-identical, gradients equal up to atomic summation order.
+    dl = scenes.make_dl_dimage(w0)
+    imgs, grads = {}, {}
     for tile in (8, 16, 32):
-        log(f"w0 tile {tile}")
-        imgs[tile] = GpuRun(renderer, w0, tile_size=tile).forward().images()[0]
-    assert np.array_equal(imgs[8], imgs[16]) and np.array_equal(imgs[16], imgs[32])
+        for batch in (32, 64, 128):
+            log(f"w0 tile {tile} batch {batch}")
+            run = GpuRun(renderer, w0, tile_size=tile, lds_batch=batch).forward()
+            imgs[tile, batch] = run.images()[0]
+            grads[tile, batch] = run.backward(dl)
+    ref_img, ref_g = imgs[16, 64], grads[16, 64]
+    for key in imgs:
+        assert np.array_equal(imgs[key], ref_img), key
+        for k, v in grads[key].items():
+            np.testing.assert_allclose(v, ref_g[k], rtol=1e-4, atol=1e-6 * np.abs(ref_g[k]).max())
 
 
 def test_w1_records_match_oracle_splats(renderer, w1):
