@@ -43,7 +43,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="2", choices=sorted(WORKLOAD_KEYS))
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune)")
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--px", type=int, default=4)
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=1)
@@ -64,7 +66,8 @@ def main():
     p = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in sc.arrays().items()}
     names = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
     g = r.gaussians(*[p[k] for k in names], sc.sh_degree, sc.t_degree)
-    settings = B.default_settings(time_period=sc.time_period, tile_size=args.tile)
+    settings = B.default_settings(time_period=sc.time_period, tile_size=args.tile or 16,
+                                  lds_batch=args.batch, px_per_lane=args.px)
     views = B.make_views(sc.views)
     npix = sc.pixels
     rgb = torch.empty(3 * npix, device=dev)
@@ -75,6 +78,12 @@ def main():
     def step():
         r.forward(g, views, settings, rgb, T)
         r.backward(g, views, settings, dL, grads)
+
+    tuned_ms = None
+    if args.tile == 0:
+        tuned_ms = r.autotune(g, views, settings, dL, rgb, T, grads, reps=2)
+        log(f"bench: autotuned tile {settings.tile_size}, LDS batch {settings.lds_batch}, "
+            f"pixels/lane {settings.px_per_lane} ({tuned_ms:.2f} ms)")
 
     # Work counts of this workload (untimed, counted by the forward kernel itself).
     r.eval_counters(True)
@@ -147,7 +156,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": sc.name, "gaussians": sc.n, "views": len(sc.views),
                    "pixels": npix, "sh_degree": sc.sh_degree, "t_degree": sc.t_degree,
-                   "tile": args.tile},
+                   "tile": settings.tile_size, "lds_batch": settings.lds_batch,
+                   "px_per_lane": settings.px_per_lane, "autotuned": args.tile == 0},
         "per_view": per_view,
         "roofline": roofline,
         "cpu_baseline": cpu,

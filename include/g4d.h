@@ -93,11 +93,15 @@ typedef struct {
  *   time_period 1     the period T of the Fourier basis of the 4DSH
  *   tile_size 16      screen tile side in pixels (8, 16 or 32)
  *   lds_batch 0       list entries a wave stages in LDS at a time: 32, 64 or 128
- *                     (0 = library default, 64) */
+ *                     (0 = library default, 64)
+ *   px_per_lane 0     pixels per lane of the raster waves: 1 (8x8 block per wave), 2 (16x8)
+ *                     or 4 (16x16); 2 and 4 need tile_size >= 16 (0 = library default:
+ *                     4, or 1 for 8-pixel tiles)
+ * Tile size, batch and pixels per lane change the work decomposition only, never the image. */
 typedef struct {
   float near_z, marginal_min, cutoff_sigma, blur, jacobian_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
-  int32_t tile_size, lds_batch;
+  int32_t tile_size, lds_batch, px_per_lane;
 } g4d_settings;
 
 /* Work counters of the last forward (host). */
@@ -152,6 +156,23 @@ g4d_status g4d_render_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_v
                                int32_t n_views, const g4d_settings *s, const float *dL_drgb,
                                const g4d_grads *out, void *stream);
 
+/* Flags of g4d_render_step. */
+#define G4D_STEP_GRAPH 1
+
+/* One training-style step: g4d_render_forward then g4d_render_backward with dL_drgb (the
+ * whole differentiable render of Sec. 3.2 and its derivative for a batch of views).  With
+ * flags & G4D_STEP_GRAPH the step is captured once into a hipGraph and replayed on later calls
+ * with the same inputs, views, settings and buffer addresses (parameter and dL values may
+ * change between calls): no host synchronization, allocation or per-kernel launch happens in
+ * a replay.  The first call (and any call whose key changed) runs one eager step on a private
+ * context to size the buffers, then captures with a pair capacity 25% above the pair count
+ * it found; if a later replay finds more pairs, g4d_sync_status reports G4D_ECAPACITY and the
+ * outputs of that replay are undefined. */
+g4d_status g4d_render_step(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                           int32_t n_views, const g4d_settings *s, const float *dL_drgb,
+                           float *out_rgb, float *out_T, const g4d_grads *grads, int32_t flags,
+                           void *stream);
+
 /* Wait for the context's work on `stream` and report errors found on the device
  * (G4D_ECAPACITY when the pair capacity was exceeded; outputs are then undefined). */
 g4d_status g4d_sync_status(g4d_ctx *ctx, void *stream);
@@ -166,6 +187,19 @@ g4d_status g4d_get_stats(g4d_ctx *ctx, g4d_stats *out, void *stream);
  * If `out` (device, [total pixels] uint32, views concatenated) is not NULL, the counters of
  * the last counted forward are copied there (G4D_ESTATE if there is none). */
 g4d_status g4d_eval_counters(g4d_ctx *ctx, int enable, uint32_t *out, void *stream);
+
+/* Autotuner: picks tile_size, lds_batch and px_per_lane for this problem shape (N, SH and
+ * Fourier degrees, view count and sizes, cutoff and thresholds) by timing `reps` forward +
+ * backward passes of every valid combination with HIP events on `stream`, and writes the
+ * fastest into *s (other fields are kept).  The choice changes the work decomposition only,
+ * never the image (eq:4dblending is evaluated per pixel with the same cutoff).  Results are
+ * cached in the context per shape; a cached shape returns at once.  out_rgb, out_T (may be
+ * NULL), dL_drgb and grads are caller buffers of the g4d_render_forward / backward layouts,
+ * overwritten.  *best_ms (may be NULL) receives the time of the chosen setting. */
+g4d_status g4d_autotune(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                        int32_t n_views, g4d_settings *s, const float *dL_drgb, float *out_rgb,
+                        float *out_T, const g4d_grads *grads, int32_t reps, double *best_ms,
+                        void *stream);
 
 /* Pipeline stages timed by g4d_profile (index: name). */
 #define G4D_NUM_STAGES 11

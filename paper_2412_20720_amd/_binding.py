@@ -18,7 +18,9 @@ STATUS_NAMES = {0: "G4D_OK", -1: "G4D_EINVAL", -2: "G4D_ENOMEM", -3: "G4D_ECAPAC
 
 EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error",
             "g4d_preprocess", "g4d_render_forward", "g4d_render_backward", "g4d_sync_status",
-            "g4d_get_stats", "g4d_eval_counters", "g4d_profile", "g4d_stage_name"]
+            "g4d_get_stats", "g4d_eval_counters", "g4d_autotune", "g4d_profile",
+            "g4d_stage_name", "g4d_render_step"]
+G4D_STEP_GRAPH = 1
 G4D_NUM_STAGES = 11
 
 
@@ -44,7 +46,7 @@ class g4d_settings(C.Structure):
                 ("blur", C.c_float), ("jacobian_margin", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("color_offset", C.c_float),
                 ("color_min", C.c_float), ("time_period", C.c_float), ("tile_size", C.c_int32),
-                ("lds_batch", C.c_int32)]
+                ("lds_batch", C.c_int32), ("px_per_lane", C.c_int32)]
 
 
 class g4d_stats(C.Structure):
@@ -79,6 +81,12 @@ def lib() -> C.CDLL:
     L.g4d_sync_status.argtypes = [vp, vp]
     L.g4d_get_stats.argtypes = [vp, C.POINTER(g4d_stats), vp]
     L.g4d_eval_counters.argtypes = [vp, C.c_int, vp, vp]
+    L.g4d_render_step.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
+                                  C.POINTER(g4d_settings), vp, vp, vp, C.POINTER(g4d_grads), i32,
+                                  vp]
+    L.g4d_autotune.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
+                               C.POINTER(g4d_settings), vp, vp, vp, C.POINTER(g4d_grads), i32,
+                               C.POINTER(C.c_double), vp]
     L.g4d_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.g4d_stage_name.argtypes = [C.c_int]
     L.g4d_stage_name.restype = C.c_char_p

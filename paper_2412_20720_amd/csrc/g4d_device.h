@@ -49,7 +49,7 @@ struct DView {
 struct DSettings {
   float near_z, marginal_min, cutoff, cut2, blur, jac_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
-  int32_t tile, tile_shift, lds_batch;
+  int32_t tile, tile_shift, lds_batch, px_per_lane;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -314,12 +314,12 @@ __device__ __forceinline__ void color_forward(const float* sh, const DSettings& 
   }
 }
 
-// Box of the cutoff ellipse, widened by 1e-4 relative so that FP32 rounding never drops a
+// Box of the cutoff ellipse, widened by 5e-4 relative so that FP32 rounding never drops a
 // pixel whose exact Mahalanobis distance passes the cutoff.
 __device__ __forceinline__ void cutoff_extent(const ViewFwd& f, const DSettings& S, float& ex,
                                               float& ey) {
-  ex = S.cutoff * sqrtf(f.cov[0]) * 1.0001f;
-  ey = S.cutoff * sqrtf(f.cov[2]) * 1.0001f;
+  ex = S.cutoff * sqrtf(f.cov[0]) * 1.0005f;
+  ey = S.cutoff * sqrtf(f.cov[2]) * 1.0005f;
 }
 
 // Tiles whose pixel centres can lie inside [u - ex, u + ex] x [v - ey, v + ey]; false if none.
@@ -338,6 +338,59 @@ __device__ __forceinline__ bool tile_rect(float u, float v, float ex, float ey, 
   y1 = (int)fy1 >> shift;
   return true;
 }
+
+// x-range [xl, xr] (relative to the splat centre) of the ellipse a dx^2 + 2 b dx dy + c dy^2
+// <= lim over the band dy in [dy0, dy1]; false if the band misses it.  ex, ey are the
+// ellipse's (already widened) half extents.  For fixed dy the ellipse spans
+// dx = -b dy / a +- sqrt(lim a - D dy^2) / a with D = ac - b^2; over a band the leftmost
+// (rightmost) x is the ellipse's own extreme -ex (+ex) if the band contains its height
+// dy = b ex / c (-b ex / c), else it is reached at an end of the band.  When D is tiny next to
+// ac (a thin, tilted ellipse) FP32 cannot resolve the chords and the full box is returned.
+__device__ __forceinline__ bool ellipse_band_xrange(float a, float b, float c, float lim,
+                                                    float ex, float ey, float dy0, float dy1,
+                                                    float& xl, float& xr) {
+  if (!(dy1 >= -ey) || !(dy0 <= ey)) return false;
+  const float D = a * c - b * b;
+  if (!(D > 1e-3f * a * c)) {
+    xl = -ex;
+    xr = ex;
+    return true;
+  }
+  dy0 = fmaxf(dy0, -ey);
+  dy1 = fminf(dy1, ey);
+  const float ia = 1.f / a;
+  const float dyl = b * ex / c;
+  const float sl = -b * ia;
+  const float h0 = sqrtf(fmaxf(0.f, lim * a - D * dy0 * dy0)) * ia;
+  const float h1 = sqrtf(fmaxf(0.f, lim * a - D * dy1 * dy1)) * ia;
+  xl = (dyl >= dy0 && dyl <= dy1) ? -ex : fminf(sl * dy0 - h0, sl * dy1 - h1);
+  xr = (-dyl >= dy0 && -dyl <= dy1) ? ex : fmaxf(sl * dy0 + h0, sl * dy1 + h1);
+  return true;
+}
+
+// Tile columns of tile row `ty` that hold a pixel centre the splat's cutoff ellipse (slightly
+// widened) can reach, clipped to [tx0, tx1]: returns (first << 16) | last, or -1 if none.
+// Not inlined, so that the preprocess (which counts the pairs) and the key generation (which
+// writes them) run the very same instructions and always agree.
+__device__ __noinline__ int tile_row_span(float u, float v, float a, float b, float c, float lim,
+                                          float ex, float ey, int ty, int shift, int width,
+                                          int height, int tx0, int tx1) {
+  const int T = 1 << shift;
+  const float y0 = (float)(ty * T) + 0.5f;
+  const float y1 = fminf((float)(ty * T + T) - 0.5f, (float)height - 0.5f);
+  float xl, xr;
+  if (!ellipse_band_xrange(a, b, c, lim, ex, ey, y0 - v, y1 - v, xl, xr)) return -1;
+  float px0 = ceilf(u + xl - 0.5f - 1e-2f), px1 = floorf(u + xr - 0.5f + 1e-2f);
+  px0 = fmaxf(px0, 0.f);
+  px1 = fminf(px1, (float)(width - 1));
+  if (!(px0 <= px1)) return -1;
+  const int c0 = max((int)px0 >> shift, tx0), c1 = min((int)px1 >> shift, tx1);
+  return c0 <= c1 ? (c0 << 16) | c1 : -1;
+}
+
+// Cutoff used for tile coverage: 1e-3 above cutoff^2, so that FP32 rounding in the coverage
+// test never drops a pixel whose exact Mahalanobis distance passes the cutoff.
+__device__ __forceinline__ float coverage_limit(const DSettings& S) { return S.cut2 * 1.001f; }
 
 // ------------------------------------------------------------------------------------------
 // Adjoint of one view.  Inputs: the screen-space gradient q[0..8] of (u, v, conic a, b, c,

@@ -44,6 +44,9 @@ void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const 
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
                  int64_t n_tiles, uint2* ranges, hipStream_t st);
 
+// *out = min(*n, cap) on the device.
+void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st);
+
 // Derive camera centres and Jacobian clamps of the views on the device.
 void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st);
 

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -60,6 +62,17 @@ struct g4d_ctx {
   std::vector<Interval> pending;
   double stage_ms[G4D_NUM_STAGES] = {};
   int64_t stage_n[G4D_NUM_STAGES] = {};
+  // autotuner cache: problem shape -> (tile, lds batch, pixels per lane, ms)
+  struct Tuned { int tile, batch, px; double ms; };
+  std::map<std::string, Tuned> tuned;
+  // graph mode: while `capturing`, no host synchronization, allocation or upload happens and
+  // grids are sized from the capacities found by an earlier eager pass
+  bool capturing = false;
+  g4d_ctx* graph_ctx = nullptr;    // private context whose buffers the captured graph uses
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<unsigned char> graph_key;
 };
 
 namespace {
@@ -84,6 +97,7 @@ g4d_status fail(g4d_ctx* c, g4d_status st, const char* fmt, ...) {
 g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
   if (bytes == 0) bytes = 256;
   if (bytes <= b.cap) return G4D_OK;
+  if (ctx->capturing) return fail(ctx, G4D_ECAPACITY, "buffer too small during graph capture");
   const size_t want = std::max(bytes, (size_t)((double)bytes * grow));
   if (b.p) {
     G4D_HIP(hipDeviceSynchronize());
@@ -125,7 +139,7 @@ struct Stage {
   hipStream_t st;
   hipEvent_t a = nullptr;
   Stage(g4d_ctx* c_, int s_, hipStream_t st_) : c(c_), stage(s_), st(st_) {
-    if (c->profiling && (a = take_event(c))) (void)hipEventRecord(a, st);
+    if (c->profiling && !c->capturing && (a = take_event(c))) (void)hipEventRecord(a, st);
   }
   ~Stage() {
     if (!a) return;
@@ -181,6 +195,10 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     return fail(ctx, G4D_EINVAL, "tile_size %d not in {8, 16, 32}", s->tile_size);
   if (s->lds_batch != 0 && s->lds_batch != 32 && s->lds_batch != 64 && s->lds_batch != 128)
     return fail(ctx, G4D_EINVAL, "lds_batch %d not in {0, 32, 64, 128}", s->lds_batch);
+  if (s->px_per_lane != 0 && s->px_per_lane != 1 && s->px_per_lane != 2 && s->px_per_lane != 4)
+    return fail(ctx, G4D_EINVAL, "px_per_lane %d not in {0, 1, 2, 4}", s->px_per_lane);
+  if (s->tile_size == 8 && s->px_per_lane > 1)
+    return fail(ctx, G4D_EINVAL, "px_per_lane %d needs tile_size >= 16", s->px_per_lane);
   return G4D_OK;
 }
 
@@ -201,6 +219,7 @@ DSettings device_settings(const g4d_settings* s) {
   d.tile = s->tile_size;
   d.tile_shift = s->tile_size == 8 ? 3 : (s->tile_size == 16 ? 4 : 5);
   d.lds_batch = s->lds_batch == 0 ? 64 : s->lds_batch;
+  d.px_per_lane = s->px_per_lane == 0 ? (s->tile_size == 8 ? 1 : 4) : s->px_per_lane;
   return d;
 }
 
@@ -212,7 +231,7 @@ GaussPtrs gauss_ptrs(const g4d_gaussians* g) {
 // Plan tile grids and offsets, upload the view table and derive per-view constants.
 g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const g4d_settings* s,
                         hipStream_t st) {
-  if (ctx->staging_pending) {
+  if (ctx->staging_pending && !ctx->capturing) {
     G4D_HIP(hipEventSynchronize(ctx->staging_done));
     ctx->staging_pending = false;
   }
@@ -247,6 +266,7 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
   ctx->h_tile_base[n_views] = (int32_t)tile_base;
   ctx->n_tiles = tile_base;
   ctx->n_pixels = pix_base;
+  if (ctx->capturing) return G4D_OK;  // the view table was uploaded before the capture
   g4d_status r;
   if ((r = ensure(ctx, ctx->views, sizeof(DView) * n_views)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->tile_base, sizeof(int32_t) * (n_views + 1))) != G4D_OK) return r;
@@ -315,6 +335,7 @@ g4d_status g4d_default_settings(g4d_settings* s) {
   s->time_period = 1.f;
   s->tile_size = 16;
   s->lds_batch = 0;
+  s->px_per_lane = 0;
   return G4D_OK;
 }
 
@@ -345,6 +366,10 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (!ctx) return G4D_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->graph_ctx) g4d_destroy(ctx->graph_ctx);
   DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->dkey,
                     &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->voff,
                     &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
@@ -402,8 +427,9 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   const int64_t slots = (int64_t)g->n * n_views;
   const DSettings DS = device_settings(s);
   if ((r = ensure(ctx, ctx->counters, 4 * sizeof(uint32_t))) != G4D_OK) return r;
-  uint32_t* cnt = P<uint32_t>(ctx->counters);  // [0] visible, [1] pairs, [2] overflow
-  G4D_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(uint32_t), st));
+  // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity
+  uint32_t* cnt = P<uint32_t>(ctx->counters);
+  fill_u32(cnt, 4, 0u, st);
   if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->ranges, sizeof(uint2) * ctx->n_tiles, 1.1)) != G4D_OK) return r;
@@ -441,32 +467,41 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
                    cnt + 1, ctx->scan_tmp.p, st);
     }
     G4D_HIP(hipGetLastError());
-    G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    G4D_HIP(hipStreamSynchronize(st));
-    n_vis = ctx->h_counters[0];
-    n_pairs = ctx->h_counters[1];
-    if (n_pairs > 0) {
+    int64_t vis_grid = slots, pair_grid;
+    if (ctx->capturing) {
+      // counts stay on the device; grids cover the capacities
+      n_pairs = pair_grid = ctx->pair_cap;
+    } else {
+      G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      G4D_HIP(hipStreamSynchronize(st));
+      n_vis = vis_grid = ctx->h_counters[0];
+      n_pairs = pair_grid = ctx->h_counters[1];
       if (n_pairs > (int64_t)UINT32_MAX - 1)
         return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^32-2", (long long)n_pairs);
-      for (int b = 0; b < 2; ++b) {
-        if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
-        if ((r = ensure(ctx, ctx->pv[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
+      if (n_pairs > 0) {
+        for (int b = 0; b < 2; ++b) {
+          if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
+          if ((r = ensure(ctx, ctx->pv[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
+        }
+        ctx->pair_cap = (int64_t)(ctx->pk[0].cap / sizeof(uint32_t));
+        if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
+            G4D_OK)
+          return r;
       }
-      ctx->pair_cap = (int64_t)(ctx->pk[0].cap / sizeof(uint32_t));
-      if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
-          G4D_OK)
-        return r;
+    }
+    if (n_pairs > 0) {
       {
         Stage t(ctx, 4, st);
-        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, n_vis, cnt + 1,
+        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
                ctx->pair_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->pk[0]),
                P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+        clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
       }
       uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
       uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
       {
         Stage t(ctx, 5, st);
-        pb = radix_sort(pk, pv, cnt + 1, n_pairs, bits_for(ctx->n_tiles), ctx->sort_tmp.p, st);
+        pb = radix_sort(pk, pv, cnt + 3, pair_grid, bits_for(ctx->n_tiles), ctx->sort_tmp.p, st);
       }
       G4D_HIP(hipGetLastError());
     }
@@ -475,7 +510,7 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   {
     Stage t(ctx, 6, st);
     if (n_pairs > 0)
-      tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 1, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
+      tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 3, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
                   st);
     else
       fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
@@ -500,6 +535,7 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   }
   G4D_HIP(hipGetLastError());
 
+  if (ctx->capturing) n_vis = n_pairs = -1;  // known on the device only
   ctx->stats.n_slots = slots;
   ctx->stats.n_visible = n_vis;
   ctx->stats.n_pairs = n_pairs;
@@ -537,7 +573,7 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     Stage t(ctx, 8, st);
     fill_u32(P<uint32_t>(ctx->grad2d), kGrad2d * slots, 0u, st);
   }
-  if (ctx->stats.n_pairs > 0) {
+  if (ctx->stats.n_pairs > 0 || ctx->capturing) {
     RasterArgs a{};
     a.rec = P<float>(ctx->rec);
     a.pval = P<uint32_t>(ctx->pv[ctx->pair_buf]);
@@ -565,14 +601,104 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   return G4D_OK;
 }
 
+g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                           int32_t n_views, const g4d_settings* s, const float* dL_drgb,
+                           float* out_rgb, float* out_T, const g4d_grads* grads, int32_t flags,
+                           void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  if (!dL_drgb || !out_rgb || !grads) return fail(ctx, G4D_EINVAL, "null buffers");
+  if (!(flags & G4D_STEP_GRAPH)) {
+    if ((r = g4d_render_forward(ctx, g, views, n_views, s, out_rgb, out_T, stream)) != G4D_OK)
+      return r;
+    return g4d_render_backward(ctx, g, views, n_views, s, dL_drgb, grads, stream);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  // Everything the captured graph depends on: inputs, views, settings and output addresses.
+  std::vector<unsigned char> key;
+  auto put = [&key](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    key.insert(key.end(), b, b + n);
+  };
+  put(g, sizeof *g);
+  put(views, sizeof(g4d_view) * n_views);
+  put(s, sizeof *s);
+  put(&dL_drgb, sizeof dL_drgb);
+  put(&out_rgb, sizeof out_rgb);
+  put(&out_T, sizeof out_T);
+  put(grads, sizeof *grads);
+  if (!ctx->graph_exec || key != ctx->graph_key) {
+    if (!ctx->graph_ctx) {
+      if ((r = g4d_create(&ctx->graph_ctx, ctx->device)) != G4D_OK)
+        return fail(ctx, r, "cannot create the graph context");
+      G4D_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    }
+    g4d_ctx* gc = ctx->graph_ctx;
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_key.clear();
+    // One eager pass sizes every buffer and finds the pair count; the capture then gets a
+    // pair capacity with 25% headroom (exceeding it is reported by g4d_sync_status).
+    if ((r = g4d_render_forward(gc, g, views, n_views, s, out_rgb, out_T, stream)) != G4D_OK ||
+        (r = g4d_render_backward(gc, g, views, n_views, s, dL_drgb, grads, stream)) != G4D_OK)
+      return fail(ctx, r, "graph sizing pass: %s", gc->err.c_str());
+    G4D_HIP(hipStreamSynchronize(st));
+    const int64_t slots = (int64_t)g->n * n_views;
+    const int64_t want = gc->stats.n_pairs + gc->stats.n_pairs / 4 + 4096;
+    for (int b = 0; b < 2; ++b) {
+      if ((r = ensure(gc, gc->pk[b], sizeof(uint32_t) * want)) != G4D_OK ||
+          (r = ensure(gc, gc->pv[b], sizeof(uint32_t) * want)) != G4D_OK)
+        return fail(ctx, r, "%s", gc->err.c_str());
+    }
+    gc->pair_cap = (int64_t)(std::min(gc->pk[0].cap, gc->pv[0].cap) / sizeof(uint32_t));
+    if ((r = ensure(gc, gc->sort_tmp, radix_scratch_bytes(std::max(gc->pair_cap, slots)))) != G4D_OK)
+      return fail(ctx, r, "%s", gc->err.c_str());
+    G4D_HIP(hipDeviceSynchronize());
+    gc->capturing = true;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      gc->capturing = false;
+      return fail(ctx, G4D_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    g4d_status r1 = g4d_render_forward(gc, g, views, n_views, s, out_rgb, out_T, ctx->cap_stream);
+    g4d_status r2 = r1 == G4D_OK ? g4d_render_backward(gc, g, views, n_views, s, dL_drgb, grads,
+                                                       ctx->cap_stream)
+                                 : r1;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    gc->capturing = false;
+    if (r2 != G4D_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(ctx, r2 != G4D_OK ? r2 : G4D_EHIP, "graph capture failed: %s",
+                  r2 != G4D_OK ? gc->err.c_str() : hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      ctx->graph_exec = nullptr;
+      return fail(ctx, G4D_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    ctx->graph = graph;
+    ctx->graph_key = key;
+  }
+  G4D_HIP(hipGraphLaunch(ctx->graph_exec, st));
+  return G4D_OK;
+}
+
 g4d_status g4d_sync_status(g4d_ctx* ctx, void* stream) {
   if (!ctx) return G4D_EINVAL;
   G4D_HIP(hipSetDevice(ctx->device));
   G4D_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  if (ctx->counters.p) {
+  for (g4d_ctx* c : {ctx, ctx->graph_ctx}) {
+    if (!c || !c->counters.p) continue;
     uint32_t flag = 0;
-    G4D_HIP(hipMemcpy(&flag, P<uint32_t>(ctx->counters) + 2, sizeof flag, hipMemcpyDeviceToHost));
-    if (flag) return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)ctx->pair_cap);
+    G4D_HIP(hipMemcpy(&flag, P<uint32_t>(c->counters) + 2, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag == 1)
+      return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)ctx->pair_cap);
+    if (flag) return fail(ctx, G4D_EHIP, "pair count mismatch between preprocess and keygen");
   }
   return G4D_OK;
 }
@@ -598,6 +724,78 @@ g4d_status g4d_eval_counters(g4d_ctx* ctx, int enable, uint32_t* out, void* stre
                            hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   }
   ctx->count_evals = enable != 0;
+  return G4D_OK;
+}
+
+g4d_status g4d_autotune(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                        int32_t n_views, g4d_settings* s, const float* dL_drgb, float* out_rgb,
+                        float* out_T, const g4d_grads* grads, int32_t reps, double* best_ms,
+                        void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  if (!dL_drgb || !out_rgb || !grads) return fail(ctx, G4D_EINVAL, "null buffers");
+  if (reps < 1) reps = 1;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  // Problem shape: N, degrees, views and their sizes, and the settings that change the work.
+  std::string key = std::to_string(g->n) + "/" + std::to_string(g->sh_degree) + "/" +
+                    std::to_string(g->t_degree) + "/" + std::to_string(n_views);
+  for (int v = 0; v < n_views; ++v)
+    key += "/" + std::to_string(views[v].width) + "x" + std::to_string(views[v].height);
+  char buf[96];
+  snprintf(buf, sizeof buf, "/%g/%g/%g/%g", s->cutoff_sigma, s->marginal_min, s->alpha_min, s->T_min);
+  key += buf;
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    s->tile_size = it->second.tile;
+    s->lds_batch = it->second.batch;
+    s->px_per_lane = it->second.px;
+    if (best_ms) *best_ms = it->second.ms;
+    return G4D_OK;
+  }
+  hipEvent_t e0, e1;
+  G4D_HIP(hipEventCreate(&e0));
+  G4D_HIP(hipEventCreate(&e1));
+  g4d_ctx::Tuned best{16, 64, 4, 1e30};
+  const int tiles[] = {8, 16, 32}, batches[] = {32, 64, 128}, pxs[] = {1, 2, 4};
+  for (int tile : tiles)
+    for (int px : pxs) {
+      if (tile == 8 && px > 1) continue;
+      for (int batch : batches) {
+        g4d_settings trial = *s;
+        trial.tile_size = tile;
+        trial.lds_batch = batch;
+        trial.px_per_lane = px;
+        // one untimed pass sizes every buffer for this tile size
+        if ((r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream)) != G4D_OK ||
+            (r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream)) != G4D_OK)
+          break;
+        G4D_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < reps && r == G4D_OK; ++k) {
+          r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream);
+          if (r == G4D_OK)
+            r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream);
+        }
+        if (r != G4D_OK) break;
+        G4D_HIP(hipEventRecord(e1, st));
+        G4D_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        G4D_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / reps;
+        if (std::getenv("G4D_TUNE_VERBOSE"))
+          fprintf(stderr, "g4d_autotune: tile %d batch %d px/lane %d: %.3f ms\n", tile, batch, px, per);
+        if (per < best.ms) best = {tile, batch, px, per};
+      }
+      if (r != G4D_OK) break;
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != G4D_OK) return r;
+  ctx->tuned[key] = best;
+  s->tile_size = best.tile;
+  s->lds_batch = best.batch;
+  s->px_per_lane = best.px;
+  if (best_ms) *best_ms = best.ms;
   return G4D_OK;
 }
 

@@ -41,7 +41,14 @@ __global__ __launch_bounds__(256) void k_preprocess(
       cutoff_extent(f, S, ex, ey);
       int x0, x1, y0, y1;
       if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1)) {
-        cnt = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        const float lim = coverage_limit(S);
+        for (int ty = y0; ty <= y1; ++ty) {
+          const int span = tile_row_span(f.u, f.v, f.conic[0], f.conic[1], f.conic[2], lim, ex,
+                                         ey, ty, S.tile_shift, V.width, V.height, x0, x1);
+          if (span >= 0) cnt += (uint32_t)((span & 0xFFFF) - (span >> 16) + 1);
+        }
+      }
+      if (cnt > 0) {
         float4* r = reinterpret_cast<float4*>(rec + slot * kRec);
         r[0] = make_float4(f.u, f.v, f.conic[0], f.conic[1]);
         r[1] = make_float4(f.conic[2], op * f.pt, f.color[0], f.color[1]);

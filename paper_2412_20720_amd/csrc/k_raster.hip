@@ -17,9 +17,9 @@
 // R <- alpha c + (1 - alpha) R (R starts at the background).  With g = dL/dC:
 //   dL/dc_i = g T_i alpha_i,  dL/dalpha_i = sum_ch g (c_i - R_i) T_i,
 // and through alpha = opacity p_t exp(-d2/2) (unless clamped at alpha_max) to the screen mean,
-// the conic and opacity p_t.  The nine per-Gaussian values are summed over the wave with DPP
-// row reductions and four readlanes, then one vector atomic (lanes 0..8) adds them to the
-// (view, Gaussian) gradient slot.
+// the conic and opacity p_t.  A lane first adds the contributions of its own pixels; the nine
+// per-Gaussian values are then summed over the wave by a permlane-swap transpose-reduce and
+// one vector atomic (nine lanes) adds them to the (view, Gaussian) gradient slot.
 #include <hip/hip_runtime.h>
 
 #include "g4d_internal.h"
@@ -61,31 +61,11 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the 64 lanes; the result is uniform.
-__device__ __forceinline__ float wave_sum(float x) {
-  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp<0x141>(x);  // row_half_mirror
-  x += dpp<0x140>(x);  // row_mirror: every lane now holds its 16-lane row sum
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-  return (r0 + r1) + (r2 + r3);
-}
-
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
   return x;
 }
-
-struct WaveTile {
-  int tile, v, px, py, lane, w;
-  bool inside;
-  float pxc, pyc, qx0, qx1, qy0, qy1;
-  uint2 range;
-};
 
 // Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b mod 8), and each XCD
 // has its own L2.  Block b is given logical block (b mod 8) * per + b / 8, so that every XCD
@@ -95,9 +75,17 @@ __device__ __forceinline__ int xcd_logical_block(int per) {
   return (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
 }
 
-template <int TILE>
+struct WaveTile {
+  int tile, v, lane, w;
+  int bx, by;                      // pixel origin of the wave's block
+  float qx0, qx1, qy0, qy1;        // pixel-centre box of the block
+  uint2 range;
+};
+
+// Map this wave to (tile, block of BW x BH pixels).  TILE is a multiple of BW and BH.
+template <int TILE, int BW, int BH>
 __device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
-  constexpr int QX = TILE / 8, QPT = QX * QX;
+  constexpr int QX = TILE / BW, QPT = QX * (TILE / BH);
   t.lane = threadIdx.x & 63;
   t.w = threadIdx.x >> 6;
   const int gw = __builtin_amdgcn_readfirstlane(xcd_logical_block(a.blocks_per_xcd) * 4 + t.w);
@@ -108,16 +96,12 @@ __device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
   const DView& V = a.views[t.v];
   const int lt = t.tile - V.tile_base;
   const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
-  const int bx = tx * TILE + (q % QX) * 8, by = ty * TILE + (q / QX) * 8;
-  t.px = bx + (t.lane & 7);
-  t.py = by + (t.lane >> 3);
-  t.inside = t.px < V.width && t.py < V.height;
-  t.pxc = (float)t.px + 0.5f;
-  t.pyc = (float)t.py + 0.5f;
-  t.qx0 = (float)bx + 0.5f;
-  t.qx1 = (float)bx + 7.5f;
-  t.qy0 = (float)by + 0.5f;
-  t.qy1 = (float)by + 7.5f;
+  t.bx = tx * TILE + (q % QX) * BW;
+  t.by = ty * TILE + (q / QX) * BH;
+  t.qx0 = (float)t.bx + 0.5f;
+  t.qx1 = (float)(t.bx + BW) - 0.5f;
+  t.qy0 = (float)t.by + 0.5f;
+  t.qy1 = (float)(t.by + BH) - 0.5f;
   t.range = a.ranges[t.tile];
   return true;
 }
@@ -129,8 +113,15 @@ __device__ __forceinline__ bool fetch_entry(const RasterArgs& a, const WaveTile&
   const uint32_t slot = a.pval[j];
   const float4* r = reinterpret_cast<const float4*>(a.rec + (size_t)slot * kRec);
   const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-  const bool keep = (r0.x + r2.y >= t.qx0) && (r0.x - r2.y <= t.qx1) &&
-                    (r0.y + r2.z >= t.qy0) && (r0.y - r2.z <= t.qy1);
+  bool keep = (r0.x + r2.y >= t.qx0) && (r0.x - r2.y <= t.qx1) &&
+              (r0.y + r2.z >= t.qy0) && (r0.y - r2.z <= t.qy1);
+  if (keep) {
+    // exact test: the ellipse's x-range over the block's rows must meet the block's columns
+    float xl, xr;
+    keep = ellipse_band_xrange(r0.z, r0.w, r1.x, coverage_limit(a.S), r2.y, r2.z,
+                               t.qy0 - r0.y, t.qy1 - r0.y, xl, xr) &&
+           r0.x + xr >= t.qx0 && r0.x + xl <= t.qx1;
+  }
   s.a = make_float4(r0.x, r0.y, r0.z, 2.f * r0.w);
   s.b = r1;
   s.c = make_float4(r2.x, __int_as_float((int)j), __uint_as_float(slot), 0.f);
@@ -160,90 +151,186 @@ __device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& 
   return n;
 }
 
-template <int TILE, int BATCH>
+// A lane owns PXX x PXY pixels of its wave's (8 PXX) x (8 PXY) block: (lane % 8 + 8 a,
+// lane / 8 + 8 b), a < PXX, b < PXY.  Pixel p = b * PXX + a.
+template <int PXX, int PXY>
+struct LanePixels {
+  static constexpr int P = PXX * PXY;
+  int px[P], py[P];
+  bool inside[P];
+  __device__ __forceinline__ void init(const WaveTile& t, const DView& V) {
+#pragma unroll
+    for (int b = 0; b < PXY; ++b)
+#pragma unroll
+      for (int a = 0; a < PXX; ++a) {
+        const int p = b * PXX + a;
+        px[p] = t.bx + (t.lane & 7) + 8 * a;
+        py[p] = t.by + (t.lane >> 3) + 8 * b;
+        inside[p] = px[p] < V.width && py[p] < V.height;
+      }
+  }
+};
+
+template <int TILE, int BATCH, int PXX, int PXY>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
+  constexpr int P = PXX * PXY;
   __shared__ Staged stage[4][BATCH];
   WaveTile t;
-  if (!wave_tile<TILE>(a, t)) return;
+  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
   const DSettings& S = a.S;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  int last = -1;
-  uint32_t evals = 0, contrib = 0;
-  bool done = !t.inside;
+  LanePixels<PXX, PXY> L;
+  L.init(t, V);
+  float T[P], C0[P], C1[P], C2[P], pxc[P], pyc[P];
+  int last[P];
+  uint32_t evals[P], contrib[P];
+  bool done[P];
+  bool live = false;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T[p] = 1.f;
+    C0[p] = C1[p] = C2[p] = 0.f;
+    pxc[p] = (float)L.px[p] + 0.5f;
+    pyc[p] = (float)L.py[p] + 0.5f;
+    last[p] = -1;
+    evals[p] = contrib[p] = 0;
+    done[p] = !L.inside[p];
+    live |= !done[p];
+  }
   Staged* st = stage[t.w];
   const int end = (int)t.range.y;
   for (int base = (int)t.range.x; base < end; base += BATCH) {
-    if (__ballot(!done) == 0ull) break;
+    if (__ballot(live) == 0ull) break;
     const int n = stage_batch<BATCH>(a, t, base, end, st);
     G4D_WAVE_SYNC();
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
-      if (!done) {
-        const float dx = t.pxc - e0.x, dy = t.pyc - e0.y;
-        const float d2 = mahalanobis(dx, dy, e0, e1.x);
-        if (d2 <= S.cut2) {
-          ++evals;
-          const float alpha = fminf(S.alpha_max, e1.y * exp2f(d2 * kNegHalfLog2e));
-          if (alpha >= S.alpha_min) {
-            const float Tn = T * (1.f - alpha);
-            if (Tn < S.T_min) {
-              done = true;
-            } else {
-              const float wgt = T * alpha;
-              C0 = fmaf(wgt, e1.z, C0);
-              C1 = fmaf(wgt, e1.w, C1);
-              C2 = fmaf(wgt, e2.x, C2);
-              T = Tn;
-              last = __float_as_int(e2.y);
-              ++contrib;
+      live = false;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (!done[p]) {
+          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+          const float d2 = mahalanobis(dx, dy, e0, e1.x);
+          if (d2 <= S.cut2) {
+            ++evals[p];
+            const float alpha = fminf(S.alpha_max, e1.y * exp2f(d2 * kNegHalfLog2e));
+            if (alpha >= S.alpha_min) {
+              const float Tn = T[p] * (1.f - alpha);
+              if (Tn < S.T_min) {
+                done[p] = true;
+              } else {
+                const float wgt = T[p] * alpha;
+                C0[p] = fmaf(wgt, e1.z, C0[p]);
+                C1[p] = fmaf(wgt, e1.w, C1[p]);
+                C2[p] = fmaf(wgt, e2.x, C2[p]);
+                T[p] = Tn;
+                last[p] = __float_as_int(e2.y);
+                ++contrib[p];
+              }
             }
           }
         }
+        live |= !done[p];
       }
-      if (__ballot(!done) == 0ull) break;
+      if (__ballot(live) == 0ull) break;
     }
     G4D_WAVE_SYNC();
   }
-  if (t.inside) {
-    const int64_t hw = (int64_t)V.width * V.height;
-    const int64_t pix = (int64_t)t.py * V.width + t.px;
-    float* rgb = a.out_rgb + 3 * (int64_t)V.pix_base;
-    rgb[pix] = fmaf(T, V.bg[0], C0);
-    rgb[hw + pix] = fmaf(T, V.bg[1], C1);
-    rgb[2 * hw + pix] = fmaf(T, V.bg[2], C2);
+  const int64_t hw = (int64_t)V.width * V.height;
+  float* rgb = a.out_rgb + 3 * (int64_t)V.pix_base;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (!L.inside[p]) continue;
+    const int64_t pix = (int64_t)L.py[p] * V.width + L.px[p];
+    rgb[pix] = fmaf(T[p], V.bg[0], C0[p]);
+    rgb[hw + pix] = fmaf(T[p], V.bg[1], C1[p]);
+    rgb[2 * hw + pix] = fmaf(T[p], V.bg[2], C2[p]);
     const int64_t gp = (int64_t)V.pix_base + pix;
-    if (a.out_T) a.out_T[gp] = T;
-    a.px_T[gp] = T;
-    a.px_last[gp] = last;
-    if (a.px_evals) a.px_evals[gp] = min(evals, 65535u) | (min(contrib, 65535u) << 16);
+    if (a.out_T) a.out_T[gp] = T[p];
+    a.px_T[gp] = T[p];
+    a.px_last[gp] = last[p];
+    if (a.px_evals) a.px_evals[gp] = min(evals[p], 65535u) | (min(contrib[p], 65535u) << 16);
   }
 }
 
-template <int TILE, int BATCH>
+// Transpose-reduce of nine per-lane values over the wave.  v_permlane32_swap exchanges the
+// upper 32 lanes of one register with the lower 32 lanes of another, so one swap and one add
+// fold two values at once (value a over lanes 0-31, value b over lanes 32-63); a
+// v_permlane16_swap folds two such registers into four values, one per 16-lane row; four DPP
+// adds then sum each row.  Afterwards lane 16 r + i holds, for i = 0, 1 (and i = 2 in row 0),
+// the total of value field(i, r) = 4 i + [0, 2, 1, 3][r].
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_sum(float x) {
+  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp<0x141>(x);  // row_half_mirror
+  x += dpp<0x140>(x);  // row_mirror
+  return x;
+}
+
+// Returns the lane's reduced value and sets `field` (0..8) for the lanes that hold one.
+__device__ __forceinline__ float wave_reduce9(const float* q, int lane, int& field) {
+  const float A = fold32(q[0], q[1]), B = fold32(q[2], q[3]);
+  const float C = fold32(q[4], q[5]), D = fold32(q[6], q[7]);
+  const float E = fold32(q[8], 0.f);
+  const float F = row_sum(fold16(A, B));   // rows: q0, q2, q1, q3
+  const float G = row_sum(fold16(C, D));   // rows: q4, q6, q5, q7
+  const float H = row_sum(fold16(E, 0.f)); // row 0: q8
+  const int r = lane >> 4, i = lane & 15;
+  field = (i < 2 || (i == 2 && r == 0)) ? 4 * i + (((r & 1) << 1) | (r >> 1)) : -1;
+  return i == 0 ? F : (i == 1 ? G : H);
+}
+
+template <int TILE, int BATCH, int PXX, int PXY>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
+  constexpr int P = PXX * PXY;
   __shared__ Staged stage[4][BATCH];
   WaveTile t;
-  if (!wave_tile<TILE>(a, t)) return;
+  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
   const DSettings& S = a.S;
-  float T = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  int last = -1;
-  if (t.inside) {
-    const int64_t hw = (int64_t)V.width * V.height;
-    const int64_t pix = (int64_t)t.py * V.width + t.px;
-    const int64_t gp = (int64_t)V.pix_base + pix;
-    T = a.px_T[gp];
-    last = a.px_last[gp];
-    const float* dl = a.dL + 3 * (int64_t)V.pix_base;
-    g0 = dl[pix];
-    g1 = dl[hw + pix];
-    g2 = dl[2 * hw + pix];
+  LanePixels<PXX, PXY> L;
+  L.init(t, V);
+  float T[P], g0[P], g1[P], g2[P], R0[P], R1[P], R2[P], pxc[P], pyc[P];
+  int last[P];
+  int lane_last = -1;
+  const int64_t hw = (int64_t)V.width * V.height;
+  const float* dl = a.dL + 3 * (int64_t)V.pix_base;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T[p] = 1.f;
+    g0[p] = g1[p] = g2[p] = 0.f;
+    last[p] = -1;
+    R0[p] = V.bg[0];
+    R1[p] = V.bg[1];
+    R2[p] = V.bg[2];
+    pxc[p] = (float)L.px[p] + 0.5f;
+    pyc[p] = (float)L.py[p] + 0.5f;
+    if (L.inside[p]) {
+      const int64_t pix = (int64_t)L.py[p] * V.width + L.px[p];
+      const int64_t gp = (int64_t)V.pix_base + pix;
+      T[p] = a.px_T[gp];
+      last[p] = a.px_last[gp];
+      g0[p] = dl[pix];
+      g1[p] = dl[hw + pix];
+      g2[p] = dl[2 * hw + pix];
+    }
+    lane_last = max(lane_last, last[p]);
   }
-  const int hi_last = wave_max(last);
+  const int hi_last = wave_max(lane_last);
   if (hi_last < 0) return;
-  float R0 = V.bg[0], R1 = V.bg[1], R2 = V.bg[2];
   Staged* st = stage[t.w];
   const int lo_list = (int)t.range.x;
   for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
@@ -253,51 +340,51 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
       const int jk = __float_as_int(e2.y);
+      const float hb = 0.5f * e0.w;  // conic b
       float q[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
-      if (jk <= last) {
-        const float dx = t.pxc - e0.x, dy = t.pyc - e0.y;
-        const float d2 = mahalanobis(dx, dy, e0, e1.x);
-        if (d2 <= S.cut2) {
-          const float G = exp2f(d2 * kNegHalfLog2e);
-          const float araw = e1.y * G;
-          const float alpha = fminf(S.alpha_max, araw);
-          if (alpha >= S.alpha_min) {
-            contrib = true;
-            const float Tb = __fdividef(T, 1.f - alpha);
-            const float wgt = alpha * Tb;
-            q[6] = g0 * wgt;
-            q[7] = g1 * wgt;
-            q[8] = g2 * wgt;
-            const float d0 = e1.z - R0, d1 = e1.w - R1, dd2 = e2.x - R2;
-            const float da = Tb * fmaf(g0, d0, fmaf(g1, d1, g2 * dd2));
-            R0 = fmaf(alpha, d0, R0);
-            R1 = fmaf(alpha, d1, R1);
-            R2 = fmaf(alpha, dd2, R2);
-            if (araw < S.alpha_max) {
-              const float hb = 0.5f * e0.w;  // conic b
-              q[5] = da * G;
-              const float sa = da * alpha;
-              q[0] = sa * fmaf(e0.z, dx, hb * dy);
-              q[1] = sa * fmaf(hb, dx, e1.x * dy);
-              q[2] = -0.5f * sa * dx * dx;
-              q[3] = -sa * dx * dy;
-              q[4] = -0.5f * sa * dy * dy;
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (jk <= last[p]) {
+          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+          const float d2 = mahalanobis(dx, dy, e0, e1.x);
+          if (d2 <= S.cut2) {
+            const float G = exp2f(d2 * kNegHalfLog2e);
+            const float araw = e1.y * G;
+            const float alpha = fminf(S.alpha_max, araw);
+            if (alpha >= S.alpha_min) {
+              any = true;
+              const float Tb = __fdividef(T[p], 1.f - alpha);
+              const float wgt = alpha * Tb;
+              q[6] = fmaf(g0[p], wgt, q[6]);
+              q[7] = fmaf(g1[p], wgt, q[7]);
+              q[8] = fmaf(g2[p], wgt, q[8]);
+              const float d0 = e1.z - R0[p], d1 = e1.w - R1[p], dd2 = e2.x - R2[p];
+              const float da = Tb * fmaf(g0[p], d0, fmaf(g1[p], d1, g2[p] * dd2));
+              R0[p] = fmaf(alpha, d0, R0[p]);
+              R1[p] = fmaf(alpha, d1, R1[p]);
+              R2[p] = fmaf(alpha, dd2, R2[p]);
+              if (araw < S.alpha_max) {
+                q[5] = fmaf(da, G, q[5]);
+                const float sa = da * alpha;
+                const float sdx = sa * dx, sdy = sa * dy;
+                q[0] = fmaf(e0.z, sdx, fmaf(hb, sdy, q[0]));
+                q[1] = fmaf(hb, sdx, fmaf(e1.x, sdy, q[1]));
+                q[2] = fmaf(-0.5f * sdx, dx, q[2]);
+                q[3] = fmaf(-sdx, dy, q[3]);
+                q[4] = fmaf(-0.5f * sdy, dy, q[4]);
+              }
+              T[p] = Tb;
             }
-            T = Tb;
           }
         }
       }
-      if (__ballot(contrib) != 0ull) {
-        float sum[9];
-#pragma unroll
-        for (int f = 0; f < 9; ++f) sum[f] = wave_sum(q[f]);
-        float val = 0.f;
-#pragma unroll
-        for (int f = 0; f < 9; ++f) val = (t.lane == f) ? sum[f] : val;
-        if (t.lane < 9) {
+      if (__ballot(any) != 0ull) {
+        int field;
+        const float val = wave_reduce9(q, t.lane, field);
+        if (field >= 0) {
           const uint32_t slot = __float_as_uint(e2.z);
-          unsafeAtomicAdd(a.grad2d + (size_t)slot * kGrad2d + t.lane, val);
+          unsafeAtomicAdd(a.grad2d + (size_t)slot * kGrad2d + field, val);
         }
       }
     }
@@ -305,9 +392,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   }
 }
 
-template <int TILE, int BATCH>
+template <int TILE, int BATCH, int PXX, int PXY>
 void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
-  constexpr int QPT = (TILE / 8) * (TILE / 8);
+  constexpr int QPT = (TILE / (8 * PXX)) * (TILE / (8 * PXY));
   const int64_t waves = (int64_t)a.n_tiles * QPT;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks == 0) return;
@@ -315,25 +402,34 @@ void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
   b.blocks_per_xcd = (int)((blocks + 7) / 8);
   const unsigned grid = 8u * (unsigned)b.blocks_per_xcd;
   if (backward)
-    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH>), dim3(grid), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY>), dim3(grid), dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH>), dim3(grid), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY>), dim3(grid), dim3(256), 0, st, b);
+}
+
+template <int TILE, int PXX, int PXY>
+void dispatch_batch(const RasterArgs& a, hipStream_t st, bool backward) {
+  switch (a.S.lds_batch) {
+    case 32: launch_raster<TILE, 32, PXX, PXY>(a, st, backward); break;
+    case 128: launch_raster<TILE, 128, PXX, PXY>(a, st, backward); break;
+    default: launch_raster<TILE, 64, PXX, PXY>(a, st, backward); break;
+  }
 }
 
 template <int TILE>
-void dispatch_batch(const RasterArgs& a, hipStream_t st, bool backward) {
-  switch (a.S.lds_batch) {
-    case 32: launch_raster<TILE, 32>(a, st, backward); break;
-    case 128: launch_raster<TILE, 128>(a, st, backward); break;
-    default: launch_raster<TILE, 64>(a, st, backward); break;
+void dispatch_px(const RasterArgs& a, hipStream_t st, bool backward) {
+  switch (a.S.px_per_lane) {
+    case 2: dispatch_batch<TILE, 2, 1>(a, st, backward); break;
+    case 4: dispatch_batch<TILE, 2, 2>(a, st, backward); break;
+    default: dispatch_batch<TILE, 1, 1>(a, st, backward); break;
   }
 }
 
 void dispatch(const RasterArgs& a, hipStream_t st, bool backward) {
   switch (a.S.tile) {
-    case 8: dispatch_batch<8>(a, st, backward); break;
-    case 32: dispatch_batch<32>(a, st, backward); break;
-    default: dispatch_batch<16>(a, st, backward); break;
+    case 8: dispatch_batch<8, 1, 1>(a, st, backward); break;
+    case 32: dispatch_px<32>(a, st, backward); break;
+    default: dispatch_px<16>(a, st, backward); break;
   }
 }
 

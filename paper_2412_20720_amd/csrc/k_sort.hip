@@ -274,68 +274,110 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 }
 
 // ------------------------------------------------------------------------------------------
-// Key generation: each wave takes 64 consecutive visible splats (in depth order) and writes
-// their (tile, slot) pairs cooperatively, one pair per lane per step, so that a splat that
-// covers thousands of tiles does not serialize one thread.
+// Key generation: each wave takes 64 consecutive visible splats (in depth order).  Their tile
+// rows (rows of each splat's tile box) are numbered consecutively; in rounds of 64 rows, each
+// lane finds its row's run of tile columns with tile_row_span (the same function the
+// preprocess counted with), a wave scan gives each run its place, and the lane writes its run.
+// So a splat that covers thousands of tiles is spread over many lanes, and the pairs come out
+// in depth order, each splat's tiles in row-major order.
 // ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
+  const uint32_t inc = wave_incl_scan(x);
+  total = __shfl(inc, 63, 64);
+  return inc - x;
+}
+
 __global__ __launch_bounds__(kThreads) void k_keygen(
     const float* __restrict__ rec, const uint32_t* __restrict__ vval,
     const uint32_t* __restrict__ voff, const uint32_t* n_vis_dev, const uint32_t* n_pairs_dev,
     int64_t pair_cap, int n_per_view, const DView* __restrict__ views, DSettings S,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* overflow) {
-  __shared__ uint32_t s_start[4][65];
-  __shared__ int32_t s_x0[4][64], s_y0[4][64], s_w[4][64], s_tx[4][64], s_tb[4][64];
+  __shared__ uint32_t s_rows[4][65];
+  __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64];
+  __shared__ float s_ex[4][64], s_ey[4][64];
+  __shared__ int32_t s_x0[4][64], s_x1[4][64], s_y0[4][64], s_tx[4][64], s_tb[4][64];
+  __shared__ int32_t s_w[4][64], s_h[4][64];
   __shared__ uint32_t s_slot[4][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n_vis = *n_vis_dev;
   const int64_t first = ((int64_t)blockIdx.x * 4 + w) * 64;
   if (first >= n_vis) return;
   const int64_t r = first + lane;
-  const bool valid = r < n_vis;
   const int64_t last = (n_vis - first < 64 ? n_vis : first + 64) - 1;
   const uint32_t off0 = voff[first];
   const uint32_t off_end = (last + 1 < n_vis) ? voff[last + 1] : *n_pairs_dev;
-  const uint32_t total = off_end - off0;
-  if (valid) {
+  uint32_t rows = 0;
+  if (r < n_vis) {
     const uint32_t slot = vval[r];
-    const int v = (int)(slot / (uint32_t)n_per_view);
-    const DView& V = views[v];
+    const DView& V = views[(int)(slot / (uint32_t)n_per_view)];
     const float* p = rec + (size_t)slot * kRec;
     int x0, x1, y0, y1;
-    tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], V, S.tile_shift, x0, x1, y0, y1);
-    s_start[w][lane] = voff[r] - off0;
+    if (tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], V, S.tile_shift, x0, x1, y0, y1))
+      rows = (uint32_t)(y1 - y0 + 1);
+    s_u[w][lane] = p[R_U];
+    s_v[w][lane] = p[R_V];
+    s_a[w][lane] = p[R_A];
+    s_b[w][lane] = p[R_B];
+    s_c[w][lane] = p[R_C];
+    s_ex[w][lane] = p[R_EX];
+    s_ey[w][lane] = p[R_EY];
     s_x0[w][lane] = x0;
+    s_x1[w][lane] = x1;
     s_y0[w][lane] = y0;
-    s_w[w][lane] = x1 - x0 + 1;
     s_tx[w][lane] = V.tiles_x;
     s_tb[w][lane] = V.tile_base;
+    s_w[w][lane] = V.width;
+    s_h[w][lane] = V.height;
     s_slot[w][lane] = slot;
-  } else {
-    s_start[w][lane] = total;
   }
-  if (lane == 0) s_start[w][64] = total;
+  uint32_t n_rows;
+  const uint32_t row0 = wave_excl_scan(rows, n_rows);
+  s_rows[w][lane] = (r < n_vis) ? row0 : n_rows;
+  if (lane == 0) s_rows[w][64] = n_rows;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (uint32_t k = lane; k < total; k += 64) {
-    // largest j with s_start[j] <= k
-    int lo = 0, hi = 63;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_start[w][mid] <= k) lo = mid; else hi = mid - 1;
+  const float lim = coverage_limit(S);
+  uint32_t cursor = off0;
+  for (uint32_t k0 = 0; k0 < n_rows; k0 += 64) {
+    const uint32_t k = k0 + lane;
+    uint32_t cnt = 0;
+    int i = 0, ty = 0, c0 = 0;
+    if (k < n_rows) {
+      int lo = 0, hi = 63;  // largest i with s_rows[i] <= k
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rows[w][mid] <= k) lo = mid; else hi = mid - 1;
+      }
+      i = lo;
+      ty = s_y0[w][i] + (int)(k - s_rows[w][i]);
+      const int span = tile_row_span(s_u[w][i], s_v[w][i], s_a[w][i], s_b[w][i], s_c[w][i], lim,
+                                     s_ex[w][i], s_ey[w][i], ty, S.tile_shift, s_w[w][i],
+                                     s_h[w][i], s_x0[w][i], s_x1[w][i]);
+      if (span >= 0) {
+        c0 = span >> 16;
+        cnt = (uint32_t)((span & 0xFFFF) - c0 + 1);
+      }
     }
-    const uint32_t rel = k - s_start[w][lo];
-    const int ww = s_w[w][lo];
-    const int ty = s_y0[w][lo] + (int)(rel / (uint32_t)ww);
-    const int tx = s_x0[w][lo] + (int)(rel % (uint32_t)ww);
-    const int64_t dst = (int64_t)off0 + k;
-    if (dst < pair_cap) {
-      pkey[dst] = (uint32_t)(s_tb[w][lo] + ty * s_tx[w][lo] + tx);
-      pval[dst] = s_slot[w][lo];
-    } else {
-      *overflow = 1u;
+    uint32_t total;
+    const uint32_t pos = cursor + wave_excl_scan(cnt, total);
+    if (cnt > 0) {
+      const uint32_t key0 = (uint32_t)(s_tb[w][i] + ty * s_tx[w][i] + c0);
+      const uint32_t slot = s_slot[w][i];
+      for (uint32_t m = 0; m < cnt; ++m) {
+        const uint32_t dst = pos + m;
+        if (dst < off_end && (int64_t)dst < pair_cap) {
+          pkey[dst] = key0 + m;
+          pval[dst] = slot;
+        } else {
+          *overflow = 1u;
+        }
+      }
     }
+    cursor += total;
   }
+  // The preprocess counted exactly these pairs; a difference would leave holes.
+  if (lane == 0 && cursor != off_end) *overflow = 2u;
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev, int64_t cap,
@@ -351,6 +393,10 @@ __global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+__global__ void k_clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out) {
+  if (threadIdx.x == 0) *out = min(*n, cap);
 }
 
 __global__ void k_view_setup(DView* views, int n_views, float m) {
@@ -435,6 +481,10 @@ void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs, pair_cap,
                      ranges);
+}
+
+void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, st, n, cap, out);
 }
 
 void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st) {

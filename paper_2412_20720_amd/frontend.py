@@ -82,6 +82,18 @@ class Renderer:
         B.check(B.lib().g4d_render_backward(self._ctx, C.byref(g), va, len(va), C.byref(settings),
                                             dL.data_ptr(), C.byref(gr), st), self._ctx)
 
+    def step(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
+             out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
+             grads: Dict[str, torch.Tensor], graph: bool = True) -> None:
+        """Forward + backward in one call; with graph=True a captured hipGraph is replayed."""
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        gr = B.g4d_grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+        B.check(B.lib().g4d_render_step(self._ctx, C.byref(g), va, len(va), C.byref(settings),
+                                        dL.data_ptr(), out_rgb.data_ptr(),
+                                        None if out_T is None else out_T.data_ptr(), C.byref(gr),
+                                        B.G4D_STEP_GRAPH if graph else 0,
+                                        _stream_handle(self.device)), self._ctx)
+
     def preprocess(self, g: B.g4d_gaussians, views, settings: B.g4d_settings):
         va = views if isinstance(views, C.Array) else B.make_views(views)
         rec = torch.empty((len(va), g.n, B.G4D_RECORD_FLOATS), device=self.device)
@@ -109,6 +121,21 @@ class Renderer:
                                           _stream_handle(self.device)), self._ctx)
         return out
 
+
+    def autotune(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
+                 out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
+                 grads: Dict[str, torch.Tensor], reps: int = 2) -> float:
+        """Pick tile size, LDS batch and pixels per lane in place in ``settings``; returns the
+        chosen forward + backward time in ms."""
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        gr = B.g4d_grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
+        ms = C.c_double()
+        B.check(B.lib().g4d_autotune(self._ctx, C.byref(g), va, len(va), C.byref(settings),
+                                     dL.data_ptr(), out_rgb.data_ptr(),
+                                     None if out_T is None else out_T.data_ptr(), C.byref(gr),
+                                     int(reps), C.byref(ms), _stream_handle(self.device)),
+                self._ctx)
+        return ms.value
 
     def profile(self, enable: bool, collect: bool = True, reset: bool = True):
         """Stage timing (HIP events on the call's stream): returns {stage: (ms, launches)}."""
