@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=1)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -113,6 +116,30 @@ def main():
     for k, v in stage_ms.items():
         log(f"  {k:15s} {v:8.3f} ms/launch")
 
+    graph = None
+    if not args.no_graph:
+        # The same step captured once into a hipGraph and replayed (no host sync per step).
+        for _ in range(args.warmup):
+            r.step(g, views, settings, dL, rgb, T, grads, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r.step(g, views, settings, dL, rgb, T, grads, graph=True)
+        torch.cuda.synchronize()
+        dg = (time.perf_counter() - t0) / args.steps
+        r.sync()
+        graph = dict(value=npix / dg / 1e6, ms_per_step=dg * 1e3)
+        log(f"bench: graph replay {dg * 1e3:.3f} ms/step, {npix / dg / 1e6:.1f} Mpix/s")
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration {args.copy_calibration} MiB read + written")
+
     per_view = None
     if not args.no_per_view:
         single = [B.make_views([v]) for v in sc.views]
@@ -159,6 +186,7 @@ def main():
                    "tile": settings.tile_size, "lds_batch": settings.lds_batch,
                    "px_per_lane": settings.px_per_lane, "autotuned": args.tile == 0},
         "per_view": per_view,
+        "graph": graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],

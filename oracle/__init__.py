@@ -14,8 +14,11 @@ from typing import Dict, Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.cpp")
+# G4D_ORACLE_LIB points the binding at another build of oracle.cpp (the mutation test uses it
+# to load copies with planted mistakes).
+LIB_OVERRIDE = os.environ.get("G4D_ORACLE_LIB")
+LIB_PATH = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 # Renderer settings (readings of the paper where it is silent; see the oracle header) and the
 # parity margins within which a discrete decision is marked as legitimately ambiguous between
@@ -83,7 +86,8 @@ _lib: Optional[C.CDLL] = None
 def lib() -> C.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        if not LIB_OVERRIDE and (not os.path.exists(LIB_PATH) or
+                                 os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)):
             build()
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)

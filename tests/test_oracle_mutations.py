@@ -1,0 +1,61 @@
+"""The pins catch plausible mistakes: each case plants one slip in a copy of the oracle source
+(on the CPU), builds it, and runs the pin tests against it in a subprocess; at least one pin
+must fail.  This checks the pins, not the GPU library."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
+PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+        os.path.join(ROOT, "tests", "test_oracle_gradients.py")]
+
+# (name, exact text in oracle.cpp, replacement)
+MUTATIONS = [
+    ("left rotor sign", "L[1][2] = -d;", "L[1][2] = d;"),
+    ("right rotor sign", "R[1][2] = s;", "R[1][2] = -s;"),
+    ("rotor not normalized", "out[i] = q[i] / n;", "out[i] = q[i];"),
+    ("slice mean sign", "mu_c[i] = mean4[i] + Sig[i][3]", "mu_c[i] = mean4[i] - Sig[i][3]"),
+    ("slice covariance term dropped",
+     "cov_c[i][j] = Sig[i][j] - Sig[i][3] * Sig[3][j] / Sig[3][3];", "cov_c[i][j] = Sig[i][j];"),
+    ("marginal variance squared", "p_t = exp(-0.5 * dt * dt / Sig[3][3]);",
+     "p_t = exp(-0.5 * dt * dt / (Sig[3][3] * Sig[3][3]));"),
+    ("Jacobian sign", "J[0][2] = -vw.fx * tx / x[2];", "J[0][2] = vw.fx * tx / x[2];"),
+    ("J W transposed",
+     "T[i][j] = J[i][0] * E[0 * 4 + j] + J[i][1] * E[1 * 4 + j] + J[i][2] * E[2 * 4 + j];",
+     "T[i][j] = J[i][0] * E[j * 4 + 0] + J[i][1] * E[j * 4 + 1] + J[i][2] * E[j * 4 + 2];"),
+    ("blur dropped", "sp.cov2d[0] = C2[0][0] + st.blur;", "sp.cov2d[0] = C2[0][0];"),
+    ("principal point swapped", "sp.u = vw.fx * x[0] / x[2] + vw.cx;", "sp.u = vw.fx * x[0] / x[2] + vw.cy;"),
+    ("SH normalization", "std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI)", "std::sqrt((2.0 * l) / (4.0 * M_PI)"),
+    ("SH m<0 uses cosine", "y = std::sqrt(2.0) * K * P * sin((double)am * phi);",
+     "y = std::sqrt(2.0) * K * P * cos((double)am * phi);"),
+    ("Fourier period", "cos(2.0 * M_PI * (double)n * dts / st.time_period)",
+     "cos(M_PI * (double)n * dts / st.time_period)"),
+    ("color offset dropped", "S acc = S(st.color_offset);", "S acc = S(0.0);"),
+    ("transmittance dropped", "C[ch] += T * alpha * s.col[ch];", "C[ch] += alpha * s.col[ch];"),
+    ("no stop", "    if (stop) break;\n", "\n"),
+    ("back-to-front order", "if (a.depth != b.depth) return a.depth < b.depth;",
+     "if (a.depth != b.depth) return a.depth > b.depth;"),
+    ("background dropped", "res.rgb[ch] = C[ch] + T * f.vw.background[ch];", "res.rgb[ch] = C[ch];"),
+    ("backward color-behind recursion",
+     "R[ch] = ct.alpha * s.col[ch] + (1.0 - ct.alpha) * R[ch];", "R[ch] = s.col[ch];"),
+    ("backward conic term sign", "a[3] += dalpha * ct.alpha * (-dx * dy);",
+     "a[3] += dalpha * ct.alpha * (dx * dy);"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique or missing: {old!r}"
+    mutated = tmp_path / "oracle_mut.cpp"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", str(lib),
+                    str(mutated)], check=True)
+    env = dict(os.environ, G4D_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin failed for planted mistake '{name}'"
