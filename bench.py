@@ -37,6 +37,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def raster_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_raster.hip", "g4d_device.h", "g4d_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2412_20720_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload_name, settings):
+    """HBM bytes per raster_bwd launch from the committed counter summary, if it was taken on
+    this workload and settings with the current raster source (else None)."""
+    path = os.path.join(ROOT, "profiles", "raster_bwd_w2_traffic.md")
+    if (workload_name != "w2_300k_16views_mixed" or not os.path.exists(path) or
+            (settings.tile_size, settings.lds_batch, settings.px_per_lane) != (32, 64, 4)):
+        return None
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and
+                  l.split(": ", 1)[0] in ("source-hash", "raster_bwd-traffic-bytes"))
+    if fields.get("source-hash") != raster_source_hash():
+        return None
+    return int(fields["raster_bwd-traffic-bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,8 +189,9 @@ def main():
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
     flops = (BWD_FLOPS_PER_PAIR * contrib) if dom == "raster_bwd" else (FWD_FLOPS_PER_PAIR * evals)
     achieved = flops / (stage_ms[dom] * 1e-3)
+    traffic = profiled_traffic(sc.name, settings) if dom == "raster_bwd" else None
     roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=None,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
                     units=contrib if dom == "raster_bwd" else evals,
                     flops_per_unit=BWD_FLOPS_PER_PAIR if dom == "raster_bwd" else FWD_FLOPS_PER_PAIR,
                     ms_per_launch=stage_ms[dom])

@@ -171,7 +171,11 @@ struct LanePixels {
   }
 };
 
-template <int TILE, int BATCH, int PXX, int PXY>
+// exp2 on the hardware instruction; its argument here is >= -6.5 log2(e) (d2 <= 9), far
+// from the range where the library version adds denormal handling.
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+template <int TILE, int BATCH, int PXX, int PXY, bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
   __shared__ Staged stage[4][BATCH];
@@ -184,8 +188,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   float T[P], C0[P], C1[P], C2[P], pxc[P], pyc[P];
   int last[P];
   uint32_t evals[P], contrib[P];
-  bool done[P];
-  bool live = false;
+  bool live[P];
+  bool any_live = false;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     T[p] = 1.f;
@@ -194,46 +198,45 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     pyc[p] = (float)L.py[p] + 0.5f;
     last[p] = -1;
     evals[p] = contrib[p] = 0;
-    done[p] = !L.inside[p];
-    live |= !done[p];
+    live[p] = L.inside[p];
+    any_live |= live[p];
   }
   Staged* st = stage[t.w];
   const int end = (int)t.range.y;
   for (int base = (int)t.range.x; base < end; base += BATCH) {
-    if (__ballot(live) == 0ull) break;
+    if (__ballot(any_live) == 0ull) break;
     const int n = stage_batch<BATCH>(a, t, base, end, st);
     G4D_WAVE_SYNC();
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
-      live = false;
+      any_live = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        if (!done[p]) {
-          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-          const float d2 = mahalanobis(dx, dy, e0, e1.x);
-          if (d2 <= S.cut2) {
-            ++evals[p];
-            const float alpha = fminf(S.alpha_max, e1.y * exp2f(d2 * kNegHalfLog2e));
-            if (alpha >= S.alpha_min) {
-              const float Tn = T[p] * (1.f - alpha);
-              if (Tn < S.T_min) {
-                done[p] = true;
-              } else {
-                const float wgt = T[p] * alpha;
-                C0[p] = fmaf(wgt, e1.z, C0[p]);
-                C1[p] = fmaf(wgt, e1.w, C1[p]);
-                C2[p] = fmaf(wgt, e2.x, C2[p]);
-                T[p] = Tn;
-                last[p] = __float_as_int(e2.y);
-                ++contrib[p];
-              }
-            }
+        const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+        const float d2 = mahalanobis(dx, dy, e0, e1.x);
+        const bool in = live[p] && d2 <= S.cut2;
+        if (__ballot(in) != 0ull) {
+          const float alpha = fminf(S.alpha_max, e1.y * fast_exp2(d2 * kNegHalfLog2e));
+          const bool ok = in && alpha >= S.alpha_min;
+          const float Tn = T[p] * (1.f - alpha);
+          const bool stop = ok && Tn < S.T_min;
+          const bool take = ok && !stop;
+          const float wgt = take ? T[p] * alpha : 0.f;
+          C0[p] = fmaf(wgt, e1.z, C0[p]);
+          C1[p] = fmaf(wgt, e1.w, C1[p]);
+          C2[p] = fmaf(wgt, e2.x, C2[p]);
+          T[p] = take ? Tn : T[p];
+          last[p] = take ? __float_as_int(e2.y) : last[p];
+          live[p] = live[p] && !stop;
+          if (COUNT) {
+            evals[p] += in ? 1u : 0u;
+            contrib[p] += take ? 1u : 0u;
           }
         }
-        live |= !done[p];
+        any_live |= live[p];
       }
-      if (__ballot(live) == 0ull) break;
+      if (__ballot(any_live) == 0ull) break;
     }
     G4D_WAVE_SYNC();
   }
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     if (a.out_T) a.out_T[gp] = T[p];
     a.px_T[gp] = T[p];
     a.px_last[gp] = last[p];
-    if (a.px_evals) a.px_evals[gp] = min(evals[p], 65535u) | (min(contrib[p], 65535u) << 16);
+    if (COUNT) a.px_evals[gp] = min(evals[p], 65535u) | (min(contrib[p], 65535u) << 16);
   }
 }
 
@@ -293,6 +296,12 @@ __device__ __forceinline__ float wave_reduce9(const float* q, int lane, int& fie
   return i == 0 ? F : (i == 1 ? G : H);
 }
 
+// Backward.  Per pixel the walk keeps T (transmittance in front of the entry, rebuilt by
+// division) and gR = g . R (the upstream gradient dotted with the color behind the entry):
+//   dL/dalpha = T_i (g . c_i - gR),  gR <- alpha (g . c_i) + (1 - alpha) gR.
+// Per Gaussian the wave accumulates q = [dL/du, dL/dv, S_xx, S_xy, S_yy, dL/d(opacity p_t),
+// dL/drgb] with S_.. the second moments of (dx, dy) weighted by dL/dalpha alpha; after the
+// reduction they become dL/da = -S_xx / 2, dL/db = -S_xy, dL/dc = -S_yy / 2.
 template <int TILE, int BATCH, int PXX, int PXY>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
@@ -303,7 +312,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   const DSettings& S = a.S;
   LanePixels<PXX, PXY> L;
   L.init(t, V);
-  float T[P], g0[P], g1[P], g2[P], R0[P], R1[P], R2[P], pxc[P], pyc[P];
+  float T[P], g0[P], g1[P], g2[P], gR[P], pxc[P], pyc[P];
   int last[P];
   int lane_last = -1;
   const int64_t hw = (int64_t)V.width * V.height;
@@ -313,9 +322,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     T[p] = 1.f;
     g0[p] = g1[p] = g2[p] = 0.f;
     last[p] = -1;
-    R0[p] = V.bg[0];
-    R1[p] = V.bg[1];
-    R2[p] = V.bg[2];
     pxc[p] = (float)L.px[p] + 0.5f;
     pyc[p] = (float)L.py[p] + 0.5f;
     if (L.inside[p]) {
@@ -327,6 +333,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
       g1[p] = dl[hw + pix];
       g2[p] = dl[2 * hw + pix];
     }
+    gR[p] = fmaf(g0[p], V.bg[0], fmaf(g1[p], V.bg[1], g2[p] * V.bg[2]));
     lane_last = max(lane_last, last[p]);
   }
   const int hi_last = wave_max(lane_last);
@@ -345,44 +352,41 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
       bool any = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        if (jk <= last[p]) {
-          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-          const float d2 = mahalanobis(dx, dy, e0, e1.x);
-          if (d2 <= S.cut2) {
-            const float G = exp2f(d2 * kNegHalfLog2e);
-            const float araw = e1.y * G;
-            const float alpha = fminf(S.alpha_max, araw);
-            if (alpha >= S.alpha_min) {
-              any = true;
-              const float Tb = __fdividef(T[p], 1.f - alpha);
-              const float wgt = alpha * Tb;
-              q[6] = fmaf(g0[p], wgt, q[6]);
-              q[7] = fmaf(g1[p], wgt, q[7]);
-              q[8] = fmaf(g2[p], wgt, q[8]);
-              const float d0 = e1.z - R0[p], d1 = e1.w - R1[p], dd2 = e2.x - R2[p];
-              const float da = Tb * fmaf(g0[p], d0, fmaf(g1[p], d1, g2[p] * dd2));
-              R0[p] = fmaf(alpha, d0, R0[p]);
-              R1[p] = fmaf(alpha, d1, R1[p]);
-              R2[p] = fmaf(alpha, dd2, R2[p]);
-              if (araw < S.alpha_max) {
-                q[5] = fmaf(da, G, q[5]);
-                const float sa = da * alpha;
-                const float sdx = sa * dx, sdy = sa * dy;
-                q[0] = fmaf(e0.z, sdx, fmaf(hb, sdy, q[0]));
-                q[1] = fmaf(hb, sdx, fmaf(e1.x, sdy, q[1]));
-                q[2] = fmaf(-0.5f * sdx, dx, q[2]);
-                q[3] = fmaf(-sdx, dy, q[3]);
-                q[4] = fmaf(-0.5f * sdy, dy, q[4]);
-              }
-              T[p] = Tb;
-            }
-          }
+        const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+        const float d2 = mahalanobis(dx, dy, e0, e1.x);
+        const bool in = jk <= last[p] && d2 <= S.cut2;
+        if (__ballot(in) != 0ull) {
+          const float G = fast_exp2(d2 * kNegHalfLog2e);
+          const float araw = e1.y * G;
+          const float alpha = fminf(S.alpha_max, araw);
+          const bool take = in && alpha >= S.alpha_min;
+          const float Tb = __fdividef(T[p], 1.f - alpha);
+          const float wgt = take ? alpha * Tb : 0.f;
+          q[6] = fmaf(g0[p], wgt, q[6]);
+          q[7] = fmaf(g1[p], wgt, q[7]);
+          q[8] = fmaf(g2[p], wgt, q[8]);
+          const float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
+          const float diff = gc - gR[p];
+          const float da = Tb * diff;
+          gR[p] = take ? fmaf(alpha, diff, gR[p]) : gR[p];
+          T[p] = take ? Tb : T[p];
+          const bool geo = take && araw < S.alpha_max;
+          q[5] = fmaf(geo ? da : 0.f, G, q[5]);
+          const float sa = geo ? da * alpha : 0.f;
+          const float sdx = sa * dx, sdy = sa * dy;
+          q[0] = fmaf(e0.z, sdx, fmaf(hb, sdy, q[0]));
+          q[1] = fmaf(hb, sdx, fmaf(e1.x, sdy, q[1]));
+          q[2] = fmaf(sdx, dx, q[2]);
+          q[3] = fmaf(sdx, dy, q[3]);
+          q[4] = fmaf(sdy, dy, q[4]);
+          any |= take;
         }
       }
       if (__ballot(any) != 0ull) {
         int field;
-        const float val = wave_reduce9(q, t.lane, field);
+        float val = wave_reduce9(q, t.lane, field);
         if (field >= 0) {
+          val *= (field == 3) ? -1.f : ((field == 2 || field == 4) ? -0.5f : 1.f);
           const uint32_t slot = __float_as_uint(e2.z);
           unsafeAtomicAdd(a.grad2d + (size_t)slot * kGrad2d + field, val);
         }
@@ -403,8 +407,10 @@ void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
   const unsigned grid = 8u * (unsigned)b.blocks_per_xcd;
   if (backward)
     hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY>), dim3(grid), dim3(256), 0, st, b);
+  else if (b.px_evals)
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, true>), dim3(grid), dim3(256), 0, st, b);
   else
-    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY>), dim3(grid), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, false>), dim3(grid), dim3(256), 0, st, b);
 }
 
 template <int TILE, int PXX, int PXY>
