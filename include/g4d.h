@@ -15,7 +15,9 @@
  *     the library beyond the call except inside the context.
  *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default stream).
  *   - Errors are returned as g4d_status; no exception crosses the ABI.  The message of the last
- *     error is g4d_last_error(ctx).  One context must not be used by two threads at once.
+ *     error is g4d_last_error(ctx).  One context must not be used by two threads at once, and
+ *     its calls should stay on one stream (the context keeps device state between calls, for
+ *     instance the view table, and reuses it in stream order).
  */
 #ifndef G4D_H
 #define G4D_H

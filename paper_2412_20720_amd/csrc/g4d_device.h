@@ -322,21 +322,30 @@ __device__ __forceinline__ void cutoff_extent(const ViewFwd& f, const DSettings&
   ey = S.cutoff * sqrtf(f.cov[2]) * 1.0005f;
 }
 
-// Tiles whose pixel centres can lie inside [u - ex, u + ex] x [v - ey, v + ey]; false if none.
-__device__ __forceinline__ bool tile_rect(float u, float v, float ex, float ey, const DView& V,
-                                          int shift, int& x0, int& x1, int& y0, int& y1) {
+// Tiles whose pixel centres can lie inside [u - ex, u + ex] x [v - ey, v + ey]:
+// (x0, x1, y0, y1), or x0 = -1 if none.  Not inlined: the preprocess (counting) and the key
+// generation (writing) must see exactly the rounded u, v, ex, ey, never a product fused into
+// the subtraction.
+__device__ __noinline__ int4 tile_rect_of(float u, float v, float ex, float ey, int width,
+                                          int height, int shift) {
   float fx0 = ceilf(u - ex - 0.5f), fx1 = floorf(u + ex - 0.5f);
   float fy0 = ceilf(v - ey - 0.5f), fy1 = floorf(v + ey - 0.5f);
   fx0 = fmaxf(fx0, 0.f);
   fy0 = fmaxf(fy0, 0.f);
-  fx1 = fminf(fx1, (float)(V.width - 1));
-  fy1 = fminf(fy1, (float)(V.height - 1));
-  if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
-  x0 = (int)fx0 >> shift;
-  x1 = (int)fx1 >> shift;
-  y0 = (int)fy0 >> shift;
-  y1 = (int)fy1 >> shift;
-  return true;
+  fx1 = fminf(fx1, (float)(width - 1));
+  fy1 = fminf(fy1, (float)(height - 1));
+  if (!(fx0 <= fx1) || !(fy0 <= fy1)) return make_int4(-1, -1, -1, -1);
+  return make_int4((int)fx0 >> shift, (int)fx1 >> shift, (int)fy0 >> shift, (int)fy1 >> shift);
+}
+
+__device__ __forceinline__ bool tile_rect(float u, float v, float ex, float ey, const DView& V,
+                                          int shift, int& x0, int& x1, int& y0, int& y1) {
+  const int4 r = tile_rect_of(u, v, ex, ey, V.width, V.height, shift);
+  x0 = r.x;
+  x1 = r.y;
+  y0 = r.z;
+  y1 = r.w;
+  return r.x >= 0;
 }
 
 // x-range [xl, xr] (relative to the splat centre) of the ellipse a dx^2 + 2 b dx dy + c dy^2

@@ -34,13 +34,15 @@ size_t radix_scratch_bytes(int64_t n_cap);
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
                int bits, void* scratch, hipStream_t st);
 
-// One (tile id, slot) pair per covered tile, records visited in depth order.
+// One (tile id, slot) pair per covered tile, records visited in depth order.  Tile ids are
+// below n_tiles; n_tiles itself marks filler pairs (never drawn).
 void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
             int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval, uint32_t* overflow,
-            hipStream_t st);
+            int n_tiles, const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval,
+            uint32_t* overflow, hipStream_t st);
 
-// ranges[tile] = [first, last+1) of the tile's pairs in the sorted key array.
+// ranges[tile] = [first, last+1) of the tile's pairs in the sorted key array (keys >= n_tiles
+// are skipped).
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
                  int64_t n_tiles, uint2* ranges, hipStream_t st);
 

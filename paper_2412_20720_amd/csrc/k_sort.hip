@@ -290,7 +290,7 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) 
 __global__ __launch_bounds__(kThreads) void k_keygen(
     const float* __restrict__ rec, const uint32_t* __restrict__ vval,
     const uint32_t* __restrict__ voff, const uint32_t* n_vis_dev, const uint32_t* n_pairs_dev,
-    int64_t pair_cap, int n_per_view, const DView* __restrict__ views, DSettings S,
+    int64_t pair_cap, int n_per_view, int n_tiles, const DView* __restrict__ views, DSettings S,
     uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* overflow) {
   __shared__ uint32_t s_rows[4][65];
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64];
@@ -376,16 +376,26 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
     }
     cursor += total;
   }
-  // The preprocess counted exactly these pairs; a difference would leave holes.
-  if (lane == 0 && cursor != off_end) *overflow = 2u;
+  // The preprocess counted exactly these pairs.  Should the two ever disagree, the shortfall
+  // is filled with the dummy tile id n_tiles (listed after every real tile, never drawn) so
+  // that no stale key survives, and the disagreement is reported.
+  if (cursor != off_end) {
+    if (lane == 0) *overflow = 2u;
+    for (uint32_t dst = cursor + lane; dst < off_end; dst += 64)
+      if ((int64_t)dst < pair_cap) {
+        pkey[dst] = (uint32_t)n_tiles;
+        pval[dst] = 0u;
+      }
+  }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev, int64_t cap,
-                         uint2* ranges) {
+                         int64_t n_tiles, uint2* ranges) {
   const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = key[i];
+  if ((int64_t)k >= n_tiles) return;  // dummy tile
   if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
   if (i == n - 1 || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
 }
@@ -465,13 +475,13 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_
 
 void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
             int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval, uint32_t* overflow,
-            hipStream_t st) {
+            int n_tiles, const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval,
+            uint32_t* overflow, hipStream_t st) {
   const int64_t waves = (n_vis_cap + 63) / 64;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_keygen, dim3((unsigned)blocks), dim3(kThreads), 0, st, rec, vval, voff, n_vis,
-                     n_pairs, pair_cap, n_slots_per_view, views, S, pkey, pval, overflow);
+                     n_pairs, pair_cap, n_slots_per_view, n_tiles, views, S, pkey, pval, overflow);
 }
 
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
@@ -480,7 +490,7 @@ void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap
   const int64_t blocks = (pair_cap + 255) / 256;
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs, pair_cap,
-                     ranges);
+                     n_tiles, ranges);
 }
 
 void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st) {

@@ -1,0 +1,97 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times (batched views,
+32-pixel tiles, 64-entry LDS batches, 4 pixels per lane): sampled pixels of batched renders of
+the 300k/16-view, 500k/32-view and 2M/8-view workloads against the oracle, the batched
+gradient against the oracle's backward, and batched launches against per-view launches."""
+import numpy as np
+import pytest
+
+from gpu_util import PARAMS, GpuRun, log, oracle_frame
+from oracle import parity
+from paper_2412_20720_amd import scenes
+
+pytestmark = pytest.mark.gpu
+BENCH_LAUNCH = dict(tile_size=32, lds_batch=64, px_per_lane=4)
+
+
+@pytest.fixture(scope="module")
+def renderer():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_20720_amd.frontend import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+@pytest.fixture(scope="module")
+def w2():
+    return scenes.make_workload(2)
+
+
+def sample_pixels(view, n, seed):
+    W, H = view["width"], view["height"]
+    rng = np.random.default_rng(seed)
+    xy = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], 1)
+    ys, xs = np.mgrid[(H // 32) * 32:H, (W // 32) * 32:min(W, (W // 32) * 32 + 32)]  # ragged tile
+    return np.concatenate([xy, np.stack([xs.ravel(), ys.ravel()], 1)])
+
+
+def check_views(sc, run, view_ids, n=2500):
+    imgs = run.images()
+    for v in view_ids:
+        xy = sample_pixels(sc.views[v], n, seed=v)
+        g = imgs[v][:, xy[:, 1], xy[:, 0]].T
+        with oracle_frame(sc, sc.views[v]) as fr:
+            rep = parity.check_image(g, fr, 1e-4, xy=xy)
+        log(f"{sc.name} view {v}: n={rep['n']} max_err={rep['max_err']:.2e} marked={rep['n_marked']} "
+            f"resolved={rep['n_resolved']} unverified={rep['n_unverified']} failures={rep['n_failures']} "
+            f"{rep['failures'][:3]}")
+        assert rep["n_failures"] == 0
+        assert rep["n_unverified"] <= 0.002 * rep["n"]
+
+
+def test_w2_batched_sampled_pixels(renderer, w2):
+    run = GpuRun(renderer, w2, **BENCH_LAUNCH).forward()
+    log(f"w2 stats {renderer.stats()}")
+    check_views(w2, run, [0, 1, 9])
+
+
+def test_w2_batched_gradients_two_views(renderer, w2):
+    # Upstream gradient nonzero on views 0 (1352x1014) and 1 (800x800) only: the batched
+    # backward must equal the oracle's backward summed over those two views.
+    rng = np.random.default_rng(21)
+    dls = [np.zeros((3, v["height"], v["width"]), np.float32) for v in w2.views]
+    for v in (0, 1):
+        dls[v] = rng.normal(size=dls[v].shape).astype(np.float32)
+    run = GpuRun(renderer, w2, **BENCH_LAUNCH).forward()
+    g = run.backward(dls)
+    ref = None
+    for v in (0, 1):
+        log(f"w2 oracle backward view {v}")
+        with oracle_frame(w2, w2.views[v]) as fr:
+            ref = fr.backward(dls[v], ref)
+    errs = parity.grad_rel_errors(g, ref)
+    log(f"w2 two-view gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
+
+
+def test_w2_per_view_launches_equal_batched(renderer, w2):
+    batched = GpuRun(renderer, w2, **BENCH_LAUNCH).forward().images()
+    for v in range(len(w2.views)):
+        single = GpuRun(renderer, w2, views=[w2.views[v]], **BENCH_LAUNCH).forward().images()[0]
+        assert np.array_equal(single, batched[v]), v
+
+
+def test_w3_batched_sampled_pixels(renderer):
+    sc = scenes.make_workload(3)
+    run = GpuRun(renderer, sc, **BENCH_LAUNCH).forward()
+    log(f"w3 stats {renderer.stats()}")
+    check_views(sc, run, [0, 17], n=2000)
+
+
+def test_w4_batched_sampled_pixels(renderer):
+    sc = scenes.make_workload(4)
+    run = GpuRun(renderer, sc, **BENCH_LAUNCH).forward()
+    log(f"w4 stats {renderer.stats()}")
+    check_views(sc, run, [0, 5], n=2000)
