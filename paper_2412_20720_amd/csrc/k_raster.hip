@@ -360,7 +360,9 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           const float araw = e1.y * G;
           const float alpha = fminf(S.alpha_max, araw);
           const bool take = in && alpha >= S.alpha_min;
-          const float Tb = __fdividef(T[p], 1.f - alpha);
+          // transmittance in front of the entry; v_rcp_f32 (about 1 ulp) instead of a
+          // correctly rounded division
+          const float Tb = T[p] * __builtin_amdgcn_rcpf(1.f - alpha);
           const float wgt = take ? alpha * Tb : 0.f;
           q[6] = fmaf(g0[p], wgt, q[6]);
           q[7] = fmaf(g1[p], wgt, q[7]);
