@@ -28,6 +28,7 @@ namespace g4d {
 namespace {
 
 constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
+constexpr float kInvNegHalfLog2e = -1.38629436111989061f;  // 1 / kNegHalfLog2e = -2 ln 2
 
 #define G4D_WAVE_SYNC()                                     \
   do {                                                      \
@@ -36,9 +37,11 @@ constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
   } while (0)
 
+// A staged entry carries the conic pre-multiplied by kNegHalfLog2e, so that the quadratic
+// form evaluated at a pixel is directly the base-2 exponent of exp(-d2 / 2).
 struct Staged {
-  float4 a;  // u, v, conic a, 2 * conic b
-  float4 b;  // conic c, opacity * p_t, r, g
+  float4 a;  // u, v, k conic a, 2 k conic b
+  float4 b;  // k conic c, opacity * p_t, r, g
   float4 c;  // b, list position (bits), slot (bits), unused
 };
 
@@ -122,8 +125,8 @@ __device__ __forceinline__ bool fetch_entry(const RasterArgs& a, const WaveTile&
                                t.qy0 - r0.y, t.qy1 - r0.y, xl, xr) &&
            r0.x + xr >= t.qx0 && r0.x + xl <= t.qx1;
   }
-  s.a = make_float4(r0.x, r0.y, r0.z, 2.f * r0.w);
-  s.b = r1;
+  s.a = make_float4(r0.x, r0.y, kNegHalfLog2e * r0.z, 2.f * kNegHalfLog2e * r0.w);
+  s.b = make_float4(kNegHalfLog2e * r1.x, r1.y, r1.z, r1.w);
   s.c = make_float4(r2.x, __int_as_float((int)j), __uint_as_float(slot), 0.f);
   return keep;
 }
@@ -185,10 +188,13 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   const DSettings& S = a.S;
   LanePixels<PXX, PXY> L;
   L.init(t, V);
-  float T[P], C0[P], C1[P], C2[P], pxc[P], pyc[P];
+  // lo[p]: a pixel takes part in an entry when the scaled quadratic form pw = k d2 is at least
+  // lo[p]; lo is k cutoff^2 while the pixel is live and +inf once it has stopped (or lies
+  // outside the image), so one compare covers both tests.
+  const float lo_cut = kNegHalfLog2e * S.cut2;
+  float T[P], C0[P], C1[P], C2[P], pxc[P], pyc[P], lo[P];
   int last[P];
   uint32_t evals[P], contrib[P];
-  bool live[P];
   bool any_live = false;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
@@ -198,28 +204,28 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     pyc[p] = (float)L.py[p] + 0.5f;
     last[p] = -1;
     evals[p] = contrib[p] = 0;
-    live[p] = L.inside[p];
-    any_live |= live[p];
+    lo[p] = L.inside[p] ? lo_cut : INFINITY;
+    any_live |= L.inside[p];
   }
+  bool done = __ballot(any_live) == 0ull;
   Staged* st = stage[t.w];
   const int end = (int)t.range.y;
-  for (int base = (int)t.range.x; base < end; base += BATCH) {
-    if (__ballot(any_live) == 0ull) break;
+  for (int base = (int)t.range.x; base < end && !done; base += BATCH) {
     const int n = stage_batch<BATCH>(a, t, base, end, st);
     G4D_WAVE_SYNC();
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
-      any_live = false;
+      bool any_stop = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-        const float d2 = mahalanobis(dx, dy, e0, e1.x);
-        const bool in = live[p] && d2 <= S.cut2;
+        const float pw = mahalanobis(dx, dy, e0, e1.x);
+        const bool in = pw >= lo[p];
         if (__ballot(in) != 0ull) {
-          const float alpha = fminf(S.alpha_max, e1.y * fast_exp2(d2 * kNegHalfLog2e));
+          const float alpha = fminf(S.alpha_max, e1.y * fast_exp2(pw));
           const bool ok = in && alpha >= S.alpha_min;
-          const float Tn = T[p] * (1.f - alpha);
+          const float Tn = fmaf(-T[p], alpha, T[p]);
           const bool stop = ok && Tn < S.T_min;
           const bool take = ok && !stop;
           const float wgt = take ? T[p] * alpha : 0.f;
@@ -228,15 +234,21 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           C2[p] = fmaf(wgt, e2.x, C2[p]);
           T[p] = take ? Tn : T[p];
           last[p] = take ? __float_as_int(e2.y) : last[p];
-          live[p] = live[p] && !stop;
+          lo[p] = stop ? INFINITY : lo[p];
+          any_stop |= stop;
           if (COUNT) {
             evals[p] += in ? 1u : 0u;
             contrib[p] += take ? 1u : 0u;
           }
         }
-        any_live |= live[p];
       }
-      if (__ballot(any_live) == 0ull) break;
+      if (__ballot(any_stop) != 0ull) {
+        any_live = false;
+#pragma unroll
+        for (int p = 0; p < P; ++p) any_live |= lo[p] != INFINITY;
+        done = __ballot(any_live) == 0ull;
+        if (done) break;
+      }
     }
     G4D_WAVE_SYNC();
   }
@@ -338,6 +350,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   }
   const int hi_last = wave_max(lane_last);
   if (hi_last < 0) return;
+  const float lo_cut = kNegHalfLog2e * S.cut2;
   Staged* st = stage[t.w];
   const int lo_list = (int)t.range.x;
   for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
@@ -347,37 +360,41 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
       const int jk = __float_as_int(e2.y);
-      const float hb = 0.5f * e0.w;  // conic b
+      // q[0], q[1] first hold the first moments sum sa dx, sum sa dy; they become dL/du, dL/dv
+      // (up to the factor 1 / k of the scaled conic) once per entry below.
       float q[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool any = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-        const float d2 = mahalanobis(dx, dy, e0, e1.x);
-        const bool in = jk <= last[p] && d2 <= S.cut2;
+        const float pw = mahalanobis(dx, dy, e0, e1.x);
+        const bool in = jk <= last[p] && pw >= lo_cut;
         if (__ballot(in) != 0ull) {
-          const float G = fast_exp2(d2 * kNegHalfLog2e);
+          const float G = fast_exp2(pw);
           const float araw = e1.y * G;
-          const float alpha = fminf(S.alpha_max, araw);
-          const bool take = in && alpha >= S.alpha_min;
+          const float ac = fminf(S.alpha_max, araw);
+          const bool take = in && ac >= S.alpha_min;
+          // alpha = 0 for an entry the pixel did not composite: then the updates of q[6..8],
+          // gR and the moments below vanish without selects
+          const float alpha = take ? ac : 0.f;
           // transmittance in front of the entry; v_rcp_f32 (about 1 ulp) instead of a
           // correctly rounded division
           const float Tb = T[p] * __builtin_amdgcn_rcpf(1.f - alpha);
-          const float wgt = take ? alpha * Tb : 0.f;
+          const float wgt = alpha * Tb;
           q[6] = fmaf(g0[p], wgt, q[6]);
           q[7] = fmaf(g1[p], wgt, q[7]);
           q[8] = fmaf(g2[p], wgt, q[8]);
           const float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
           const float diff = gc - gR[p];
           const float da = Tb * diff;
-          gR[p] = take ? fmaf(alpha, diff, gR[p]) : gR[p];
+          gR[p] = fmaf(alpha, diff, gR[p]);
           T[p] = take ? Tb : T[p];
-          const bool geo = take && araw < S.alpha_max;
-          q[5] = fmaf(geo ? da : 0.f, G, q[5]);
-          const float sa = geo ? da * alpha : 0.f;
+          const float ga = (take && araw < S.alpha_max) ? da : 0.f;
+          q[5] = fmaf(ga, G, q[5]);
+          const float sa = ga * alpha;
           const float sdx = sa * dx, sdy = sa * dy;
-          q[0] = fmaf(e0.z, sdx, fmaf(hb, sdy, q[0]));
-          q[1] = fmaf(hb, sdx, fmaf(e1.x, sdy, q[1]));
+          q[0] += sdx;
+          q[1] += sdy;
           q[2] = fmaf(sdx, dx, q[2]);
           q[3] = fmaf(sdx, dy, q[3]);
           q[4] = fmaf(sdy, dy, q[4]);
@@ -385,10 +402,15 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
         }
       }
       if (__ballot(any) != 0ull) {
+        const float hb = 0.5f * e0.w;  // k conic b
+        const float m0 = q[0], m1 = q[1];
+        q[0] = fmaf(e0.z, m0, hb * m1);
+        q[1] = fmaf(hb, m0, e1.x * m1);
         int field;
         float val = wave_reduce9(q, t.lane, field);
         if (field >= 0) {
-          val *= (field == 3) ? -1.f : ((field == 2 || field == 4) ? -0.5f : 1.f);
+          val *= (field <= 1) ? kInvNegHalfLog2e
+                              : ((field == 3) ? -1.f : ((field == 2 || field == 4) ? -0.5f : 1.f));
           const uint32_t slot = __float_as_uint(e2.z);
           unsafeAtomicAdd(a.grad2d + (size_t)slot * kGrad2d + field, val);
         }
