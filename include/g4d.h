@@ -88,8 +88,9 @@ typedef struct {
  *   blur 0.3          EWA low-pass: added to both diagonal entries of the 2D covariance (px^2)
  *   jacobian_margin 0.15  the perspective Jacobian is evaluated at x/z, y/z clamped to the
  *                     image widened by this fraction on each side
- *   alpha_min 1/255   contributions with alpha below this are skipped
- *   alpha_max 0.99    alpha = min(alpha_max, opacity p(t) p(u, v | t))
+ *   alpha_min 1/255   contributions with alpha below this are skipped (must be > 0)
+ *   alpha_max 0.99    alpha = min(alpha_max, opacity p(t) p(u, v | t)); alpha_min <=
+ *                     alpha_max < 1 (the backward divides by 1 - alpha)
  *   T_min 1e-4        a pixel stops before the Gaussian that would take T below T_min
  *   color_offset 0.5, color_min 0   c = max(color_min, color_offset + 4DSH sum)
  *   time_period 1     the period T of the Fourier basis of the 4DSH

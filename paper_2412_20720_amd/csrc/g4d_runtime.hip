@@ -189,8 +189,10 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     for (int k = 0; k < 12; ++k)
       if (!finite(V.world_to_cam[k])) return fail(ctx, G4D_EINVAL, "view %d: bad extrinsic", v);
   }
-  if (!(s->cutoff_sigma > 0.f) || !(s->alpha_max > 0.f) || !(s->alpha_max <= 1.f) ||
-      !(s->alpha_min >= 0.f) || !(s->T_min >= 0.f) || !(s->time_period > 0.f) ||
+  // 0 < alpha_min <= alpha_max < 1: the backward rebuilds T by dividing by 1 - alpha and
+  // recovers the opacity partial of an entry by dividing by its opacity p_t >= alpha_min.
+  if (!(s->cutoff_sigma > 0.f) || !(s->alpha_min > 0.f) || !(s->alpha_max >= s->alpha_min) ||
+      !(s->alpha_max < 1.f) || !(s->T_min >= 0.f) || !(s->time_period > 0.f) ||
       !(s->blur >= 0.f) || !(s->jacobian_margin >= 0.f) || !finite(s->near_z) ||
       !finite(s->marginal_min) || !finite(s->color_offset) || std::isnan(s->color_min))
     return fail(ctx, G4D_EINVAL, "invalid settings");

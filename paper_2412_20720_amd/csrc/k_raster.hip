@@ -30,6 +30,16 @@ namespace {
 constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
 constexpr float kInvNegHalfLog2e = -1.38629436111989061f;  // 1 / kNegHalfLog2e = -2 ln 2
 
+// A lane's pixels are tested against an entry in groups of kSlotGroup: the group is skipped
+// when none of its pixels in the whole wave is covered; otherwise all of them are evaluated
+// without branches, which lets the compiler interleave their independent dependency chains.
+// Measured on the 300k/16-view workload (32-pixel tiles, 4 pixels per lane), groups of 1 are
+// fastest: the skipped work outweighs the extra instruction-level parallelism of larger groups.
+#ifndef G4D_SLOT_GROUP
+#define G4D_SLOT_GROUP 1
+#endif
+constexpr int kSlotGroup = G4D_SLOT_GROUP;
+
 #define G4D_WAVE_SYNC()                                     \
   do {                                                      \
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
@@ -181,6 +191,7 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 template <int TILE, int BATCH, int PXX, int PXY, bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
+  constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
   __shared__ Staged stage[4][BATCH];
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
@@ -218,11 +229,24 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
       bool any_stop = false;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-        const float pw = mahalanobis(dx, dy, e0, e1.x);
-        const bool in = pw >= lo[p];
-        if (__ballot(in) != 0ull) {
+      for (int g = 0; g < P; g += kGroup) {
+        float pwg[kGroup];
+        bool ing[kGroup];
+        bool gin = false;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const int p = g + i;
+          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+          pwg[i] = mahalanobis(dx, dy, e0, e1.x);
+          ing[i] = pwg[i] >= lo[p];
+          gin |= ing[i];
+        }
+        if (__ballot(gin) == 0ull) continue;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const int p = g + i;
+          const float pw = pwg[i];
+          const bool in = ing[i];
           const float alpha = fminf(S.alpha_max, e1.y * fast_exp2(pw));
           const bool ok = in && alpha >= S.alpha_min;
           const float Tn = fmaf(-T[p], alpha, T[p]);
@@ -317,6 +341,7 @@ __device__ __forceinline__ float wave_reduce9(const float* q, int lane, int& fie
 template <int TILE, int BATCH, int PXX, int PXY>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
+  constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
   __shared__ Staged stage[4][BATCH];
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
@@ -325,6 +350,10 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   LanePixels<PXX, PXY> L;
   L.init(t, V);
   float T[P], g0[P], g1[P], g2[P], gR[P], pxc[P], pyc[P];
+  // pixel centre relative to the block centre (ox, oy), and its products: the moment sums
+  // below are taken in these coordinates and re-centred on the splat once per entry
+  float rx[P], ry[P], rxx[P], rxy[P], ryy[P];
+  const float ox = (float)t.bx + 4.f * PXX, oy = (float)t.by + 4.f * PXY;
   int last[P];
   int lane_last = -1;
   const int64_t hw = (int64_t)V.width * V.height;
@@ -336,6 +365,11 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     last[p] = -1;
     pxc[p] = (float)L.px[p] + 0.5f;
     pyc[p] = (float)L.py[p] + 0.5f;
+    rx[p] = pxc[p] - ox;
+    ry[p] = pyc[p] - oy;
+    rxx[p] = rx[p] * rx[p];
+    rxy[p] = rx[p] * ry[p];
+    ryy[p] = ry[p] * ry[p];
     if (L.inside[p]) {
       const int64_t pix = (int64_t)L.py[p] * V.width + L.px[p];
       const int64_t gp = (int64_t)V.pix_base + pix;
@@ -360,52 +394,76 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
       const int jk = __float_as_int(e2.y);
-      // q[0], q[1] first hold the first moments sum sa dx, sum sa dy; they become dL/du, dL/dv
-      // (up to the factor 1 / k of the scaled conic) once per entry below.
+      // Per pixel the lane adds sa = alpha dL/dalpha (unclamped branch only) into the moments
+      // q[0..5] = sum sa [rx, ry, rx^2, rx ry, ry^2, 1] of the block-centred pixel position
+      // and the color partials into q[6..8]; once per entry they are turned into the
+      // splat-centred moments and the partials (see below).
       float q[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool any = false;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
-        const float pw = mahalanobis(dx, dy, e0, e1.x);
-        const bool in = jk <= last[p] && pw >= lo_cut;
-        if (__ballot(in) != 0ull) {
+      for (int g = 0; g < P; g += kGroup) {
+        float pwg[kGroup];
+        bool ing[kGroup];
+        bool gin = false;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const int p = g + i;
+          const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
+          pwg[i] = mahalanobis(dx, dy, e0, e1.x);
+          ing[i] = jk <= last[p] && pwg[i] >= lo_cut;
+          gin |= ing[i];
+        }
+        if (__ballot(gin) == 0ull) continue;
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+          const int p = g + i;
+          const float pw = pwg[i];
+          const bool in = ing[i];
           const float G = fast_exp2(pw);
           const float araw = e1.y * G;
           const float ac = fminf(S.alpha_max, araw);
           const bool take = in && ac >= S.alpha_min;
-          // alpha = 0 for an entry the pixel did not composite: then the updates of q[6..8],
-          // gR and the moments below vanish without selects
+          // alpha = 0 for an entry the pixel did not composite: then T, gR, q[5..8] and the
+          // moments below are left exactly as they were, without selects
           const float alpha = take ? ac : 0.f;
-          // transmittance in front of the entry; v_rcp_f32 (about 1 ulp) instead of a
-          // correctly rounded division
-          const float Tb = T[p] * __builtin_amdgcn_rcpf(1.f - alpha);
+          // transmittance in front of the entry, T / (1 - alpha) = T + T alpha / (1 - alpha),
+          // with v_rcp_f32 (about 1 ulp) instead of a correctly rounded division
+          const float Tb = fmaf(T[p], alpha * __builtin_amdgcn_rcpf(1.f - alpha), T[p]);
           const float wgt = alpha * Tb;
           q[6] = fmaf(g0[p], wgt, q[6]);
           q[7] = fmaf(g1[p], wgt, q[7]);
           q[8] = fmaf(g2[p], wgt, q[8]);
           const float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
           const float diff = gc - gR[p];
-          const float da = Tb * diff;
           gR[p] = fmaf(alpha, diff, gR[p]);
-          T[p] = take ? Tb : T[p];
-          const float ga = (take && araw < S.alpha_max) ? da : 0.f;
-          q[5] = fmaf(ga, G, q[5]);
-          const float sa = ga * alpha;
-          const float sdx = sa * dx, sdy = sa * dy;
-          q[0] += sdx;
-          q[1] += sdy;
-          q[2] = fmaf(sdx, dx, q[2]);
-          q[3] = fmaf(sdx, dy, q[3]);
-          q[4] = fmaf(sdy, dy, q[4]);
+          // dL/dalpha = Tb diff, so sa = alpha dL/dalpha = wgt diff
+          const float sa = araw < S.alpha_max ? wgt * diff : 0.f;
+          T[p] = Tb;
+          q[0] = fmaf(sa, rx[p], q[0]);
+          q[1] = fmaf(sa, ry[p], q[1]);
+          q[2] = fmaf(sa, rxx[p], q[2]);
+          q[3] = fmaf(sa, rxy[p], q[3]);
+          q[4] = fmaf(sa, ryy[p], q[4]);
+          q[5] += sa;
           any |= take;
         }
       }
       if (__ballot(any) != 0ull) {
+        // Re-centre on the splat: with (cu, cv) its centre in block coordinates, dx = rx - cu,
+        // so S_x = sum sa dx = q0 - cu q5, S_xx = q2 - cu q0 - cu S_x, S_xy = q3 - cu q1 -
+        // cv S_x, S_yy = q4 - cv q1 - cv S_y.
+        const float cu = e0.x - ox, cv = e0.y - oy;
+        const float sx = fmaf(-cu, q[5], q[0]), sy = fmaf(-cv, q[5], q[1]);
+        q[2] = fmaf(-cu, sx, fmaf(-cu, q[0], q[2]));
+        q[3] = fmaf(-cv, sx, fmaf(-cu, q[1], q[3]));
+        q[4] = fmaf(-cv, sy, fmaf(-cv, q[1], q[4]));
+        // screen-mean partials (times k, the conic scale): dL/du ~ a S_x + b S_y, etc.
         const float hb = 0.5f * e0.w;  // k conic b
-        const float m0 = q[0], m1 = q[1];
-        q[0] = fmaf(e0.z, m0, hb * m1);
-        q[1] = fmaf(hb, m0, e1.x * m1);
+        q[0] = fmaf(e0.z, sx, hb * sy);
+        q[1] = fmaf(hb, sx, e1.x * sy);
+        // alpha = opacity p_t G on the unclamped branch, so sum G dL/dalpha = (sum sa) /
+        // (opacity p_t); a composited entry has opacity p_t >= alpha_min > 0
+        q[5] *= __builtin_amdgcn_rcpf(e1.y);
         int field;
         float val = wave_reduce9(q, t.lane, field);
         if (field >= 0) {

@@ -221,3 +221,6 @@ def test_argument_errors(renderer, w0):
     views = [dict(run.views[0], width=0)]
     with pytest.raises(B.G4DError, match="EINVAL"):
         renderer.forward(run.g, views, run.settings, run.rgb, run.T)
+    for bad_alpha in (dict(alpha_max=1.0), dict(alpha_min=0.0), dict(alpha_min=0.5, alpha_max=0.4)):
+        with pytest.raises(B.G4DError, match="EINVAL"):
+            renderer.forward(run.g, run.views, settings_for(w0, **bad_alpha), run.rgb, run.T)
