@@ -24,12 +24,15 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+bwd Mpix/s at 300k 4D Gaussians, 1352x1014; batched vs per-view launch"
 PEAK_FP32_VALU = 157.3e12   # MI355X published FP32 vector peak (FLOP/s)
 PEAK_HBM = 8.0e12           # MI355X HBM3E (B/s)
-# Algorithmic FP32 work per (Gaussian, pixel) pair, counted from the per-pair arithmetic:
-# forward 21 flops per evaluated pair (distance, exp, alpha, transmittance, color);
-# backward 62 flops per composited pair (transmittance rebuild, dL/dalpha, color behind,
-# the nine screen-space partials and their reduction).
-FWD_FLOPS_PER_PAIR = 21
-BWD_FLOPS_PER_PAIR = 62
+# Algorithmic FP32 work per (Gaussian, pixel) pair, counted from the per-pair arithmetic (an
+# FMA counts 2).  Every evaluated pair (within the cutoff, visited before the pixel's stop) costs
+# the test: offsets 2, quadratic form 7, exp(-d2/2) 2, alpha 1.  A composited pair adds, in the
+# forward, transmittance 2, weight 1 and the color FMAs 6 (21 in all); in the backward, the
+# transmittance rebuild 2, weight 1, dL/dc 6, g.c 5, g.c - g.R 1, g.R update 2, dL/dalpha 1,
+# alpha dL/dalpha 1, opacity partial 2, dL/du and dL/dv 10, conic moments 8 (51 in all).
+FLOPS_PER_EVALUATED = 12
+FWD_FLOPS_PER_COMPOSITED = 9
+BWD_FLOPS_PER_COMPOSITED = 39
 WORKLOAD_KEYS = {"0": 0, "1": 1, "2": 2, "2b": "2b", "3": 3, "4": 4}
 
 
@@ -187,14 +190,23 @@ def main():
 
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
-    flops = (BWD_FLOPS_PER_PAIR * contrib) if dom == "raster_bwd" else (FWD_FLOPS_PER_PAIR * evals)
+    per_comp = BWD_FLOPS_PER_COMPOSITED if dom == "raster_bwd" else FWD_FLOPS_PER_COMPOSITED
+    flops = FLOPS_PER_EVALUATED * evals + per_comp * contrib
     achieved = flops / (stage_ms[dom] * 1e-3)
     traffic = profiled_traffic(sc.name, settings) if dom == "raster_bwd" else None
     roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
-                    units=contrib if dom == "raster_bwd" else evals,
-                    flops_per_unit=BWD_FLOPS_PER_PAIR if dom == "raster_bwd" else FWD_FLOPS_PER_PAIR,
-                    ms_per_launch=stage_ms[dom])
+                    units={"evaluated_pairs": evals, "composited_pairs": contrib},
+                    flops_per_unit={"evaluated_pair": FLOPS_PER_EVALUATED,
+                                    "composited_pair_extra": per_comp},
+                    flops_per_launch=flops, ms_per_launch=stage_ms[dom])
+
+    # Whole-path bound from the algorithmic work alone (forward + backward raster flops at the
+    # FP32 VALU peak).
+    bound_s = (2 * FLOPS_PER_EVALUATED * evals +
+               (FWD_FLOPS_PER_COMPOSITED + BWD_FLOPS_PER_COMPOSITED) * contrib) / PEAK_FP32_VALU
+    alg_bound = dict(mpix_s=npix / bound_s / 1e6, frac=(npix / dt / 1e6) / (npix / bound_s / 1e6),
+                     evaluated_pairs_per_px=evals / npix, composited_pairs_per_px=contrib / npix)
 
     cpu = None
     if not args.no_cpu:
@@ -211,6 +223,7 @@ def main():
         "per_view": per_view,
         "graph": graph,
         "roofline": roofline,
+        "alg_bound": alg_bound,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
                  "evaluated_pairs": evals, "composited_pairs": contrib},
