@@ -74,6 +74,12 @@ class _Grads(C.Structure):
                 ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")]
 
 
+class _Channels(C.Structure):
+    _fields_ = [("n_features", C.c_int32), ("features", C.POINTER(C.c_double)),
+                ("gate", C.POINTER(C.c_double)), ("depth", C.c_int32), ("flow", C.c_int32),
+                ("flow_dt", C.c_double)]
+
+
 SPLAT_DTYPE = np.dtype([("alive", np.int32), ("optional", np.int32), ("depth", np.float64),
                         ("mean2d", np.float64, 2), ("cov2d", np.float64, 3),
                         ("conic", np.float64, 3), ("p_t", np.float64), ("opt", np.float64),
@@ -101,11 +107,14 @@ def lib() -> C.CDLL:
         L.orc_frame_new.restype = C.c_void_p
         L.orc_frame_free.argtypes = [C.c_void_p]
         L.orc_frame_splats.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_frame_set_channels.argtypes = [C.c_void_p, C.POINTER(_Channels)]
+        L.orc_frame_set_channels.restype = C.c_int
         L.orc_frame_render.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
-                                       C.c_void_p, C.c_void_p, C.c_void_p]
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_frame_variants.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Grads),
                                          C.c_void_p, C.c_void_p]
-        L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(_Grads)]
         L.orc_frame_backward_splat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -182,7 +191,25 @@ class Frame:
         s = _Settings(*[float(st[k]) if (exact_f64 or k.startswith("margin_"))
                         else float(np.float32(st[k])) for k in _SETTING_NAMES])
         self.settings = st
+        self._conv = conv
+        self.n_ext = self.n_features = 0
+        self.depth = self.flow = False
         self._h = lib().orc_frame_new(C.byref(g), C.byref(v), C.byref(s), int(use_bins))
+
+    def set_channels(self, features: Optional[np.ndarray] = None, gate=None, depth: bool = False,
+                     flow: bool = False, flow_dt: float = 0.0) -> int:
+        """Attach extra channels (features [n, D] gated by `gate` [D] and normalized, depth,
+        flow over `flow_dt`); returns their number E = D + depth + 2 flow."""
+        D = 0 if features is None else int(np.asarray(features).shape[1])
+        self._features = self._conv(features) if D else None
+        self._gate = self._conv(gate) if (D and gate is not None) else None
+        dt = float(flow_dt) if self._conv is not _f64 else float(np.float32(flow_dt))
+        ch = _Channels(D, _dp(self._features) if D else None,
+                       _dp(self._gate) if self._gate is not None else None, int(depth),
+                       int(flow), dt)
+        self.n_ext = int(lib().orc_frame_set_channels(self._h, C.byref(ch)))
+        self.n_features, self.depth, self.flow = D, bool(depth), bool(flow)
+        return self.n_ext
 
     def close(self):
         if getattr(self, "_h", None):
@@ -216,35 +243,56 @@ class Frame:
         nc = np.zeros(n, np.int32)
         nm = np.zeros(n, np.int32)
         ne = np.zeros(n, np.int64)
+        E = self.n_ext
+        ext = np.zeros((n, E))
         lib().orc_frame_render(self._h, n, None if xyp is None else xyp.ctypes.data,
                                rgb.ctypes.data, T.ctypes.data, nc.ctypes.data, nm.ctypes.data,
-                               ne.ctypes.data)
+                               ne.ctypes.data, ext.ctypes.data if E else None)
         out = dict(rgb=rgb, T=T, n_contrib=nc, n_marks=nm, n_evals=ne)
+        if E:
+            out["ext"] = ext
         if xy is None:
             H, W = self.height, self.width
             out = dict(rgb=rgb.reshape(H, W, 3).transpose(2, 0, 1).copy(), T=T.reshape(H, W),
                        n_contrib=nc.reshape(H, W), n_marks=nm.reshape(H, W),
                        n_evals=ne.reshape(H, W))
+            if E:
+                out["ext"] = ext.reshape(H, W, E).transpose(2, 0, 1).copy()
         return out
 
     def variants(self, x: int, y: int, max_marks: int = 4):
-        """All admissible (rgb, T) of pixel (x, y), or None if it has too many marked decisions."""
+        """All admissible (rgb, T, extra channels) of pixel (x, y), or None if it has too many
+        marked decisions."""
         cap = 1 << max_marks
         rgb = np.zeros((cap, 3))
         T = np.zeros(cap)
+        ext = np.zeros((cap, self.n_ext))
         nv = lib().orc_frame_variants(self._h, int(x), int(y), max_marks, cap, rgb.ctypes.data,
-                                      T.ctypes.data)
+                                      T.ctypes.data, ext.ctypes.data if self.n_ext else None)
         if nv < 0:
             return None
-        return rgb[:nv], T[:nv]
+        return rgb[:nv], T[:nv], ext[:nv]
 
-    def backward(self, dL_drgb: np.ndarray, grads: Optional[Dict[str, np.ndarray]] = None):
-        """Accumulate d<dL_drgb, image>/d(params) into ``grads`` (float64; created if None)."""
+    def backward(self, dL_drgb: np.ndarray, grads: Optional[Dict[str, np.ndarray]] = None,
+                 dL_dext: Optional[np.ndarray] = None):
+        """Accumulate d(<dL_drgb, image> + <dL_dext, extra channels>)/d(params) into ``grads``
+        (float64; created if None).  With features attached, ``grads`` also receives
+        "features" [n, D] and "gate" [D].  The flow channels of dL_dext are ignored."""
         if grads is None:
             grads = {k: np.zeros_like(a) for k, a in self._arrays.items()}
+        if self.n_features:
+            grads.setdefault("features", np.zeros((self.n, self.n_features)))
+            grads.setdefault("gate", np.zeros(self.n_features))
         g = np.ascontiguousarray(dL_drgb, np.float64).reshape(3, self.height, self.width)
+        gx = None
+        if dL_dext is not None and self.n_ext:
+            gx = np.ascontiguousarray(dL_dext, np.float64).reshape(self.n_ext, self.height,
+                                                                    self.width)
         gs = _Grads(*[_dp(grads[k]) for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
-        lib().orc_frame_backward(self._h, g.ctypes.data, C.byref(gs))
+        lib().orc_frame_backward(self._h, g.ctypes.data, None if gx is None else gx.ctypes.data,
+                                 C.byref(gs),
+                                 grads["features"].ctypes.data if self.n_features else None,
+                                 grads["gate"].ctypes.data if self.n_features else None)
         return grads
 
     def backward_splat(self, dL_drgb: np.ndarray) -> np.ndarray:

@@ -33,6 +33,18 @@
 // cutoff, so candidate sets and all arithmetic are those of the definition; a test checks the
 // binned search against an exhaustive all-pairs loop.
 //
+// Extra channels (optional, orc_frame_set_channels), composited with the same weights T alpha:
+//   features: per Gaussian f in R^D gated by a per-call vector g (the scale gate S(s)) and
+//       normalized, f_hat = (g * f) / |g * f| (0 where g * f = 0) -- the color replaced by the
+//       normalized scale-gated feature (Sec. 3.4, 4D segmentation);
+//   depth: the camera-space z of the sliced mean (the rendered depth of the urban LiDAR loss,
+//       Sec. 3.4);
+//   flow: the image-plane displacement of the projected conditional mean between t and
+//       t + dt (Sec. 4.1.3, the emerged scene dynamics), 0 where the moved mean is not in front
+//       of the camera.
+//   The extra channels have a zero background.  Their backward differentiates the features,
+//   the gate and the depth; flow is forward only (its upstream gradient is ignored).
+//
 // Readings where the paper is silent (defaults chosen by the caller through orc_settings):
 // unnormalized Gaussians; opacity clamp alpha_max and skip threshold alpha_min; transmittance
 // stop T_min; per-pixel Mahalanobis cutoff; EWA low-pass "blur"; Jacobian clamp margin;
@@ -89,6 +101,15 @@ typedef struct {
 typedef struct {
   double *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
 } orc_grads;
+
+typedef struct {
+  int32_t n_features;      // D >= 0
+  const double* features;  // [n][D] (may be NULL when D = 0)
+  const double* gate;      // [D], or NULL for all ones
+  int32_t depth;           // 1: add a depth channel
+  int32_t flow;            // 1: add two flow channels (du, dv)
+  double flow_dt;          // time step of the flow
+} orc_channels;
 
 }  // extern "C"
 
@@ -454,6 +475,7 @@ struct PixelResult {
   int n_contrib;
   int64_t n_evals;
   std::vector<Decision> marks;
+  std::vector<double> ext;  // extra channels (E)
 };
 
 struct Frame {
@@ -464,6 +486,12 @@ struct Frame {
   int bin = 16, bins_x = 0, bins_y = 0;
   std::vector<std::vector<int32_t>> bins;
   bool use_bins = true;
+  // Extra channels: E = D + depth + 2 flow values per splat, in that order.
+  int D = 0, E = 0, off_depth = -1, off_flow = -1;
+  const double* features = nullptr;  // [n][D]
+  std::vector<double> gate;          // [D]
+  std::vector<double> fnorm;         // |g * f| per Gaussian
+  std::vector<double> ext;           // [n][E]
 };
 
 void load_params(const orc_gaussians& g, int i, double m4[4], double s4[4], double ql[4],
@@ -595,6 +623,7 @@ void composite(const Frame& f, const std::vector<Cand>& cands, const std::vector
     if (marks[j].type == D_SWAP && ((flip >> j) & 1u)) std::swap(order[marks[j].pos], order[marks[j].pos2]);
 
   double T = 1.0, C[3] = {0, 0, 0};
+  res.ext.assign(f.E, 0.0);
   int n_contrib = 0;
   int64_t n_evals = 0;
   int last_pos = -1;  // order position of the previous contributing candidate
@@ -632,6 +661,7 @@ void composite(const Frame& f, const std::vector<Cand>& cands, const std::vector
     }
     if (contrib) contrib->push_back({order[k], T, alpha, G, raw >= st.alpha_max});
     for (int ch = 0; ch < 3; ++ch) C[ch] += T * alpha * s.col[ch];
+    for (int c = 0; c < f.E; ++c) res.ext[c] += T * alpha * f.ext[(size_t)cd.idx * f.E + c];
     T = Tn;
     ++n_contrib;
     last_pos = (int)k;
@@ -655,14 +685,18 @@ void render_pixel(const Frame& f, int px, int py, PixelResult& res, std::vector<
 // 0-1 mean2d (u, v), 2-4 conic (a, b, c), 5 opt, 6-8 color.
 constexpr int NQ = 9;
 
+// gx: upstream gradient of the extra channels (E values, the flow entries set to zero by the
+// caller); acc_ext (n * E) receives dL/d(extra payload) per splat.  Both may be NULL.
 void pixel_backward(const Frame& f, int px, int py, const double g[3], std::vector<Cand>& cands,
-                    std::vector<Contrib>& contrib, double* acc /* n * NQ */) {
+                    std::vector<Contrib>& contrib, double* acc /* n * NQ */,
+                    const double* gx = nullptr, double* acc_ext = nullptr) {
   gather(f, px, py, cands);
   PixelResult res;
   contrib.clear();
   composite(f, cands, {}, 0u, false, res, &contrib);
   // Reverse sweep: R = color of everything behind the current contributor (incl. background).
   double R[3] = {f.vw.background[0], f.vw.background[1], f.vw.background[2]};
+  std::vector<double> Rx(gx ? f.E : 0, 0.0);  // extra channels behind (zero background)
   const double cx = px + 0.5, cy = py + 0.5;
   for (int k = (int)contrib.size() - 1; k >= 0; --k) {
     const Contrib& ct = contrib[k];
@@ -673,6 +707,14 @@ void pixel_backward(const Frame& f, int px, int py, const double g[3], std::vect
     for (int ch = 0; ch < 3; ++ch) {
       a[6 + ch] += g[ch] * ct.T * ct.alpha;
       dalpha += g[ch] * ct.T * (s.col[ch] - R[ch]);
+    }
+    if (gx) {
+      const double* e = f.ext.data() + (size_t)cd.idx * f.E;
+      for (int c = 0; c < f.E; ++c) {
+        acc_ext[(size_t)cd.idx * f.E + c] += gx[c] * ct.T * ct.alpha;
+        dalpha += gx[c] * ct.T * (e[c] - Rx[c]);
+        Rx[c] = ct.alpha * e[c] + (1.0 - ct.alpha) * Rx[c];
+      }
     }
     if (!ct.clamped) {
       const double dx = cx - s.u, dy = cy - s.v;
@@ -688,7 +730,8 @@ void pixel_backward(const Frame& f, int px, int py, const double g[3], std::vect
   }
 }
 
-void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grads& out) {
+void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grads& out,
+                       double q_depth = 0.0) {
   double m4[4], s4[4], ql[4], qr[4], o;
   load_params(f.g, i, m4, s4, ql, qr, o);
   Dual M[4], Sc[4], QL[4], QR[4];
@@ -706,6 +749,7 @@ void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grad
   double grad[NG] = {0};
   for (int j = 0; j < NQ; ++j)
     for (int k = 0; k < NG; ++k) grad[k] += q[j] * outs[j]->d[k];
+  for (int k = 0; k < NG; ++k) grad[k] += q_depth * sp.depth.d[k];
   for (int k = 0; k < 4; ++k) {
     out.mean4[4 * i + k] += grad[k];
     out.scale4[4 * i + k] += grad[4 + k];
@@ -724,6 +768,31 @@ void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grad
       for (int ch = 0; ch < 3; ++ch)
         if (!sp.color_clamped[ch]) gsh[(n * nsh + k) * 3 + ch] += q[6 + ch] * fn * Y[k];
   }
+}
+
+// Image-plane displacement of the projected conditional mean of Gaussian i between the frame's
+// time t and t + dt (0 where either mean is not in front of the camera).
+void flow_of(const Frame& f, int i, double dt, double out[2]) {
+  double m4[4], s4[4], ql[4], qr[4], o;
+  load_params(f.g, i, m4, s4, ql, qr, o);
+  double Rm[4][4], Sig[4][4], mu[2][3], cov[3][3], pt;
+  rotation4<double>(ql, qr, Rm);
+  covariance4<double>(Rm, s4, Sig);
+  slice<double>(Sig, m4, f.vw.t, mu[0], cov, pt);
+  slice<double>(Sig, m4, f.vw.t + dt, mu[1], cov, pt);
+  const double* E = f.vw.world_to_cam;
+  double uv[2][2];
+  out[0] = out[1] = 0.0;
+  for (int k = 0; k < 2; ++k) {
+    double x[3];
+    for (int r = 0; r < 3; ++r)
+      x[r] = E[4 * r] * mu[k][0] + E[4 * r + 1] * mu[k][1] + E[4 * r + 2] * mu[k][2] + E[4 * r + 3];
+    if (!(x[2] > 0.0)) return;
+    uv[k][0] = f.vw.fx * x[0] / x[2] + f.vw.cx;
+    uv[k][1] = f.vw.fy * x[1] / x[2] + f.vw.cy;
+  }
+  out[0] = uv[1][0] - uv[0][0];
+  out[1] = uv[1][1] - uv[0][1];
 }
 
 }  // namespace
@@ -777,6 +846,42 @@ void* orc_frame_new(const orc_gaussians* g, const orc_view* vw, const orc_settin
 
 void orc_frame_free(void* h) { delete static_cast<Frame*>(h); }
 
+// Attach extra channels to the frame (features, depth, flow; see the file header).  The
+// feature array must stay alive as long as the frame is used.  Returns E, the number of extra
+// channels.
+int orc_frame_set_channels(void* h, const orc_channels* ch) {
+  Frame& f = *static_cast<Frame*>(h);
+  const int n = f.g.n;
+  f.D = ch->n_features;
+  f.features = ch->features;
+  f.off_depth = ch->depth ? f.D : -1;
+  f.off_flow = ch->flow ? f.D + (ch->depth ? 1 : 0) : -1;
+  f.E = f.D + (ch->depth ? 1 : 0) + (ch->flow ? 2 : 0);
+  f.gate.assign(f.D, 1.0);
+  if (ch->gate)
+    for (int c = 0; c < f.D; ++c) f.gate[c] = ch->gate[c];
+  f.fnorm.assign(n, 0.0);
+  f.ext.assign((size_t)n * f.E, 0.0);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int i = 0; i < n; ++i) {
+    double* e = f.ext.data() + (size_t)i * f.E;
+    if (f.D > 0) {
+      double nrm2 = 0.0;
+      for (int c = 0; c < f.D; ++c) {
+        const double v = f.gate[c] * f.features[(size_t)i * f.D + c];
+        nrm2 += v * v;
+      }
+      const double nrm = std::sqrt(nrm2);
+      f.fnorm[i] = nrm;
+      for (int c = 0; c < f.D; ++c)
+        e[c] = nrm > 0.0 ? f.gate[c] * f.features[(size_t)i * f.D + c] / nrm : 0.0;
+    }
+    if (f.off_depth >= 0) e[f.off_depth] = f.splats[i].depth;
+    if (f.off_flow >= 0) flow_of(f, i, ch->flow_dt, e + f.off_flow);
+  }
+  return f.E;
+}
+
 // Full O1-O7 output per Gaussian (alive Gaussians only carry meaningful values).
 int orc_frame_splats(void* h, orc_splat* out) {
   Frame& f = *static_cast<Frame*>(h);
@@ -813,9 +918,10 @@ int orc_frame_splats(void* h, orc_splat* out) {
 
 // Render pixels.  xy: n_pix (x, y) pairs, or NULL for the whole image in row-major order.
 // rgb: [n_pix][3]; T, n_contrib, n_marks: [n_pix]; n_evals: [n_pix] candidates evaluated
-// (Mahalanobis distance within the cutoff) up to the stop.  Any output may be NULL.
+// (Mahalanobis distance within the cutoff) up to the stop; ext: [n_pix][E] extra channels.
+// Any output may be NULL.
 int orc_frame_render(void* h, int n_pix, const int32_t* xy, double* rgb, double* T,
-                     int32_t* n_contrib, int32_t* n_marks, int64_t* n_evals) {
+                     int32_t* n_contrib, int32_t* n_marks, int64_t* n_evals, double* ext) {
   Frame& f = *static_cast<Frame*>(h);
   const int W = f.vw.width;
   if (!xy) n_pix = W * f.vw.height;
@@ -833,6 +939,8 @@ int orc_frame_render(void* h, int n_pix, const int32_t* xy, double* rgb, double*
       if (n_contrib) n_contrib[p] = res.n_contrib;
       if (n_marks) n_marks[p] = (int32_t)res.marks.size();
       if (n_evals) n_evals[p] = res.n_evals;
+      if (ext)
+        for (int c = 0; c < f.E; ++c) ext[(size_t)p * f.E + c] = res.ext[c];
     }
   }
   return 0;
@@ -842,7 +950,7 @@ int orc_frame_render(void* h, int n_pix, const int32_t* xy, double* rgb, double*
 // way.  Returns the number of variants written (2^marks), or -1 if the pixel has more than
 // max_marks marked decisions (unverifiable), or -2 if the output buffer is too small.
 int orc_frame_variants(void* h, int px, int py, int max_marks, int max_out, double* rgb,
-                       double* T) {
+                       double* T, double* ext) {
   Frame& f = *static_cast<Frame*>(h);
   std::vector<Cand> cands;
   PixelResult base;
@@ -856,36 +964,70 @@ int orc_frame_variants(void* h, int px, int py, int max_marks, int max_out, doub
     composite(f, cands, base.marks, (unsigned)v, false, r, nullptr);
     for (int ch = 0; ch < 3; ++ch) rgb[3 * v + ch] = r.rgb[ch];
     if (T) T[v] = r.T;
+    if (ext)
+      for (int c = 0; c < f.E; ++c) ext[(size_t)v * f.E + c] = r.ext[c];
   }
   return nv;
 }
 
 // Backward of the whole image of this view: accumulates (+=) the gradient of
-// L = <dL_drgb, image> into `out`.  dL_drgb is planar [3][H][W].
-int orc_frame_backward(void* h, const double* dL_drgb, orc_grads* out) {
+// L = <dL_drgb, image> + <dL_dext, extra channels> into `out`, `d_features` ([n][D]) and
+// `d_gate` ([D]).  dL_drgb is planar [3][H][W]; dL_dext is planar [E][H][W] or NULL (its flow
+// channels are ignored).  d_features and d_gate may be NULL when there are no features.
+int orc_frame_backward(void* h, const double* dL_drgb, const double* dL_dext, orc_grads* out,
+                       double* d_features, double* d_gate) {
   Frame& f = *static_cast<Frame*>(h);
   const int W = f.vw.width, H = f.vw.height, n = f.g.n;
-  std::vector<double> acc((size_t)n * NQ, 0.0);
+  const bool has_ext = dL_dext && f.E > 0;
+  const int E = has_ext ? f.E : 0;
+  std::vector<double> acc((size_t)n * NQ, 0.0), acc_ext((size_t)n * E, 0.0);
 #pragma omp parallel
   {
-    std::vector<double> local((size_t)n * NQ, 0.0);
+    std::vector<double> local((size_t)n * NQ, 0.0), local_ext((size_t)n * E, 0.0);
+    std::vector<double> gx(E, 0.0);
     std::vector<Cand> cands;
     std::vector<Contrib> contrib;
 #pragma omp for schedule(dynamic, 64)
     for (int p = 0; p < W * H; ++p) {
       const double g[3] = {dL_drgb[p], dL_drgb[(size_t)W * H + p], dL_drgb[2 * (size_t)W * H + p]};
-      pixel_backward(f, p % W, p / W, g, cands, contrib, local.data());
+      for (int c = 0; c < E; ++c) {
+        const bool is_flow = f.off_flow >= 0 && c >= f.off_flow;
+        gx[c] = is_flow ? 0.0 : dL_dext[(size_t)c * W * H + p];
+      }
+      pixel_backward(f, p % W, p / W, g, cands, contrib, local.data(),
+                     has_ext ? gx.data() : nullptr, has_ext ? local_ext.data() : nullptr);
     }
 #pragma omp critical
-    for (size_t k = 0; k < local.size(); ++k) acc[k] += local[k];
+    {
+      for (size_t k = 0; k < local.size(); ++k) acc[k] += local[k];
+      for (size_t k = 0; k < local_ext.size(); ++k) acc_ext[k] += local_ext[k];
+    }
   }
 #pragma omp parallel for schedule(dynamic, 64)
   for (int i = 0; i < n; ++i) {
     const double* q = acc.data() + (size_t)i * NQ;
-    bool any = false;
+    const double q_depth = (has_ext && f.off_depth >= 0) ? acc_ext[(size_t)i * E + f.off_depth] : 0.0;
+    bool any = q_depth != 0.0;
     for (int j = 0; j < NQ; ++j) any |= q[j] != 0.0;
     if (!any || !f.splats[i].alive) continue;
-    gaussian_backward(f, i, q, *out);
+    gaussian_backward(f, i, q, *out, q_depth);
+  }
+  // Features: f_hat = s / |s|, s = gate * f.  dL/ds = (dL/df_hat - f_hat (f_hat . dL/df_hat)) / |s|,
+  // dL/df = gate * dL/ds, dL/dgate = sum over Gaussians of f * dL/ds.  (Zero where |s| = 0.)
+  if (has_ext && f.D > 0 && d_features) {
+    for (int i = 0; i < n; ++i) {
+      const double nrm = f.fnorm[i];
+      if (!(nrm > 0.0)) continue;
+      const double* gf = acc_ext.data() + (size_t)i * E;
+      const double* fh = f.ext.data() + (size_t)i * f.E;
+      double dot = 0.0;
+      for (int c = 0; c < f.D; ++c) dot += fh[c] * gf[c];
+      for (int c = 0; c < f.D; ++c) {
+        const double ds = (gf[c] - fh[c] * dot) / nrm;
+        d_features[(size_t)i * f.D + c] += f.gate[c] * ds;
+        if (d_gate) d_gate[c] += f.features[(size_t)i * f.D + c] * ds;
+      }
+    }
   }
   return 0;
 }

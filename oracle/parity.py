@@ -16,22 +16,27 @@ import numpy as np
 
 
 def check_image(gpu_rgb: np.ndarray, frame, tol: float = 1e-4, xy: Optional[np.ndarray] = None,
-                max_marks: int = 4, ref=None) -> Dict:
-    """gpu_rgb: [3, H, W] (full image) or [n, 3] at the pixels xy."""
+                max_marks: int = 4, ref=None, channels: str = "rgb", rel_tol: float = 0.0) -> Dict:
+    """gpu_rgb: [C, H, W] (full image) or [n, C] at the pixels xy, C = 3 for channels="rgb" or
+    the frame's extra channels for channels="ext".  An element agrees when
+    |gpu - oracle| <= tol + rel_tol |oracle|."""
     if ref is None:
         ref = frame.render(xy)
+    key, vi = ("rgb", 0) if channels == "rgb" else ("ext", 2)
+    nc = 3 if channels == "rgb" else frame.n_ext
     if xy is None:
-        g = np.asarray(gpu_rgb, np.float64).reshape(3, -1).T
-        r = ref["rgb"].reshape(3, -1).T
+        g = np.asarray(gpu_rgb, np.float64).reshape(nc, -1).T
+        r = ref[key].reshape(nc, -1).T
         marks = ref["n_marks"].reshape(-1)
         W = frame.width
         coords = np.stack([np.arange(g.shape[0]) % W, np.arange(g.shape[0]) // W], 1)
     else:
-        g = np.asarray(gpu_rgb, np.float64).reshape(-1, 3)
-        r = ref["rgb"]
+        g = np.asarray(gpu_rgb, np.float64).reshape(-1, nc)
+        r = ref[key]
         marks = ref["n_marks"]
         coords = np.asarray(xy).reshape(-1, 2)
-    err = np.abs(g - r).max(1)
+    lim = tol + rel_tol * np.abs(r)
+    err = (np.abs(g - r) / lim).max(1) * tol if len(r) else np.zeros(0)
     bad = np.nonzero(err > tol)[0]
     resolved, unverified, failures = 0, 0, []
     for p in bad:
@@ -42,7 +47,8 @@ def check_image(gpu_rgb: np.ndarray, frame, tol: float = 1e-4, xy: Optional[np.n
         if var is None:
             unverified += 1
             continue
-        if (np.abs(var[0] - g[p]).max(1) <= tol).any():
+        vv = var[vi]
+        if (np.abs(vv - g[p]) <= tol + rel_tol * np.abs(vv)).all(1).any():
             resolved += 1
         else:
             failures.append((int(coords[p][0]), int(coords[p][1]), float(err[p]), "no variant"))

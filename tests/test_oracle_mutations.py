@@ -10,7 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-        os.path.join(ROOT, "tests", "test_oracle_gradients.py")]
+        os.path.join(ROOT, "tests", "test_oracle_gradients.py"),
+        os.path.join(ROOT, "tests", "test_oracle_channels.py")]
 
 # (name, exact text in oracle.cpp, replacement)
 MUTATIONS = [
@@ -43,6 +44,17 @@ MUTATIONS = [
      "R[ch] = ct.alpha * s.col[ch] + (1.0 - ct.alpha) * R[ch];", "R[ch] = s.col[ch];"),
     ("backward conic term sign", "a[3] += dalpha * ct.alpha * (-dx * dy);",
      "a[3] += dalpha * ct.alpha * (dx * dy);"),
+    ("extra channels without transmittance",
+     "res.ext[c] += T * alpha * f.ext[(size_t)cd.idx * f.E + c];",
+     "res.ext[c] += alpha * f.ext[(size_t)cd.idx * f.E + c];"),
+    ("features not normalized", "e[c] = nrm > 0.0 ? f.gate[c] * f.features[(size_t)i * f.D + c] / nrm : 0.0;",
+     "e[c] = f.gate[c] * f.features[(size_t)i * f.D + c];"),
+    ("flow over the wrong time", "slice<double>(Sig, m4, f.vw.t + dt, mu[1], cov, pt);",
+     "slice<double>(Sig, m4, f.vw.t + 0.5 * dt, mu[1], cov, pt);"),
+    ("extra channels behind not updated", "Rx[c] = ct.alpha * e[c] + (1.0 - ct.alpha) * Rx[c];",
+     "Rx[c] = e[c];"),
+    ("feature gradient without the projection", "const double ds = (gf[c] - fh[c] * dot) / nrm;",
+     "const double ds = gf[c] / nrm;"),
 ]
 
 
