@@ -159,6 +159,52 @@ g4d_status g4d_render_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_v
                                int32_t n_views, const g4d_settings *s, const float *dL_drgb,
                                const g4d_grads *out, void *stream);
 
+/* Extra channels rendered with the same weights T alpha as the image (Sec. 3.4: the 2D feature
+ * map of 4D segmentation, the color replaced by the normalized scale-gated feature, and the
+ * rendered depth of the urban LiDAR loss; Sec. 4.1.3: the rendered optical flow, the image
+ * displacement of each conditional mean between t and t + flow_dt).  The channels of a pixel
+ * are, in order: n_features feature channels, then the depth channel (if depth), then du, dv
+ * (if flow); E = n_features + depth + 2 flow <= G4D_MAX_CHANNELS.  Their background is 0.
+ *   features: device [N][n_features] float32, row-major (NULL iff n_features = 0); each
+ *             Gaussian's f is gated and normalized, f_hat = (gate * f) / |gate * f| (0 when
+ *             gate * f = 0);
+ *   gate:     device [n_features] float32 (the scale gate S(s)), or NULL for all ones;
+ *   depth:    camera-space z of the sliced mean;
+ *   flow:     (u, v)(t + flow_dt) - (u, v)(t) of the projected conditional mean, 0 where the
+ *             moved mean is not in front of the camera.  Flow is forward only. */
+#define G4D_MAX_CHANNELS 36
+typedef struct {
+  int32_t n_features;
+  const float *features, *gate;
+  int32_t depth, flow;
+  float flow_dt;
+} g4d_channels;
+
+/* g4d_render_forward plus the extra channels of *ch:
+ *   out_ch: per view planar [E][H][W], views concatenated in order (caller-owned device memory).
+ * Rasterization uses one pixel per lane and 64-entry LDS batches whatever s->px_per_lane and
+ * s->lds_batch say (tile_size is honored); out_rgb and out_T are bit-identical to
+ * g4d_render_forward's.  Saves the state g4d_render_channels_backward needs. */
+g4d_status g4d_render_channels_forward(g4d_ctx *ctx, const g4d_gaussians *g,
+                                       const g4d_view *views, int32_t n_views,
+                                       const g4d_settings *s, const g4d_channels *ch,
+                                       float *out_rgb, float *out_T, float *out_ch, void *stream);
+
+/* Backward of the last g4d_render_channels_forward on this context with the same g, views,
+ * settings and *ch (else G4D_ESTATE): given dL/d(out_rgb) and dL/d(out_ch) (same layout as
+ * out_ch, or NULL for zero; its flow channels are ignored), writes dL/d(parameters) into *out,
+ * dL/d(features) [N][n_features] into d_features and dL/d(gate) [n_features] into d_gate, all
+ * summed over the views and overwritten.  d_features may be NULL only when n_features is 0;
+ * d_gate may be NULL (then not computed).  The depth channel's gradient reaches the Gaussians
+ * through the sliced mean.  g4d_render_backward after g4d_render_channels_forward gives the
+ * image gradients alone. */
+g4d_status g4d_render_channels_backward(g4d_ctx *ctx, const g4d_gaussians *g,
+                                        const g4d_view *views, int32_t n_views,
+                                        const g4d_settings *s, const g4d_channels *ch,
+                                        const float *dL_drgb, const float *dL_dch,
+                                        const g4d_grads *out, float *d_features, float *d_gate,
+                                        void *stream);
+
 /* Flags of g4d_render_step. */
 #define G4D_STEP_GRAPH 1
 

@@ -24,7 +24,7 @@
 namespace g4d {
 
 constexpr int kRec = 12;      // floats per (view, Gaussian) record
-constexpr int kGrad2d = 12;   // floats per (view, Gaussian) screen-space gradient slot (9 used)
+constexpr int kGrad2d = 12;   // floats per (view, Gaussian) gradient slot (GradField, 10 used)
 
 // Record layout (kRec floats).
 enum RecField {
@@ -32,7 +32,8 @@ enum RecField {
   R_EX = 9, R_EY = 10, R_DEPTH = 11
 };
 // Screen-space gradient slot layout: d/du, d/dv, d/da, d/db, d/dc, d/d(opacity p_t), d/drgb.
-enum GradField { G_U = 0, G_V = 1, G_A = 2, G_B = 3, G_C = 4, G_OPT = 5, G_R = 6 };
+// G_DEPTH: dL/d(camera depth), from the depth channel of the extra-channel render (0 otherwise).
+enum GradField { G_U = 0, G_V = 1, G_A = 2, G_B = 3, G_C = 4, G_OPT = 5, G_R = 6, G_DEPTH = 9 };
 
 struct DView {
   float W[9];        // world-to-camera rotation, row-major
@@ -502,7 +503,7 @@ __device__ __forceinline__ void view_backward(const Geom& g, const float4 mean, 
   gx[0] = grx * f.iz;
   gx[1] = gry * f.iz;
   giz = fmaf(grx, f.x[0], fmaf(gry, f.x[1], giz));
-  gx[2] = -giz * f.iz * f.iz;
+  gx[2] = fmaf(-giz * f.iz, f.iz, q[G_DEPTH]);
   // x = W mu_c + tau
 #pragma unroll
   for (int j = 0; j < 3; ++j) gmuc[j] += V.W[j] * gx[0] + V.W[3 + j] * gx[1] + V.W[6 + j] * gx[2];

@@ -83,7 +83,25 @@ struct RasterArgs {
   uint32_t* px_evals;        // optional per-pixel evaluation counter
   const float* dL;           // backward
   float* grad2d;             // backward
+  // Extra channels (0 when none): E = n_feat + has_depth + 2 has_flow values per pixel, in
+  // that order.  Features are read per Gaussian (fn, [n_gauss][n_feat], normalized), depth
+  // from the record, flow from `flow` ([slots][2]).
+  int n_ext, n_feat, has_depth, has_flow, n_gauss;
+  const float* fn;
+  const float* flow;
+  float* out_ch;             // forward: per view [E][H][W]
+  const float* dL_ch;        // backward: same layout (flow channels ignored)
+  float* dfn;                // backward: dL/d(normalized features) [n_gauss][n_feat], atomics
 };
+
+// Extra-channel helpers (k_channels.hip).
+void feature_normalize(int n, int d, const float* f, const float* gate, float* fn, float* fnorm,
+                       hipStream_t st);
+void flow_forward(const GaussPtrs& g, const DView* views, int n_views, const uint32_t* tiles,
+                  float dt, float* flow, hipStream_t st);
+void feature_backward(int n, int d, const float* f, const float* gate, const float* fn,
+                      const float* fnorm, const float* dfn, float* d_features, float* d_gate,
+                      hipStream_t st);
 
 void raster_forward(const RasterArgs& a, hipStream_t st);
 void raster_backward(const RasterArgs& a, hipStream_t st);

@@ -33,6 +33,7 @@ struct SavedKey {
   const void* ptrs[6] = {};
   std::vector<g4d_view> views;
   g4d_settings s{};
+  g4d_channels ch{};  // n_features = depth = flow = 0 for a plain forward
 };
 
 }  // namespace
@@ -42,6 +43,7 @@ struct g4d_ctx {
   std::string err;
   DevBuf views, tile_base, rec, tiles, dkey, vk[2], vv[2], voff, pk[2], pv[2], scan_tmp,
       sort_tmp, ranges, px_T, px_last, px_evals, grad2d, counters;
+  DevBuf fn, fnorm, flow, dfn;     // extra channels
   uint32_t* h_counters = nullptr;  // pinned: visible, pairs, overflow
   DView* h_views = nullptr;        // pinned staging
   int32_t* h_tile_base = nullptr;  // pinned staging
@@ -205,6 +207,30 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
   if (s->tile_size == 8 && s->px_per_lane > 1)
     return fail(ctx, G4D_EINVAL, "px_per_lane %d needs tile_size >= 16", s->px_per_lane);
   return G4D_OK;
+}
+
+int n_ext_of(const g4d_channels* ch) {
+  return ch ? ch->n_features + (ch->depth ? 1 : 0) + (ch->flow ? 2 : 0) : 0;
+}
+
+g4d_status check_channels(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_channels* ch) {
+  if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
+  if (ch->n_features < 0) return fail(ctx, G4D_EINVAL, "n_features %d < 0", ch->n_features);
+  if ((ch->depth != 0 && ch->depth != 1) || (ch->flow != 0 && ch->flow != 1))
+    return fail(ctx, G4D_EINVAL, "depth and flow must be 0 or 1");
+  const int E = n_ext_of(ch);
+  if (E < 1 || E > G4D_MAX_CHANNELS)
+    return fail(ctx, G4D_EINVAL, "%d extra channels outside 1..%d", E, G4D_MAX_CHANNELS);
+  if (ch->n_features > 0 && g->n > 0 && !ch->features)
+    return fail(ctx, G4D_EINVAL, "null features");
+  if (ch->flow && !finite(ch->flow_dt)) return fail(ctx, G4D_EINVAL, "flow_dt not finite");
+  return G4D_OK;
+}
+
+bool same_channels(const g4d_channels& a, const g4d_channels& b) {
+  return a.n_features == b.n_features && a.features == b.features && a.gate == b.gate &&
+         a.depth == b.depth && a.flow == b.flow &&
+         (!a.flow || std::memcmp(&a.flow_dt, &b.flow_dt, sizeof(float)) == 0);
 }
 
 DSettings device_settings(const g4d_settings* s) {
@@ -385,7 +411,8 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
                     &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->voff,
                     &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
                     &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
-                    &ctx->grad2d, &ctx->counters};
+                    &ctx->grad2d, &ctx->counters, &ctx->fn, &ctx->fnorm, &ctx->flow,
+                    &ctx->dfn};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
@@ -425,18 +452,30 @@ g4d_status g4d_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* 
   return G4D_OK;
 }
 
-g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
-                              int32_t n_views, const g4d_settings* s, float* out_rgb,
-                              float* out_T, void* stream) {
+// Forward of the whole batch; with ch, also the extra channels into out_ch.
+static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                               int32_t n_views, const g4d_settings* s, const g4d_channels* ch,
+                               float* out_rgb, float* out_T, float* out_ch, void* stream) {
   g4d_status r = check_common(ctx, g, views, n_views, s);
   if (r != G4D_OK) return r;
   if (!out_rgb) return fail(ctx, G4D_EINVAL, "null out_rgb");
+  if (ch) {
+    if ((r = check_channels(ctx, g, ch)) != G4D_OK) return r;
+    if (!out_ch) return fail(ctx, G4D_EINVAL, "null out_ch");
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   G4D_HIP(hipSetDevice(ctx->device));
   ctx->saved = false;
   if ((r = upload_views(ctx, views, n_views, s, st)) != G4D_OK) return r;
   const int64_t slots = (int64_t)g->n * n_views;
-  const DSettings DS = device_settings(s);
+  // the extra-channel raster runs one pixel per lane with 64-entry batches
+  g4d_settings s_run = *s;
+  if (ch) {
+    s_run.px_per_lane = 1;
+    s_run.lds_batch = 64;
+  }
+  const DSettings DS = device_settings(&s_run);
+  const int n_ext = n_ext_of(ch);
   if ((r = ensure(ctx, ctx->counters, 4 * sizeof(uint32_t))) != G4D_OK) return r;
   // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity
   uint32_t* cnt = P<uint32_t>(ctx->counters);
@@ -451,7 +490,19 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   int64_t n_vis = 0, n_pairs = 0;
   int pb = 0;
   if (slots > 0) {
-    if ((r = run_preprocess(ctx, g, n_views, s, st)) != G4D_OK) return r;
+    if ((r = run_preprocess(ctx, g, n_views, &s_run, st)) != G4D_OK) return r;
+    if (ch && ch->n_features > 0) {
+      if ((r = ensure(ctx, ctx->fn, sizeof(float) * (size_t)g->n * ch->n_features, 1.1)) != G4D_OK)
+        return r;
+      if ((r = ensure(ctx, ctx->fnorm, sizeof(float) * (size_t)g->n, 1.1)) != G4D_OK) return r;
+      feature_normalize(g->n, ch->n_features, ch->features, ch->gate, P<float>(ctx->fn),
+                        P<float>(ctx->fnorm), st);
+    }
+    if (ch && ch->flow) {
+      if ((r = ensure(ctx, ctx->flow, sizeof(float) * 2 * slots, 1.1)) != G4D_OK) return r;
+      flow_forward(gauss_ptrs(g), P<DView>(ctx->views), n_views, P<uint32_t>(ctx->tiles),
+                   ch->flow_dt, P<float>(ctx->flow), st);
+    }
     for (int b = 0; b < 2; ++b) {
       if ((r = ensure(ctx, ctx->vk[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
       if ((r = ensure(ctx, ctx->vv[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
@@ -540,7 +591,17 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   a.out_T = out_T;
   a.px_T = P<float>(ctx->px_T);
   a.px_last = P<int32_t>(ctx->px_last);
-  a.px_evals = ctx->count_evals ? P<uint32_t>(ctx->px_evals) : nullptr;
+  a.px_evals = (ctx->count_evals && !ch) ? P<uint32_t>(ctx->px_evals) : nullptr;
+  if (ch) {
+    a.n_ext = n_ext;
+    a.n_feat = ch->n_features;
+    a.has_depth = ch->depth;
+    a.has_flow = ch->flow;
+    a.n_gauss = g->n;
+    a.fn = P<float>(ctx->fn);
+    a.flow = P<float>(ctx->flow);
+    a.out_ch = out_ch;
+  }
   {
     Stage t(ctx, 7, st);
     raster_forward(a, st);
@@ -563,27 +624,48 @@ g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_vi
   for (int i = 0; i < 6; ++i) k.ptrs[i] = p[i];
   k.views.assign(views, views + n_views);
   k.s = *s;
+  k.ch = ch ? *ch : g4d_channels{};
   ctx->saved = true;
   return G4D_OK;
 }
 
-g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
-                               int32_t n_views, const g4d_settings* s, const float* dL_drgb,
-                               const g4d_grads* out, void* stream) {
+// Backward of the last forward; with ch (which must match that forward's), also the extra
+// channels' contributions and the feature and gate gradients.
+static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                                int32_t n_views, const g4d_settings* s, const g4d_channels* ch,
+                                const float* dL_drgb, const float* dL_dch, const g4d_grads* out,
+                                float* d_features, float* d_gate, void* stream) {
   g4d_status r = check_common(ctx, g, views, n_views, s);
   if (r != G4D_OK) return r;
   if (!dL_drgb || !out) return fail(ctx, G4D_EINVAL, "null dL_drgb or grads");
-  if (!ctx->saved || !same_key(ctx->key, g, views, n_views, s))
+  if (ch) {
+    if ((r = check_channels(ctx, g, ch)) != G4D_OK) return r;
+    if (ch->n_features > 0 && g->n > 0 && !d_features)
+      return fail(ctx, G4D_EINVAL, "null d_features");
+  }
+  if (!ctx->saved || !same_key(ctx->key, g, views, n_views, s) ||
+      (ch && !same_channels(ctx->key.ch, *ch)))
     return fail(ctx, G4D_ESTATE, "backward without a matching forward on this context");
   hipStream_t st = static_cast<hipStream_t>(stream);
   G4D_HIP(hipSetDevice(ctx->device));
   const int64_t slots = (int64_t)g->n * n_views;
+  const int D = ch ? ch->n_features : 0;
+  if (d_gate && D > 0) fill_u32(reinterpret_cast<uint32_t*>(d_gate), D, 0u, st);
   if (slots == 0) return G4D_OK;
-  const DSettings DS = device_settings(s);
+  g4d_settings s_run = *s;
+  if (ch) {
+    s_run.px_per_lane = 1;
+    s_run.lds_batch = 64;
+  }
+  const DSettings DS = device_settings(&s_run);
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
   {
     Stage t(ctx, 8, st);
     fill_u32(P<uint32_t>(ctx->grad2d), kGrad2d * slots, 0u, st);
+  }
+  if (D > 0) {
+    if ((r = ensure(ctx, ctx->dfn, sizeof(float) * (size_t)g->n * D, 1.1)) != G4D_OK) return r;
+    fill_u32(P<uint32_t>(ctx->dfn), (int64_t)g->n * D, 0u, st);
   }
   if (ctx->stats.n_pairs > 0 || ctx->capturing) {
     RasterArgs a{};
@@ -599,6 +681,17 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     a.px_last = P<int32_t>(ctx->px_last);
     a.dL = dL_drgb;
     a.grad2d = P<float>(ctx->grad2d);
+    if (ch) {
+      a.n_ext = n_ext_of(ch);
+      a.n_feat = D;
+      a.has_depth = ch->depth;
+      a.has_flow = ch->flow;
+      a.n_gauss = g->n;
+      a.fn = P<float>(ctx->fn);
+      a.flow = P<float>(ctx->flow);
+      a.dL_ch = dL_dch;
+      a.dfn = P<float>(ctx->dfn);
+    }
     Stage t(ctx, 9, st);
     raster_backward(a, st);
     G4D_HIP(hipGetLastError());
@@ -609,8 +702,45 @@ g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
                         P<float>(ctx->grad2d), gp, st);
   }
+  if (D > 0)
+    feature_backward(g->n, D, ch->features, ch->gate, P<float>(ctx->fn), P<float>(ctx->fnorm),
+                     P<float>(ctx->dfn), d_features, d_gate, st);
   G4D_HIP(hipGetLastError());
   return G4D_OK;
+}
+
+g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                              int32_t n_views, const g4d_settings* s, float* out_rgb,
+                              float* out_T, void* stream) {
+  return forward_impl(ctx, g, views, n_views, s, nullptr, out_rgb, out_T, nullptr, stream);
+}
+
+g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                               int32_t n_views, const g4d_settings* s, const float* dL_drgb,
+                               const g4d_grads* out, void* stream) {
+  return backward_impl(ctx, g, views, n_views, s, nullptr, dL_drgb, nullptr, out, nullptr,
+                       nullptr, stream);
+}
+
+g4d_status g4d_render_channels_forward(g4d_ctx* ctx, const g4d_gaussians* g,
+                                       const g4d_view* views, int32_t n_views,
+                                       const g4d_settings* s, const g4d_channels* ch,
+                                       float* out_rgb, float* out_T, float* out_ch, void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
+  return forward_impl(ctx, g, views, n_views, s, ch, out_rgb, out_T, out_ch, stream);
+}
+
+g4d_status g4d_render_channels_backward(g4d_ctx* ctx, const g4d_gaussians* g,
+                                        const g4d_view* views, int32_t n_views,
+                                        const g4d_settings* s, const g4d_channels* ch,
+                                        const float* dL_drgb, const float* dL_dch,
+                                        const g4d_grads* out, float* d_features, float* d_gate,
+                                        void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
+  return backward_impl(ctx, g, views, n_views, s, ch, dL_drgb, dL_dch, out, d_features, d_gate,
+                       stream);
 }
 
 g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,

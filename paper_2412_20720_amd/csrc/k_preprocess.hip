@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     if (tiles[slot] == 0u) continue;
     const float4* gp = reinterpret_cast<const float4*>(grad2d + slot * kGrad2d);
     const float4 q0 = gp[0], q1 = gp[1], q2 = gp[2];
-    const float q[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x};
+    const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
     const DView& V = views[v];
     ViewFwd f;
     view_forward<false>(g, mean, V, S, f);

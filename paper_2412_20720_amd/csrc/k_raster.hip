@@ -20,6 +20,12 @@
 // the conic and opacity p_t.  A lane first adds the contributions of its own pixels; the nine
 // per-Gaussian values are then summed over the wave by a permlane-swap transpose-reduce and
 // one vector atomic (nine lanes) adds them to the (view, Gaussian) gradient slot.
+//
+// Extra channels (CX > 0, one pixel per lane): each staged entry also carries CX payload values
+// (normalized features, camera depth, flow; zero padding) in a second wave-private LDS array;
+// they are composited with the same weights, add g_x . payload to g . c in the backward, and
+// their per-entry partials are reduced like the nine above and added to the feature and depth
+// gradients.
 #include <hip/hip_runtime.h>
 
 #include "g4d_internal.h"
@@ -164,6 +170,29 @@ __device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& 
   return n;
 }
 
+// Copy the CX payload values of the n staged entries into xp[k * CX + c] (all lanes; the
+// caller synchronizes the wave before and after).
+template <int CX>
+__device__ __forceinline__ void stage_payload(const RasterArgs& a, const WaveTile& t,
+                                              const Staged* st, int n, float* xp) {
+  const size_t vbase = (size_t)t.v * (size_t)a.n_gauss;
+  for (int idx = t.lane; idx < n * CX; idx += 64) {
+    const int k = idx / CX, c = idx - k * CX;
+    const size_t slot = __float_as_uint(st[k].c.z);
+    float val = 0.f;
+    if (c < a.n_feat) {
+      val = a.fn[(slot - vbase) * (size_t)a.n_feat + c];
+    } else if (c < a.n_ext) {
+      const int e = c - a.n_feat;
+      if (a.has_depth && e == 0)
+        val = a.rec[slot * kRec + 11];
+      else
+        val = a.flow[slot * 2 + (e - a.has_depth)];
+    }
+    xp[idx] = val;
+  }
+}
+
 // A lane owns PXX x PXY pixels of its wave's (8 PXX) x (8 PXY) block: (lane % 8 + 8 a,
 // lane / 8 + 8 b), a < PXX, b < PXY.  Pixel p = b * PXX + a.
 template <int PXX, int PXY>
@@ -188,11 +217,16 @@ struct LanePixels {
 // from the range where the library version adds denormal handling.
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-template <int TILE, int BATCH, int PXX, int PXY, bool COUNT>
+template <int TILE, int BATCH, int PXX, int PXY, bool COUNT, int CX>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
+  static_assert(CX == 0 || P == 1, "extra channels use one pixel per lane");
   constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
   __shared__ Staged stage[4][BATCH];
+  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
+  float X[CX > 0 ? CX : 1];
+#pragma unroll
+  for (int c = 0; c < (CX > 0 ? CX : 1); ++c) X[c] = 0.f;
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
@@ -220,10 +254,15 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   }
   bool done = __ballot(any_live) == 0ull;
   Staged* st = stage[t.w];
+  float* xp = xstage[t.w];
   const int end = (int)t.range.y;
   for (int base = (int)t.range.x; base < end && !done; base += BATCH) {
     const int n = stage_batch<BATCH>(a, t, base, end, st);
     G4D_WAVE_SYNC();
+    if constexpr (CX > 0) {
+      stage_payload<CX>(a, t, st, n, xp);
+      G4D_WAVE_SYNC();
+    }
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
@@ -256,6 +295,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           C0[p] = fmaf(wgt, e1.z, C0[p]);
           C1[p] = fmaf(wgt, e1.w, C1[p]);
           C2[p] = fmaf(wgt, e2.x, C2[p]);
+          if constexpr (CX > 0) {
+            const float* xk = xp + k * CX;
+#pragma unroll
+            for (int c = 0; c < CX; ++c) X[c] = fmaf(wgt, xk[c], X[c]);
+          }
           T[p] = take ? Tn : T[p];
           last[p] = take ? __float_as_int(e2.y) : last[p];
           lo[p] = stop ? INFINITY : lo[p];
@@ -290,6 +334,12 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     a.px_T[gp] = T[p];
     a.px_last[gp] = last[p];
     if (COUNT) a.px_evals[gp] = min(evals[p], 65535u) | (min(contrib[p], 65535u) << 16);
+    if constexpr (CX > 0) {
+      float* o = a.out_ch + (size_t)a.n_ext * (size_t)V.pix_base + pix;
+#pragma unroll
+      for (int c = 0; c < CX; ++c)
+        if (c < a.n_ext) o[(size_t)c * hw] = X[c];
+    }
   }
 }
 
@@ -332,17 +382,30 @@ __device__ __forceinline__ float wave_reduce9(const float* q, int lane, int& fie
   return i == 0 ? F : (i == 1 ? G : H);
 }
 
+// Transpose-reduce of N (a multiple of 4) per-lane values: r[j] then holds, in every lane of
+// row `row` (lane / 16), the wave total of value 4 j + [0, 2, 1, 3][row].
+template <int N>
+__device__ __forceinline__ void wave_reduce_rows(const float* q, float* r) {
+#pragma unroll
+  for (int j = 0; j < N / 4; ++j)
+    r[j] = row_sum(fold16(fold32(q[4 * j], q[4 * j + 1]), fold32(q[4 * j + 2], q[4 * j + 3])));
+}
+
 // Backward.  Per pixel the walk keeps T (transmittance in front of the entry, rebuilt by
 // division) and gR = g . R (the upstream gradient dotted with the color behind the entry):
 //   dL/dalpha = T_i (g . c_i - gR),  gR <- alpha (g . c_i) + (1 - alpha) gR.
 // Per Gaussian the wave accumulates q = [dL/du, dL/dv, S_xx, S_xy, S_yy, dL/d(opacity p_t),
 // dL/drgb] with S_.. the second moments of (dx, dy) weighted by dL/dalpha alpha; after the
 // reduction they become dL/da = -S_xx / 2, dL/db = -S_xy, dL/dc = -S_yy / 2.
-template <int TILE, int BATCH, int PXX, int PXY>
+template <int TILE, int BATCH, int PXX, int PXY, int CX>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
+  static_assert(CX == 0 || P == 1, "extra channels use one pixel per lane");
+  static_assert(CX % 4 == 0, "extra channels come in groups of four");
   constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
   __shared__ Staged stage[4][BATCH];
+  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
+  float gx[CX > 0 ? CX : 1];  // upstream gradient of the extra channels (0: flow, padding)
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
@@ -379,6 +442,15 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
       g1[p] = dl[hw + pix];
       g2[p] = dl[2 * hw + pix];
     }
+    if constexpr (CX > 0) {
+      const int n_grad = a.n_feat + a.has_depth;
+      const float* dxp = a.dL_ch ? a.dL_ch + (size_t)a.n_ext * (size_t)V.pix_base +
+                                       (size_t)L.py[p] * V.width + L.px[p]
+                                 : nullptr;
+#pragma unroll
+      for (int c = 0; c < CX; ++c)
+        gx[c] = (dxp && L.inside[p] && c < n_grad) ? dxp[(size_t)c * hw] : 0.f;
+    }
     gR[p] = fmaf(g0[p], V.bg[0], fmaf(g1[p], V.bg[1], g2[p] * V.bg[2]));
     lane_last = max(lane_last, last[p]);
   }
@@ -386,14 +458,22 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   if (hi_last < 0) return;
   const float lo_cut = kNegHalfLog2e * S.cut2;
   Staged* st = stage[t.w];
+  float* xp = xstage[t.w];
   const int lo_list = (int)t.range.x;
   for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
     const int lo = max(lo_list, hi - BATCH);
     const int n = stage_batch<BATCH>(a, t, lo, hi, st);
     G4D_WAVE_SYNC();
+    if constexpr (CX > 0) {
+      stage_payload<CX>(a, t, st, n, xp);
+      G4D_WAVE_SYNC();
+    }
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
       const int jk = __float_as_int(e2.y);
+      float qx[CX > 0 ? CX : 1];
+#pragma unroll
+      for (int c = 0; c < (CX > 0 ? CX : 1); ++c) qx[c] = 0.f;
       // Per pixel the lane adds sa = alpha dL/dalpha (unclamped branch only) into the moments
       // q[0..5] = sum sa [rx, ry, rx^2, rx ry, ry^2, 1] of the block-centred pixel position
       // and the color partials into q[6..8]; once per entry they are turned into the
@@ -433,7 +513,17 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           q[6] = fmaf(g0[p], wgt, q[6]);
           q[7] = fmaf(g1[p], wgt, q[7]);
           q[8] = fmaf(g2[p], wgt, q[8]);
-          const float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
+          float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
+          if constexpr (CX > 0) {
+            const float* xk = xp + k * CX;
+            float gcx = 0.f;
+#pragma unroll
+            for (int c = 0; c < CX; ++c) {
+              gcx = fmaf(gx[c], xk[c], gcx);
+              qx[c] = fmaf(gx[c], wgt, qx[c]);
+            }
+            gc += gcx;
+          }
           const float diff = gc - gR[p];
           gR[p] = fmaf(alpha, diff, gR[p]);
           // dL/dalpha = Tb diff, so sa = alpha dL/dalpha = wgt diff
@@ -472,13 +562,29 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           const uint32_t slot = __float_as_uint(e2.z);
           unsafeAtomicAdd(a.grad2d + (size_t)slot * kGrad2d + field, val);
         }
+        if constexpr (CX > 0) {
+          float r[CX / 4];
+          wave_reduce_rows<CX>(qx, r);
+          const int row = t.lane >> 4, i = t.lane & 15;
+          float v = r[0];
+#pragma unroll
+          for (int j = 1; j < CX / 4; ++j) v = (i == j) ? r[j] : v;
+          const int c = 4 * i + (((row & 1) << 1) | (row >> 1));
+          const size_t slot = __float_as_uint(e2.z);
+          if (i < CX / 4 && c < a.n_feat) {
+            const size_t gi = slot - (size_t)t.v * (size_t)a.n_gauss;
+            unsafeAtomicAdd(a.dfn + gi * (size_t)a.n_feat + c, v);
+          } else if (i < CX / 4 && a.has_depth && c == a.n_feat) {
+            unsafeAtomicAdd(a.grad2d + slot * kGrad2d + G_DEPTH, v);
+          }
+        }
       }
     }
     G4D_WAVE_SYNC();
   }
 }
 
-template <int TILE, int BATCH, int PXX, int PXY>
+template <int TILE, int BATCH, int PXX, int PXY, int CX = 0>
 void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
   constexpr int QPT = (TILE / (8 * PXX)) * (TILE / (8 * PXY));
   const int64_t waves = (int64_t)a.n_tiles * QPT;
@@ -488,11 +594,23 @@ void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
   b.blocks_per_xcd = (int)((blocks + 7) / 8);
   const unsigned grid = 8u * (unsigned)b.blocks_per_xcd;
   if (backward)
-    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY>), dim3(grid), dim3(256), 0, st, b);
-  else if (b.px_evals)
-    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, true>), dim3(grid), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY, CX>), dim3(grid), dim3(256), 0, st, b);
+  else if (CX == 0 && b.px_evals)
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, true, 0>), dim3(grid), dim3(256), 0, st,
+                       b);
   else
-    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, false>), dim3(grid), dim3(256), 0, st, b);
+    hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, false, CX>), dim3(grid), dim3(256), 0,
+                       st, b);
+}
+
+// Extra channels: one pixel per lane, 64-entry batches, CX the smallest supported payload width
+// that holds the E channels (the rest is zero padding).
+template <int TILE>
+void dispatch_ext(const RasterArgs& a, hipStream_t st, bool backward) {
+  if (a.n_ext <= 4) launch_raster<TILE, 64, 1, 1, 4>(a, st, backward);
+  else if (a.n_ext <= 8) launch_raster<TILE, 64, 1, 1, 8>(a, st, backward);
+  else if (a.n_ext <= 16) launch_raster<TILE, 64, 1, 1, 16>(a, st, backward);
+  else launch_raster<TILE, 64, 1, 1, 36>(a, st, backward);
 }
 
 template <int TILE, int PXX, int PXY>
@@ -514,6 +632,14 @@ void dispatch_px(const RasterArgs& a, hipStream_t st, bool backward) {
 }
 
 void dispatch(const RasterArgs& a, hipStream_t st, bool backward) {
+  if (a.n_ext > 0) {
+    switch (a.S.tile) {
+      case 8: dispatch_ext<8>(a, st, backward); break;
+      case 32: dispatch_ext<32>(a, st, backward); break;
+      default: dispatch_ext<16>(a, st, backward); break;
+    }
+    return;
+  }
   switch (a.S.tile) {
     case 8: dispatch_batch<8, 1, 1>(a, st, backward); break;
     case 32: dispatch_px<32>(a, st, backward); break;

@@ -82,6 +82,39 @@ class Renderer:
         B.check(B.lib().g4d_render_backward(self._ctx, C.byref(g), va, len(va), C.byref(settings),
                                             dL.data_ptr(), C.byref(gr), st), self._ctx)
 
+    @staticmethod
+    def channels(features: Optional[torch.Tensor] = None, gate: Optional[torch.Tensor] = None,
+                 depth: bool = False, flow: bool = False, flow_dt: float = 0.0) -> B.g4d_channels:
+        """Extra-channel spec: features [N, D] (float32, contiguous, on the device) gated by
+        `gate` [D] and normalized, then depth, then the two flow channels."""
+        D = 0 if features is None else int(features.shape[1])
+        return B.g4d_channels(D, None if features is None else features.data_ptr(),
+                              None if gate is None else gate.data_ptr(), int(depth), int(flow),
+                              float(flow_dt))
+
+    def forward_channels(self, g: B.g4d_gaussians, views, settings: B.g4d_settings,
+                         ch: B.g4d_channels, out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
+                         out_ch: torch.Tensor) -> None:
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        B.check(B.lib().g4d_render_channels_forward(
+            self._ctx, C.byref(g), va, len(va), C.byref(settings), C.byref(ch), out_rgb.data_ptr(),
+            None if out_T is None else out_T.data_ptr(), out_ch.data_ptr(),
+            _stream_handle(self.device)), self._ctx)
+
+    def backward_channels(self, g: B.g4d_gaussians, views, settings: B.g4d_settings,
+                          ch: B.g4d_channels, dL: torch.Tensor, dL_ch: Optional[torch.Tensor],
+                          grads: Dict[str, torch.Tensor]) -> None:
+        """grads: the parameter groups plus "features" [N, D] and "gate" [D] (optional)."""
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        gr = B.g4d_grads(*[grads[k].data_ptr() if grads.get(k) is not None else None
+                           for k in PARAM_NAMES])
+        df, dg = grads.get("features"), grads.get("gate")
+        B.check(B.lib().g4d_render_channels_backward(
+            self._ctx, C.byref(g), va, len(va), C.byref(settings), C.byref(ch), dL.data_ptr(),
+            None if dL_ch is None else dL_ch.data_ptr(), C.byref(gr),
+            None if df is None else df.data_ptr(), None if dg is None else dg.data_ptr(),
+            _stream_handle(self.device)), self._ctx)
+
     def step(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
              out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
              grads: Dict[str, torch.Tensor], graph: bool = True) -> None:
@@ -174,6 +207,43 @@ class _Render4D(torch.autograd.Function):
         return (None, None, None, None, None) + tuple(grads[k] for k in PARAM_NAMES)
 
 
+class _RenderChannels(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, depth, flow,
+                flow_dt, mean4, scale4, rot_l, rot_r, opacity, sh, features, gate):
+        g = renderer.gaussians(mean4, scale4, rot_l, rot_r, opacity, sh, sh_degree, t_degree)
+        va = B.make_views(views)
+        npix = Renderer.pixel_count(views)
+        ch = Renderer.channels(features, gate, depth, flow, flow_dt)
+        E = ch.n_features + int(depth) + 2 * int(flow)
+        rgb = torch.empty(3 * npix, device=renderer.device)
+        T = torch.empty(npix, device=renderer.device)
+        out = torch.empty(E * npix, device=renderer.device)
+        renderer.forward_channels(g, va, settings, ch, rgb, T, out)
+        ctx.renderer, ctx.views, ctx.settings = renderer, va, settings
+        ctx.degrees = (sh_degree, t_degree)
+        ctx.spec = (depth, flow, flow_dt)
+        ctx.save_for_backward(mean4, scale4, rot_l, rot_r, opacity, sh, features, gate)
+        ctx.mark_non_differentiable(T)
+        return rgb, T, out
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_T, d_ch):
+        *params, features, gate = ctx.saved_tensors
+        r: Renderer = ctx.renderer
+        g = r.gaussians(*params, *ctx.degrees)
+        ch = Renderer.channels(features, gate, *ctx.spec)
+        grads = {k: torch.empty_like(p) for k, p in zip(PARAM_NAMES, params)}
+        if features is not None:
+            grads["features"] = torch.empty_like(features)
+            if gate is not None:
+                grads["gate"] = torch.empty_like(gate)
+        r.backward_channels(g, ctx.views, ctx.settings, ch, d_rgb.contiguous(),
+                            None if d_ch is None else d_ch.contiguous(), grads)
+        return ((None,) * 8 + tuple(grads[k] for k in PARAM_NAMES) +
+                (grads.get("features"), grads.get("gate")))
+
+
 def split_views(flat: torch.Tensor, views, channels: int) -> List[torch.Tensor]:
     out, off = [], 0
     for v in views:
@@ -193,3 +263,27 @@ def render(mean4, scale4, rot_l, rot_r, opacity, sh, views: Sequence[dict], *, s
     rgb, T = _Render4D.apply(renderer, list(views), s, sh_degree, t_degree, mean4, scale4, rot_l,
                              rot_r, opacity, sh)
     return split_views(rgb, views, 3), [t[0] for t in split_views(T, views, 1)]
+
+
+def render_channels(mean4, scale4, rot_l, rot_r, opacity, sh, views: Sequence[dict], *,
+                    sh_degree: int, t_degree: int, renderer: Renderer,
+                    features: Optional[torch.Tensor] = None, gate: Optional[torch.Tensor] = None,
+                    depth: bool = False, flow: bool = False, flow_dt: float = 0.0,
+                    settings: Optional[B.g4d_settings] = None):
+    """Differentiable render with extra channels (normalized gated features, depth, flow).
+
+    Returns (images, transmittances, channels): per view [3, H, W], [H, W] and [E, H, W] with
+    E = D + depth + 2 flow (features first).  Gradients reach the parameters, the features and
+    the gate; the flow channels carry none.
+    """
+    s = settings if settings is not None else B.default_settings()
+    if features is not None:
+        features = features.contiguous()
+    if gate is not None:
+        gate = gate.contiguous()
+    E = (0 if features is None else int(features.shape[1])) + int(depth) + 2 * int(flow)
+    rgb, T, ch = _RenderChannels.apply(renderer, list(views), s, sh_degree, t_degree, depth, flow,
+                                       flow_dt, mean4, scale4, rot_l, rot_r, opacity, sh,
+                                       features, gate)
+    return (split_views(rgb, views, 3), [t[0] for t in split_views(T, views, 1)],
+            split_views(ch, views, E))

@@ -227,6 +227,26 @@ def make_dl_dimage(scene: Scene, seed: int = 7) -> List[np.ndarray]:
     return [rng.normal(size=(3, v["height"], v["width"])).astype(np.float32) for v in scene.views]
 
 
+def make_features(scene: Scene, dim: int = 32, seed: int = 11) -> np.ndarray:
+    """Per-Gaussian feature vectors f ~ N(0, 1), [N, dim] float32 (the segmentation features
+    are learned; D = 32 as in the paper's segmentation experiments)."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(scene.n, dim)).astype(np.float32)
+
+
+def make_gate(dim: int = 32, seed: int = 12) -> np.ndarray:
+    """A scale gate S(s) in [0, 1]^dim, float32."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, dim).astype(np.float32)
+
+
+def make_dl_dchannels(scene: Scene, n_channels: int, seed: int = 13) -> List[np.ndarray]:
+    """Upstream dL/d(extra channels) ~ N(0,1) per view, planar [E, H, W] float32."""
+    rng = np.random.default_rng(seed)
+    return [rng.normal(size=(n_channels, v["height"], v["width"])).astype(np.float32)
+            for v in scene.views]
+
+
 def subset(scene: Scene, idx) -> Scene:
     """Scene restricted to the Gaussians ``idx`` (same views)."""
     idx = np.asarray(idx)
