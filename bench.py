@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=1)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--channels", type=int, default=32, metavar="D",
+                    help="also time the render with D feature channels + depth + flow "
+                         "(-1: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +191,10 @@ def main():
                         batched_speedup=dpv / dt)
         log(f"bench: per-view {dpv * 1e3:.3f} ms/step, {npix / dpv / 1e6:.1f} Mpix/s")
 
+    chan = None
+    if args.channels >= 0:
+        chan = channel_step(r, g, views, settings, sc, p, dL, args, npix)
+
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
     per_comp = BWD_FLOPS_PER_COMPOSITED if dom == "raster_bwd" else FWD_FLOPS_PER_COMPOSITED
@@ -224,6 +231,7 @@ def main():
         "graph": graph,
         "roofline": roofline,
         "alg_bound": alg_bound,
+        "channels": chan,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
                  "evaluated_pairs": evals, "composited_pairs": contrib},
@@ -231,6 +239,50 @@ def main():
     }
     print(json.dumps(out), flush=True)
     r.close()
+
+
+def channel_step(r, g, views, settings, sc, p, dL, args, npix):
+    """Forward + backward with D normalized gated feature channels, depth and flow (the extra
+    channels of the 4D segmentation, depth and flow renders), on the same workload."""
+    import torch
+    from paper_2412_20720_amd import scenes
+    from paper_2412_20720_amd.frontend import Renderer
+    dev = p["mean4"].device
+    D = args.channels
+    feats = torch.from_numpy(scenes.make_features(sc, D)).to(dev) if D else None
+    gate = torch.from_numpy(scenes.make_gate(D)).to(dev) if D else None
+    ch = Renderer.channels(feats, gate, True, True, 0.05)
+    E = D + 3
+    rgb = torch.empty(3 * npix, device=dev)
+    T = torch.empty(npix, device=dev)
+    out = torch.empty(E * npix, device=dev)
+    dX = torch.from_numpy(np.concatenate([d.reshape(-1) for d in scenes.make_dl_dchannels(sc, E)])).to(dev)
+    grads = {k: torch.empty_like(p[k]) for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")}
+    if D:
+        grads["features"] = torch.empty_like(feats)
+        grads["gate"] = torch.empty_like(gate)
+
+    def step():
+        r.forward_channels(g, views, settings, ch, rgb, T, out)
+        r.backward_channels(g, views, settings, ch, dL, dX, grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    r.profile(True, collect=True, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stages = r.profile(False, collect=True, reset=True)
+    r.sync()
+    st = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
+    log(f"bench: channels D={D} + depth + flow: {dt * 1e3:.3f} ms/step, {npix / dt / 1e6:.1f} Mpix/s "
+        f"(raster_fwd {st.get('raster_fwd', 0):.3f} ms, raster_bwd {st.get('raster_bwd', 0):.3f} ms)")
+    return dict(features=D, depth=True, flow=True, flow_dt=0.05, value=npix / dt / 1e6,
+                unit="Mpix/s", ms_per_step=dt * 1e3, stages_ms=st)
 
 
 def cpu_baseline(sc, n_views):
