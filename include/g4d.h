@@ -81,7 +81,7 @@ typedef struct {
 } g4d_view;
 
 /* (host) Render settings.  The paper leaves these unstated except the marginal filter
- * (p(t) threshold, Sec. 4.1.1 implementation details); g4d_default_settings fills in:
+ * (p(t) threshold, Sec. 8.1 implementation details); g4d_default_settings fills in:
  *   near_z 0.2        cull when the camera-space depth of the sliced mean is <= near_z
  *   marginal_min 1/255 cull when p(t) < marginal_min (the paper quotes 0.05)
  *   cutoff_sigma 3    a splat covers pixels with Mahalanobis distance <= cutoff_sigma
@@ -159,9 +159,9 @@ g4d_status g4d_render_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_v
                                int32_t n_views, const g4d_settings *s, const float *dL_drgb,
                                const g4d_grads *out, void *stream);
 
-/* Extra channels rendered with the same weights T alpha as the image (Sec. 3.4: the 2D feature
- * map of 4D segmentation, the color replaced by the normalized scale-gated feature, and the
- * rendered depth of the urban LiDAR loss; Sec. 4.1.3: the rendered optical flow, the image
+/* Extra channels rendered with the same weights T alpha as the image (Sec. 7: the 2D feature
+ * map of 4D segmentation, the color replaced by the normalized scale-gated feature; Sec. 5: the
+ * rendered depth of the urban LiDAR loss; Sec. 8.1: the rendered optical flow, the image
  * displacement of each conditional mean between t and t + flow_dt).  The channels of a pixel
  * are, in order: n_features feature channels, then the depth channel (if depth), then du, dv
  * (if flow); E = n_features + depth + 2 flow <= G4D_MAX_CHANNELS.  Their background is 0.

@@ -37,12 +37,12 @@ SMOOTH_SETTINGS = dict(DEFAULT_SETTINGS, cutoff_sigma=5.0, alpha_min=1e-6, T_min
 
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with g++ (-O2, OpenMP)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", LIB_PATH + ".tmp",
-           SRC_PATH]
+    tmp = f"{LIB_PATH}.tmp{os.getpid()}"  # one per process: parallel test workers may build
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC_PATH]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
 
@@ -50,7 +50,8 @@ class _Gaussians(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("t_degree", C.c_int32),
                 ("mean4", C.POINTER(C.c_double)), ("scale4", C.POINTER(C.c_double)),
                 ("rot_l", C.POINTER(C.c_double)), ("rot_r", C.POINTER(C.c_double)),
-                ("opacity", C.POINTER(C.c_double)), ("sh", C.POINTER(C.c_double))]
+                ("opacity", C.POINTER(C.c_double)), ("sh", C.POINTER(C.c_double)),
+                ("mask", C.POINTER(C.c_double)), ("mask_threshold", C.c_double)]
 
 
 class _View(C.Structure):
@@ -71,7 +72,7 @@ class _Settings(C.Structure):
 
 class _Grads(C.Structure):
     _fields_ = [(k, C.POINTER(C.c_double)) for k in
-                ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")]
+                ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh", "mask", "densify")]
 
 
 class _Channels(C.Structure):
@@ -166,7 +167,8 @@ class Frame:
 
     def __init__(self, arrays: Dict[str, np.ndarray], sh_degree: int, t_degree: int, view: Dict,
                  settings: Optional[Dict[str, float]] = None, use_bins: bool = True,
-                 exact_f64: bool = False):
+                 exact_f64: bool = False, mask: Optional[np.ndarray] = None,
+                 mask_threshold: float = 0.0):
         st = dict(DEFAULT_SETTINGS)
         if settings:
             st.update(settings)
@@ -178,9 +180,13 @@ class Frame:
         assert self._arrays["sh"].size == self.n * (t_degree + 1) * (sh_degree + 1) ** 2 * 3
         self.view = view
         self.width, self.height = int(view["width"]), int(view["height"])
+        # Volume mask: significance M per Gaussian, kept when M > threshold.
+        self._mask = None if mask is None else conv(mask)
+        thr = float(mask_threshold) if exact_f64 else float(np.float32(mask_threshold))
         g = _Gaussians(self.n, self.sh_degree, self.t_degree,
                        *[_dp(self._arrays[k]) for k in
-                         ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
+                         ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")],
+                       None if self._mask is None else _dp(self._mask), thr)
         conv_s = (lambda x: float(x)) if exact_f64 else (lambda x: float(np.float32(x)))
         v = _View(self.width, self.height, conv_s(view["fx"]), conv_s(view["fy"]),
                   conv_s(view["cx"]), conv_s(view["cy"]),
@@ -277,9 +283,14 @@ class Frame:
                  dL_dext: Optional[np.ndarray] = None):
         """Accumulate d(<dL_drgb, image> + <dL_dext, extra channels>)/d(params) into ``grads``
         (float64; created if None).  With features attached, ``grads`` also receives
-        "features" [n, D] and "gate" [D].  The flow channels of dL_dext are ignored."""
+        "features" [n, D] and "gate" [D].  The flow channels of dL_dext are ignored.  "densify"
+        [n] accumulates |dL/d mean2d| of this view; with a mask, "mask" [n] the
+        straight-through dL/dM."""
         if grads is None:
             grads = {k: np.zeros_like(a) for k, a in self._arrays.items()}
+        grads.setdefault("densify", np.zeros(self.n))
+        if self._mask is not None:
+            grads.setdefault("mask", np.zeros(self.n))
         if self.n_features:
             grads.setdefault("features", np.zeros((self.n, self.n_features)))
             grads.setdefault("gate", np.zeros(self.n_features))
@@ -288,7 +299,9 @@ class Frame:
         if dL_dext is not None and self.n_ext:
             gx = np.ascontiguousarray(dL_dext, np.float64).reshape(self.n_ext, self.height,
                                                                     self.width)
-        gs = _Grads(*[_dp(grads[k]) for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
+        gs = _Grads(*[_dp(grads[k]) for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")],
+                    _dp(grads["mask"]) if self._mask is not None else None,
+                    _dp(grads["densify"]))
         lib().orc_frame_backward(self._h, g.ctypes.data, None if gx is None else gx.ctypes.data,
                                  C.byref(gs),
                                  grads["features"].ctypes.data if self.n_features else None,

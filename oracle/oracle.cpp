@@ -12,7 +12,7 @@
 //   O4  conditional 3D Gaussian and temporal marginal at time t (Sec. 3.2, the conditional mean
 //       and covariance equations and p(t) = N(t; mu_4, Sigma_44)), all unnormalized
 //       (Sec. 3.1, eq. gaussianfunction).
-//   O5  culls: p(t) below the marginal threshold (Sec. 4.1.1 implementation details), then the
+//   O5  culls: p(t) below the marginal threshold (Sec. 8.1 implementation details), then the
 //       near plane.
 //   O6  EWA splatting: mean = Proj(mu | E, K)_{1:2} (eq. meansplatting),
 //       Sigma2d = (J W Sigma W^T J^T)_{1:2,1:2} + blur I (eq. covsplatting), conic = inverse.
@@ -33,14 +33,21 @@
 // cutoff, so candidate sets and all arithmetic are those of the definition; a test checks the
 // binned search against an exhaustive all-pairs loop.
 //
+// Volume mask (optional, Sec. 4.3 "Insignificant Gaussian removal"): M_hat = 1{M > eps} in the
+// forward with the straight-through derivative dM_hat/dM = 1; S_hat = M_hat S, alpha_hat =
+// M_hat alpha.  A masked Gaussian (M_hat = 0) is dropped (its zero covariance has no slice);
+// for the others dL/dM = sum_j s_j dL/ds_j + o dL/do.  Densification statistic (Sec. 3.3,
+// densification in spacetime): per view, |dL/d mean2d| of every Gaussian alive in it; the
+// |dL/d mu_t| indicator is the mean4 gradient's time component.
+//
 // Extra channels (optional, orc_frame_set_channels), composited with the same weights T alpha:
 //   features: per Gaussian f in R^D gated by a per-call vector g (the scale gate S(s)) and
 //       normalized, f_hat = (g * f) / |g * f| (0 where g * f = 0) -- the color replaced by the
-//       normalized scale-gated feature (Sec. 3.4, 4D segmentation);
+//       normalized scale-gated feature (Sec. 7, segment anything in 4D);
 //   depth: the camera-space z of the sliced mean (the rendered depth of the urban LiDAR loss,
-//       Sec. 3.4);
+//       Sec. 5, urban scenes);
 //   flow: the image-plane displacement of the projected conditional mean between t and
-//       t + dt (Sec. 4.1.3, the emerged scene dynamics), 0 where the moved mean is not in front
+//       t + dt (Sec. 8.1, the emerged scene dynamics), 0 where the moved mean is not in front
 //       of the camera.
 //   The extra channels have a zero background.  Their backward differentiates the features,
 //   the gate and the depth; flow is forward only (its upstream gradient is ignored).
@@ -67,6 +74,8 @@ extern "C" {
 typedef struct {
   int32_t n, sh_degree, t_degree;
   const double *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  const double* mask;     // [n] significance M (NULL: no mask)
+  double mask_threshold;  // epsilon
 } orc_gaussians;
 
 typedef struct {
@@ -100,6 +109,8 @@ typedef struct {
 
 typedef struct {
   double *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  double* mask;     // [n] (+=) straight-through dL/dM, or NULL
+  double* densify;  // [n] (+=) |dL/d mean2d| of this view, or NULL
 } orc_grads;
 
 typedef struct {
@@ -516,6 +527,10 @@ void build_frame(Frame& f) {
   const double reach = std::sqrt(cut2 * (1.0 + f.st.margin_d2)) * (1.0 + 1e-9);
 #pragma omp parallel for schedule(dynamic, 256)
   for (int i = 0; i < n; ++i) {
+    if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold)) {
+      f.splats[i].alive = f.splats[i].optional = false;  // masked: M_hat = 0
+      continue;
+    }
     double m4[4], s4[4], ql[4], qr[4], o;
     load_params(f.g, i, m4, s4, ql, qr, o);
     SplatT<double> sp = preprocess<double>(m4, s4, ql, qr, o, f.g.sh + (size_t)i * sh_stride(f.g),
@@ -757,6 +772,13 @@ void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grad
     out.rot_r[4 * i + k] += grad[12 + k];
   }
   out.opacity[i] += grad[16];
+  // Straight-through mask: S_hat = M_hat S and alpha_hat = M_hat o at M_hat = 1.
+  if (out.mask) {
+    double gm = o * grad[16];
+    for (int k = 0; k < 4; ++k) gm += s4[k] * grad[4 + k];
+    out.mask[i] += gm;
+  }
+  if (out.densify) out.densify[i] += std::sqrt(q[0] * q[0] + q[1] * q[1]);
   // SH: color is linear in the coefficients; zero where the color was clamped.
   const int Ds = f.g.sh_degree, nsh = (Ds + 1) * (Ds + 1);
   std::vector<double> Y(nsh);

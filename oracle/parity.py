@@ -61,10 +61,11 @@ def check_image(gpu_rgb: np.ndarray, frame, tol: float = 1e-4, xy: Optional[np.n
 
 
 def grad_rel_errors(gpu: Dict[str, np.ndarray], ref: Dict[str, np.ndarray]) -> Dict[str, float]:
+    """Relative L2 error of every group the GPU computed (each must exist in ref)."""
     out = {}
-    for k, r in ref.items():
+    for k in gpu:
         g = np.asarray(gpu[k], np.float64).reshape(-1)
-        r = np.asarray(r, np.float64).reshape(-1)
+        r = np.asarray(ref[k], np.float64).reshape(-1)
         nr = np.linalg.norm(r)
         out[k] = float(np.linalg.norm(g - r) / nr) if nr > 0 else float(np.linalg.norm(g))
     return out

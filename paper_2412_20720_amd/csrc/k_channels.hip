@@ -1,5 +1,5 @@
-// Per-Gaussian work of the extra render channels (Sec. 3.4 feature and depth rendering,
-// Sec. 4.1.3 rendered flow); their compositing lives in the raster kernels.
+// Per-Gaussian work of the extra render channels (Sec. 7 feature rendering, Sec. 5
+// rendered depth, Sec. 8.1 rendered flow); their compositing lives in the raster kernels.
 //
 //   feature_normalize: f_hat = s / |s| with s = gate * f (0 when s = 0), one thread per Gaussian.
 //   flow_forward:      per visible (view, Gaussian) slot, the image displacement of the

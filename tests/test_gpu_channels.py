@@ -1,6 +1,6 @@
 """Extra render channels through the C ABI (g4d_render_channels_forward / _backward): normalized
-scale-gated features (Sec. 3.4, 4D segmentation), depth (Sec. 3.4, the LiDAR depth loss) and
-flow (Sec. 4.1.3, the rendered displacement of the conditional means), against the FP64 oracle.
+scale-gated features (Sec. 7, 4D segmentation), depth (Sec. 5, the LiDAR depth loss) and
+flow (Sec. 8.1, the rendered displacement of the conditional means), against the FP64 oracle.
 
 Feature channels: |GPU - oracle| <= 1e-4; depth and flow: <= 1e-4 + 1e-4 |oracle| (they are in
 scene units and pixels); marked decisions resolved as for images.  Gradients of the parameters,

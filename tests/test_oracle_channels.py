@@ -1,13 +1,13 @@
 """Pins of the oracle's extra channels: features, depth and flow composited with the weights of
 eq:4dblending.
 
-- Features (Sec. 3.4, 4D segmentation: the color replaced by the normalized scale-gated
+- Features (Sec. 7, 4D segmentation: the color replaced by the normalized scale-gated
   feature): with unit-norm features equal to the colors, the feature channels are the RGB
   render with a black background (the RGB path is pinned in test_oracle_pins.py); scaling a
   feature does not change it; a zero gate entry zeroes its channel.
-- Depth (Sec. 3.4, the rendered depth of the LiDAR loss): with every Gaussian at depth z0 the
+- Depth (Sec. 5, the rendered depth of the LiDAR loss): with every Gaussian at depth z0 the
   channel is z0 (1 - T); two Gaussians on the axis give the closed form.
-- Flow (Sec. 4.1.3: the displacement of the conditional mean projected to the image): zero for
+- Flow (Sec. 8.1: the displacement of the conditional mean projected to the image): zero for
   Gaussians whose rotation leaves space and time uncoupled; for a rotation in the (x, t) plane
   the mean moves at Sigma_xt / Sigma_tt (closed form) and the centre pixel shows o times the
   projected displacement.

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
         os.path.join(ROOT, "tests", "test_oracle_gradients.py"),
-        os.path.join(ROOT, "tests", "test_oracle_channels.py")]
+        os.path.join(ROOT, "tests", "test_oracle_channels.py"),
+        os.path.join(ROOT, "tests", "test_oracle_training.py")]
 
 # (name, exact text in oracle.cpp, replacement)
 MUTATIONS = [
@@ -55,6 +56,11 @@ MUTATIONS = [
      "Rx[c] = e[c];"),
     ("feature gradient without the projection", "const double ds = (gf[c] - fh[c] * dot) / nrm;",
      "const double ds = gf[c] / nrm;"),
+    ("mask gradient without the opacity term", "double gm = o * grad[16];", "double gm = 0.0;"),
+    ("densify statistic of u only", "out.densify[i] += std::sqrt(q[0] * q[0] + q[1] * q[1]);",
+     "out.densify[i] += std::fabs(q[0]);"),
+    ("mask threshold inclusive", "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold)) {",
+     "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold + 0.2)) {"),
 ]
 
 
