@@ -56,16 +56,29 @@ typedef enum {
  *   opacity [N]    in [0, 1], already activated
  *   sh      [N, t_degree+1, (sh_degree+1)^2, 3]  4DSH coefficients k[n, l*l+l+m, channel]
  *           (Sec. 3.2, Z = cos(2 pi n dt / T) Y_l^m; real Y without Condon-Shortley phase).
+ *   mask    [N]    optional (NULL: none) significance M of the volume mask (Sec. 4.3,
+ *           eq. mask_prune), already activated: the forward uses M_hat = 1{M > mask_threshold},
+ *           scales and opacity multiplied by M_hat, so a Gaussian with M <= mask_threshold is
+ *           removed; the backward's dL/dM is straight-through (dM_hat/dM = 1).
  * sh_degree in 0..3, t_degree in 0..2, N >= 0. */
 typedef struct {
   int32_t n, sh_degree, t_degree;
   const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  const float *mask;
+  float mask_threshold;
 } g4d_gaussians;
 
 /* Gradients, same shapes as g4d_gaussians; overwritten (not accumulated) with the sum over
- * the call's views.  Any pointer may be NULL to skip that group (sh only if sh is NULL). */
+ * the call's views.  Any pointer may be NULL to skip that group.
+ *   mask     [N]    dL/dM = sum_j s_j dL/ds_j + opacity dL/d(opacity) for a kept Gaussian, 0
+ *                   for a removed one (without g4d_gaussians.mask every Gaussian is kept);
+ *   densify  [N,3]  densification statistics of the call (Sec. 3.3, densification in
+ *                   spacetime): sum over the views where the Gaussian is listed in a tile of
+ *                   |dL/d(u, v)| (screen-space mean, pixels), |dL/d mu_t| (of the summed
+ *                   gradient), and the number of such views. */
 typedef struct {
   float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  float *mask, *densify;
 } g4d_grads;
 
 /* (host) One view: pinhole intrinsics K = (fx, fy, cx, cy), extrinsic world->camera

@@ -29,12 +29,14 @@ G4D_MAX_CHANNELS = 36
 class g4d_gaussians(C.Structure):
     _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("t_degree", C.c_int32),
                 ("mean4", C.c_void_p), ("scale4", C.c_void_p), ("rot_l", C.c_void_p),
-                ("rot_r", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("rot_r", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p),
+                ("mask", C.c_void_p), ("mask_threshold", C.c_float)]
 
 
 class g4d_grads(C.Structure):
     _fields_ = [("mean4", C.c_void_p), ("scale4", C.c_void_p), ("rot_l", C.c_void_p),
-                ("rot_r", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("rot_r", C.c_void_p), ("opacity", C.c_void_p), ("sh", C.c_void_p),
+                ("mask", C.c_void_p), ("densify", C.c_void_p)]
 
 
 class g4d_view(C.Structure):

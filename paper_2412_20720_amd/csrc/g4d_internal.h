@@ -55,9 +55,12 @@ void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st);
 struct GaussPtrs {
   int n, sh_degree, t_degree;
   const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  const float* mask;      // optional volume mask (kept when mask > mask_thr)
+  float mask_thr;
 };
 struct GradPtrs {
   float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
+  float *mask, *densify;  // optional: straight-through dL/dM; [N][3] densification statistics
 };
 
 void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,

@@ -31,6 +31,8 @@ struct DevBuf {
 struct SavedKey {
   int32_t n = -1, sh_degree = 0, t_degree = 0, n_views = 0;
   const void* ptrs[6] = {};
+  const float* mask = nullptr;
+  float mask_thr = 0.f;
   std::vector<g4d_view> views;
   g4d_settings s{};
   g4d_channels ch{};  // n_features = depth = flow = 0 for a plain forward
@@ -176,6 +178,7 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     return fail(ctx, G4D_EINVAL, "t_degree %d outside 0..%d", g->t_degree, G4D_MAX_T_DEGREE);
   if (g->n > 0 && (!g->mean4 || !g->scale4 || !g->rot_l || !g->rot_r || !g->opacity || !g->sh))
     return fail(ctx, G4D_EINVAL, "null Gaussian parameter array");
+  if (g->mask && std::isnan(g->mask_threshold)) return fail(ctx, G4D_EINVAL, "mask_threshold NaN");
   if (n_views < 1 || n_views > G4D_MAX_VIEWS)
     return fail(ctx, G4D_EINVAL, "n_views %d outside 1..%d", n_views, G4D_MAX_VIEWS);
   if ((int64_t)g->n * n_views > (int64_t)INT32_MAX)
@@ -255,8 +258,8 @@ DSettings device_settings(const g4d_settings* s) {
 }
 
 GaussPtrs gauss_ptrs(const g4d_gaussians* g) {
-  return GaussPtrs{g->n, g->sh_degree, g->t_degree, g->mean4, g->scale4, g->rot_l, g->rot_r,
-                   g->opacity, g->sh};
+  return GaussPtrs{g->n,       g->sh_degree, g->t_degree, g->mean4, g->scale4, g->rot_l,
+                   g->rot_r,   g->opacity,   g->sh,       g->mask,  g->mask_threshold};
 }
 
 // Plan tile grids and offsets, upload the view table and derive per-view constants.
@@ -343,6 +346,9 @@ bool same_key(const SavedKey& k, const g4d_gaussians* g, const g4d_view* views, 
   const void* p[6] = {g->mean4, g->scale4, g->rot_l, g->rot_r, g->opacity, g->sh};
   for (int i = 0; i < 6; ++i)
     if (p[i] != k.ptrs[i]) return false;
+  if (g->mask != k.mask ||
+      (g->mask && std::memcmp(&g->mask_threshold, &k.mask_thr, sizeof(float)) != 0))
+    return false;
   if (std::memcmp(k.views.data(), views, sizeof(g4d_view) * n_views) != 0) return false;
   return std::memcmp(&k.s, s, sizeof(g4d_settings)) == 0;
 }
@@ -622,6 +628,8 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   k.n_views = n_views;
   const void* p[6] = {g->mean4, g->scale4, g->rot_l, g->rot_r, g->opacity, g->sh};
   for (int i = 0; i < 6; ++i) k.ptrs[i] = p[i];
+  k.mask = g->mask;
+  k.mask_thr = g->mask_threshold;
   k.views.assign(views, views + n_views);
   k.s = *s;
   k.ch = ch ? *ch : g4d_channels{};
@@ -696,7 +704,8 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
     raster_backward(a, st);
     G4D_HIP(hipGetLastError());
   }
-  GradPtrs gp{out->mean4, out->scale4, out->rot_l, out->rot_r, out->opacity, out->sh};
+  GradPtrs gp{out->mean4, out->scale4, out->rot_l,  out->rot_r,
+              out->opacity, out->sh,  out->mask, out->densify};
   {
     Stage t(ctx, 10, st);
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),

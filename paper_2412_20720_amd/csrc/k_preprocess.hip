@@ -18,10 +18,16 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
-    uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey) {
+    uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey, const float* __restrict__ mask,
+    float mask_thr) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n) return;
+  if (mask && !(mask[gi] > mask_thr)) {
+    // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
+    for (int v = 0; v < n_views; ++v) tiles[(size_t)v * n + gi] = 0u;
+    return;
+  }
   Geom g;
   geom_forward(rot_l[gi], rot_r[gi], scale4[gi], g);
   const float4 mean = mean4[gi];
@@ -89,11 +95,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     for (int j = 0; j < 4; ++j) gM[i][j] = 0.f;
   float gmean[4] = {0.f, 0.f, 0.f, 0.f};
   float gop = 0.f;
+  float dens = 0.f;  // sum over listed views of |dL/d(u, v)|
+  int nvis = 0;
   for (int v = 0; v < n_views; ++v) {
     const size_t slot = (size_t)v * n + gi;
     if (tiles[slot] == 0u) continue;
     const float4* gp = reinterpret_cast<const float4*>(grad2d + slot * kGrad2d);
     const float4 q0 = gp[0], q1 = gp[1], q2 = gp[2];
+    dens += sqrtf(fmaf(q0.x, q0.x, q0.y * q0.y));
+    ++nvis;
     const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
     const DView& V = views[v];
     ViewFwd f;
@@ -108,6 +118,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = make_float4(gql[0], gql[1], gql[2], gql[3]);
   if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = make_float4(gqr[0], gqr[1], gqr[2], gqr[3]);
   if (out.opacity) out.opacity[gi] = gop;
+  // straight-through volume mask: S_hat = M_hat S, opacity_hat = M_hat opacity at M_hat = 1 (a
+  // removed Gaussian has no listed view, so every term is 0)
+  if (out.mask)
+    out.mask[gi] = fmaf(op, gop, fmaf(sc.x, gs[0], fmaf(sc.y, gs[1], fmaf(sc.z, gs[2], sc.w * gs[3]))));
+  if (out.densify) {
+    out.densify[3 * (size_t)gi + 0] = dens;
+    out.densify[3 * (size_t)gi + 1] = fabsf(gmean[3]);
+    out.densify[3 * (size_t)gi + 2] = (float)nvis;
+  }
   if (out.sh) {
     float* o = out.sh + (size_t)gi * NSH;
 #pragma unroll
@@ -124,7 +143,7 @@ void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings 
                      reinterpret_cast<const float4*>(gp.scale4),
                      reinterpret_cast<const float4*>(gp.rot_l),
                      reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S, rec,
-                     tiles, dkey);
+                     tiles, dkey, gp.mask, gp.mask_thr);
 }
 
 template <int DS, int DT>

@@ -45,7 +45,10 @@ class Renderer:
 
     # -- marshalling ---------------------------------------------------------------------
     def gaussians(self, mean4, scale4, rot_l, rot_r, opacity, sh, sh_degree: int,
-                  t_degree: int) -> B.g4d_gaussians:
+                  t_degree: int, mask: Optional[torch.Tensor] = None,
+                  mask_threshold: float = 0.0) -> B.g4d_gaussians:
+        """Parameter pointers for the ABI; `mask` [N] is the optional volume-mask
+        significance (kept where mask > mask_threshold)."""
         n = int(mean4.shape[0])
         k = (sh_degree + 1) ** 2
         want = {"mean4": (n, 4), "scale4": (n, 4), "rot_l": (n, 4), "rot_r": (n, 4),
@@ -55,9 +58,13 @@ class Renderer:
                 raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device}")
             if tuple(t.shape) != want[name]:
                 raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want[name]}")
+        if mask is not None and (mask.dtype != torch.float32 or mask.device != self.device or
+                                 not mask.is_contiguous() or tuple(mask.shape) != (n,)):
+            raise ValueError(f"mask must be a contiguous float32 [{n}] tensor on {self.device}")
         return B.g4d_gaussians(n, sh_degree, t_degree, mean4.data_ptr(), scale4.data_ptr(),
                                rot_l.data_ptr(), rot_r.data_ptr(), opacity.data_ptr(),
-                               sh.data_ptr())
+                               sh.data_ptr(), None if mask is None else mask.data_ptr(),
+                               float(mask_threshold))
 
     @staticmethod
     def pixel_count(views) -> int:
@@ -78,7 +85,7 @@ class Renderer:
         va = views if isinstance(views, C.Array) else B.make_views(views)
         st = _stream_handle(self.device)
         gr = B.g4d_grads(*[grads[k].data_ptr() if grads.get(k) is not None else None
-                           for k in PARAM_NAMES])
+                           for k in PARAM_NAMES + ("mask", "densify")])
         B.check(B.lib().g4d_render_backward(self._ctx, C.byref(g), va, len(va), C.byref(settings),
                                             dL.data_ptr(), C.byref(gr), st), self._ctx)
 
@@ -107,7 +114,7 @@ class Renderer:
         """grads: the parameter groups plus "features" [N, D] and "gate" [D] (optional)."""
         va = views if isinstance(views, C.Array) else B.make_views(views)
         gr = B.g4d_grads(*[grads[k].data_ptr() if grads.get(k) is not None else None
-                           for k in PARAM_NAMES])
+                           for k in PARAM_NAMES + ("mask", "densify")])
         df, dg = grads.get("features"), grads.get("gate")
         B.check(B.lib().g4d_render_channels_backward(
             self._ctx, C.byref(g), va, len(va), C.byref(settings), C.byref(ch), dL.data_ptr(),
@@ -183,9 +190,10 @@ class Renderer:
 
 class _Render4D(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, mean4, scale4,
-                rot_l, rot_r, opacity, sh):
-        g = renderer.gaussians(mean4, scale4, rot_l, rot_r, opacity, sh, sh_degree, t_degree)
+    def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, mask_threshold,
+                densify_out, mean4, scale4, rot_l, rot_r, opacity, sh, mask):
+        g = renderer.gaussians(mean4, scale4, rot_l, rot_r, opacity, sh, sh_degree, t_degree,
+                               mask, mask_threshold)
         va = B.make_views(views)
         npix = Renderer.pixel_count(views)
         rgb = torch.empty(3 * npix, device=renderer.device)
@@ -193,18 +201,23 @@ class _Render4D(torch.autograd.Function):
         renderer.forward(g, va, settings, rgb, T)
         ctx.renderer, ctx.views, ctx.settings = renderer, va, settings
         ctx.degrees = (sh_degree, t_degree)
-        ctx.save_for_backward(mean4, scale4, rot_l, rot_r, opacity, sh)
+        ctx.mask_threshold, ctx.densify_out = mask_threshold, densify_out
+        ctx.save_for_backward(mean4, scale4, rot_l, rot_r, opacity, sh, mask)
         ctx.mark_non_differentiable(T)
         return rgb, T
 
     @staticmethod
     def backward(ctx, d_rgb, d_T):
-        params = ctx.saved_tensors
+        *params, mask = ctx.saved_tensors
         r: Renderer = ctx.renderer
-        g = r.gaussians(*params, *ctx.degrees)
+        g = r.gaussians(*params, *ctx.degrees, mask, ctx.mask_threshold)
         grads = {k: torch.empty_like(p) for k, p in zip(PARAM_NAMES, params)}
+        if mask is not None:
+            grads["mask"] = torch.empty_like(mask)
+        if ctx.densify_out is not None:
+            grads["densify"] = ctx.densify_out
         r.backward(g, ctx.views, ctx.settings, d_rgb.contiguous(), grads)
-        return (None, None, None, None, None) + tuple(grads[k] for k in PARAM_NAMES)
+        return ((None,) * 7 + tuple(grads[k] for k in PARAM_NAMES) + (grads.get("mask"),))
 
 
 class _RenderChannels(torch.autograd.Function):
@@ -254,14 +267,20 @@ def split_views(flat: torch.Tensor, views, channels: int) -> List[torch.Tensor]:
 
 
 def render(mean4, scale4, rot_l, rot_r, opacity, sh, views: Sequence[dict], *, sh_degree: int,
-           t_degree: int, renderer: Renderer, settings: Optional[B.g4d_settings] = None):
+           t_degree: int, renderer: Renderer, settings: Optional[B.g4d_settings] = None,
+           mask: Optional[torch.Tensor] = None, mask_threshold: float = 0.0,
+           densify_out: Optional[torch.Tensor] = None):
     """Differentiable render of all ``views`` in one batch.
 
-    Returns (images, transmittances): lists of [3, H, W] and [H, W] tensors, one per view.
+    ``mask`` [N] is the optional volume-mask significance (activated; kept where above
+    ``mask_threshold``, straight-through gradient).  ``densify_out`` [N, 3] receives the
+    densification statistics of the backward (sum over views of |dL/d mean2d|, |dL/d mu_t|,
+    number of views).  Returns (images, transmittances): lists of [3, H, W] and [H, W] tensors.
     """
     s = settings if settings is not None else B.default_settings()
-    rgb, T = _Render4D.apply(renderer, list(views), s, sh_degree, t_degree, mean4, scale4, rot_l,
-                             rot_r, opacity, sh)
+    rgb, T = _Render4D.apply(renderer, list(views), s, sh_degree, t_degree, mask_threshold,
+                             densify_out, mean4, scale4, rot_l, rot_r, opacity, sh,
+                             None if mask is None else mask.contiguous())
     return split_views(rgb, views, 3), [t[0] for t in split_views(T, views, 1)]
 
 

@@ -247,6 +247,12 @@ def make_dl_dchannels(scene: Scene, n_channels: int, seed: int = 13) -> List[np.
             for v in scene.views]
 
 
+def make_mask(scene: Scene, seed: int = 14) -> np.ndarray:
+    """Volume-mask significances M ~ U(0, 1) per Gaussian, float32."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, scene.n).astype(np.float32)
+
+
 def subset(scene: Scene, idx) -> Scene:
     """Scene restricted to the Gaussians ``idx`` (same views)."""
     idx = np.asarray(idx)
