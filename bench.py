@@ -194,6 +194,7 @@ def main():
     chan = None
     if args.channels >= 0:
         chan = channel_step(r, g, views, settings, sc, p, dL, args, npix)
+    train = training_step(r, views, settings, sc, p, dL, args, npix)
 
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
@@ -232,6 +233,7 @@ def main():
         "roofline": roofline,
         "alg_bound": alg_bound,
         "channels": chan,
+        "training_fusion": train,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
                  "evaluated_pairs": evals, "composited_pairs": contrib},
@@ -283,6 +285,41 @@ def channel_step(r, g, views, settings, sc, p, dL, args, npix):
         f"(raster_fwd {st.get('raster_fwd', 0):.3f} ms, raster_bwd {st.get('raster_bwd', 0):.3f} ms)")
     return dict(features=D, depth=True, flow=True, flow_dt=0.05, value=npix / dt / 1e6,
                 unit="Mpix/s", ms_per_step=dt * 1e3, stages_ms=st)
+
+
+def training_step(r, views, settings, sc, p, dL, args, npix):
+    """The same step with the training-side fusion on: a volume mask (significances U(0, 1),
+    threshold 0.1, so about 90% of the Gaussians are kept) and the straight-through mask
+    gradient plus the densification statistics written by the backward."""
+    import torch
+    from paper_2412_20720_amd import scenes
+    names = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
+    dev = p["mean4"].device
+    mask = torch.from_numpy(scenes.make_mask(sc)).to(dev)
+    g = r.gaussians(*[p[k] for k in names], sc.sh_degree, sc.t_degree, mask, 0.1)
+    rgb = torch.empty(3 * npix, device=dev)
+    T = torch.empty(npix, device=dev)
+    grads = {k: torch.empty_like(p[k]) for k in names}
+    grads["mask"] = torch.empty_like(mask)
+    grads["densify"] = torch.empty((sc.n, 3), device=dev)
+
+    def step():
+        r.forward(g, views, settings, rgb, T)
+        r.backward(g, views, settings, dL, grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    r.sync()
+    log(f"bench: training fusion (mask 0.1 + densify): {dt * 1e3:.3f} ms/step, "
+        f"{npix / dt / 1e6:.1f} Mpix/s")
+    return dict(mask_threshold=0.1, kept=float((mask > 0.1).float().mean()), value=npix / dt / 1e6,
+                unit="Mpix/s", ms_per_step=dt * 1e3)
 
 
 def cpu_baseline(sc, n_views):
