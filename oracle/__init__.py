@@ -117,6 +117,9 @@ def lib() -> C.CDLL:
         L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Grads),
                                          C.c_void_p, C.c_void_p]
         L.orc_frame_backward_splat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_sky.argtypes = [C.POINTER(_View), dp, C.c_int, C.c_double, dp, dp, C.c_void_p]
+        L.orc_sky_backward.argtypes = [C.POINTER(_View), C.c_int, dp, dp]
+        L.orc_frame_set_background.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -162,6 +165,37 @@ def sh_basis(deg: int, direction) -> np.ndarray:
     return Y
 
 
+def _make_view(view: Dict, exact_f64: bool) -> "_View":
+    conv_s = (lambda x: float(x)) if exact_f64 else (lambda x: float(np.float32(x)))
+    return _View(int(view["width"]), int(view["height"]), conv_s(view["fx"]), conv_s(view["fy"]),
+                 conv_s(view["cx"]), conv_s(view["cy"]),
+                 (C.c_double * 12)(*[conv_s(x) for x in np.asarray(view["world_to_cam"]).ravel()]),
+                 conv_s(view["t"]),
+                 (C.c_double * 3)(*[conv_s(x) for x in np.asarray(view["background"]).ravel()]))
+
+
+def sky(view: Dict, cube: np.ndarray, margin: float = 1e-5, exact_f64: bool = False):
+    """Cube-map sky of a view: (sky [3, H, W], alt [3, H, W], near [H, W]); alt is the lookup
+    on the other face where the face choice is within `margin` of a tie (else equal to sky)."""
+    v = _make_view(view, exact_f64)
+    R = int(cube.shape[1])
+    cb = np.ascontiguousarray(cube, np.float64) if exact_f64 else _f64(cube)
+    H, W = v.height, v.width
+    out, alt = np.zeros((H, W, 3)), np.zeros((H, W, 3))
+    near = np.zeros((H, W), np.int32)
+    lib().orc_sky(C.byref(v), _dp(cb), R, float(margin), _dp(out), _dp(alt), near.ctypes.data)
+    return out.transpose(2, 0, 1).copy(), alt.transpose(2, 0, 1).copy(), near
+
+
+def sky_backward(view: Dict, R: int, dsky: np.ndarray, exact_f64: bool = False) -> np.ndarray:
+    """Adjoint of `sky`: gradient [6, R, R, 3] of <dsky [3, H, W], sky image> w.r.t. the cube."""
+    v = _make_view(view, exact_f64)
+    d = np.ascontiguousarray(np.asarray(dsky, np.float64).transpose(1, 2, 0))
+    out = np.zeros((6, R, R, 3))
+    lib().orc_sky_backward(C.byref(v), int(R), _dp(d), _dp(out))
+    return out
+
+
 class Frame:
     """All Gaussians of a scene preprocessed in FP64 for one view."""
 
@@ -201,6 +235,16 @@ class Frame:
         self.n_ext = self.n_features = 0
         self.depth = self.flow = False
         self._h = lib().orc_frame_new(C.byref(g), C.byref(v), C.byref(s), int(use_bins))
+
+    def set_background(self, bg: Optional[np.ndarray]) -> None:
+        """Per-pixel background [3, H, W] (float64, e.g. a sky image) instead of the view's
+        constant; None restores the constant."""
+        if bg is None:
+            self._bg = None
+            lib().orc_frame_set_background(self._h, None)
+            return
+        self._bg = np.ascontiguousarray(np.asarray(bg, np.float64).transpose(1, 2, 0))
+        lib().orc_frame_set_background(self._h, self._bg.ctypes.data)
 
     def set_channels(self, features: Optional[np.ndarray] = None, gate=None, depth: bool = False,
                      flow: bool = False, flow_dt: float = 0.0) -> int:

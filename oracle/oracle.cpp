@@ -40,6 +40,13 @@
 // densification in spacetime): per view, |dL/d mean2d| of every Gaussian alive in it; the
 // |dL/d mu_t| indicator is the mean4 gradient's time component.
 //
+// Sky (optional, Sec. 5, urban scenes): I = I_gs + (1 - O_gs) M_sky(r) = C + T M_sky(r), a cube
+// map queried by the world direction r of the pixel's ray (the background of that pixel).
+// Readings: the OpenGL cube-map convention (faces +x, -x, +y, -y, +z, -z; the major axis of r
+// picks the face, ties to x before y before z; face coordinates s = (sc / |ma| + 1) / 2,
+// t = (tc / |ma| + 1) / 2 with (sc, tc) from the published face table), texel (i, j) centred
+// at ((i + 1/2) / R, (j + 1/2) / R), bilinear within the face, clamped at its edges.
+//
 // Extra channels (optional, orc_frame_set_channels), composited with the same weights T alpha:
 //   features: per Gaussian f in R^D gated by a per-call vector g (the scale gate S(s)) and
 //       normalized, f_hat = (g * f) / |g * f| (0 where g * f = 0) -- the color replaced by the
@@ -482,6 +489,7 @@ struct Decision {
 };
 
 struct PixelResult {
+  int px = 0, py = 0;
   double rgb[3], T;
   int n_contrib;
   int64_t n_evals;
@@ -497,6 +505,7 @@ struct Frame {
   int bin = 16, bins_x = 0, bins_y = 0;
   std::vector<std::vector<int32_t>> bins;
   bool use_bins = true;
+  std::vector<double> bg_px;  // per-pixel background [H][W][3] (empty: the view's constant)
   // Extra channels: E = D + depth + 2 flow values per splat, in that order.
   int D = 0, E = 0, off_depth = -1, off_flow = -1;
   const double* features = nullptr;  // [n][D]
@@ -681,7 +690,9 @@ void composite(const Frame& f, const std::vector<Cand>& cands, const std::vector
     ++n_contrib;
     last_pos = (int)k;
   }
-  for (int ch = 0; ch < 3; ++ch) res.rgb[ch] = C[ch] + T * f.vw.background[ch];
+  const double* bg = f.vw.background;
+  if (!f.bg_px.empty()) bg = f.bg_px.data() + 3 * ((size_t)res.py * f.vw.width + res.px);
+  for (int ch = 0; ch < 3; ++ch) res.rgb[ch] = C[ch] + T * bg[ch];
   res.T = T;
   res.n_contrib = n_contrib;
   res.n_evals = n_evals;
@@ -690,6 +701,8 @@ void composite(const Frame& f, const std::vector<Cand>& cands, const std::vector
 void render_pixel(const Frame& f, int px, int py, PixelResult& res, std::vector<Cand>& cands) {
   gather(f, px, py, cands);
   res.marks.clear();
+  res.px = px;
+  res.py = py;
   composite(f, cands, {}, 0u, true, res, nullptr);
 }
 
@@ -707,10 +720,14 @@ void pixel_backward(const Frame& f, int px, int py, const double g[3], std::vect
                     const double* gx = nullptr, double* acc_ext = nullptr) {
   gather(f, px, py, cands);
   PixelResult res;
+  res.px = px;
+  res.py = py;
   contrib.clear();
   composite(f, cands, {}, 0u, false, res, &contrib);
   // Reverse sweep: R = color of everything behind the current contributor (incl. background).
-  double R[3] = {f.vw.background[0], f.vw.background[1], f.vw.background[2]};
+  const double* bg = f.vw.background;
+  if (!f.bg_px.empty()) bg = f.bg_px.data() + 3 * ((size_t)py * f.vw.width + px);
+  double R[3] = {bg[0], bg[1], bg[2]};
   std::vector<double> Rx(gx ? f.E : 0, 0.0);  // extra channels behind (zero background)
   const double cx = px + 0.5, cy = py + 0.5;
   for (int k = (int)contrib.size() - 1; k >= 0; --k) {
@@ -790,6 +807,79 @@ void gaussian_backward(const Frame& f, int i, const double* q /* NQ */, orc_grad
       for (int ch = 0; ch < 3; ++ch)
         if (!sp.color_clamped[ch]) gsh[(n * nsh + k) * 3 + ch] += q[6 + ch] * fn * Y[k];
   }
+}
+
+// Cube-map face and coordinates of direction r (the OpenGL table): face 0..5 = +x, -x, +y, -y,
+// +z, -z; (s, t) in [0, 1].  `alt` receives the face the next axis would pick and its
+// coordinates when two axes are within `margin` (relative) of a tie, else -1.
+struct CubeHit {
+  int face;
+  double s, t;
+};
+
+CubeHit cube_face(const double r[3], int axis) {
+  const double x = r[0], y = r[1], z = r[2];
+  double sc, tc, ma;
+  int face;
+  if (axis == 0) {
+    face = x >= 0 ? 0 : 1;
+    ma = std::fabs(x);
+    sc = x >= 0 ? -z : z;
+    tc = -y;
+  } else if (axis == 1) {
+    face = y >= 0 ? 2 : 3;
+    ma = std::fabs(y);
+    sc = x;
+    tc = y >= 0 ? z : -z;
+  } else {
+    face = z >= 0 ? 4 : 5;
+    ma = std::fabs(z);
+    sc = z >= 0 ? x : -x;
+    tc = -y;
+  }
+  return {face, 0.5 * (sc / ma + 1.0), 0.5 * (tc / ma + 1.0)};
+}
+
+int major_axis(const double r[3]) {
+  const double ax = std::fabs(r[0]), ay = std::fabs(r[1]), az = std::fabs(r[2]);
+  if (ax >= ay && ax >= az) return 0;
+  return ay >= az ? 1 : 2;
+}
+
+// Bilinear lookup (clamped to the face) of a cube map [6][R][R][3]; with `grad`, adds w * g
+// to the four texels instead.
+void cube_bilinear(const CubeHit& h, int R, const double* cube, double out[3], double* grad,
+                   const double g[3]) {
+  const double x = h.s * R - 0.5, y = h.t * R - 0.5;
+  const double fx = std::floor(x), fy = std::floor(y);
+  const double ax = x - fx, ay = y - fy;
+  const int x0 = (int)fx, y0 = (int)fy;
+  const int xs[2] = {std::min(std::max(x0, 0), R - 1), std::min(std::max(x0 + 1, 0), R - 1)};
+  const int ys[2] = {std::min(std::max(y0, 0), R - 1), std::min(std::max(y0 + 1, 0), R - 1)};
+  const double wx[2] = {1.0 - ax, ax}, wy[2] = {1.0 - ay, ay};
+  if (out) out[0] = out[1] = out[2] = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const size_t k = (((size_t)h.face * R + ys[b]) * R + xs[a]) * 3;
+      const double w = wx[a] * wy[b];
+      for (int c = 0; c < 3; ++c) {
+        if (out) out[c] += w * cube[k + c];
+        if (grad) grad[k + c] += w * g[c];
+      }
+    }
+}
+
+// World direction of the ray through the centre of pixel (px, py).
+void pixel_ray(const orc_view& vw, int px, int py, double r[3]) {
+  const double d[3] = {(px + 0.5 - vw.cx) / vw.fx, (py + 0.5 - vw.cy) / vw.fy, 1.0};
+  const double* E = vw.world_to_cam;
+  double n2 = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    r[j] = E[0 * 4 + j] * d[0] + E[1 * 4 + j] * d[1] + E[2 * 4 + j] * d[2];
+    n2 += r[j] * r[j];
+  }
+  const double inv = 1.0 / std::sqrt(n2);
+  for (int j = 0; j < 3; ++j) r[j] *= inv;
 }
 
 // Image-plane displacement of the projected conditional mean of Gaussian i between the frame's
@@ -983,6 +1073,8 @@ int orc_frame_variants(void* h, int px, int py, int max_marks, int max_out, doub
   if (nv > max_out) return -2;
   for (int v = 0; v < nv; ++v) {
     PixelResult r;
+    r.px = px;
+    r.py = py;
     composite(f, cands, base.marks, (unsigned)v, false, r, nullptr);
     for (int ch = 0; ch < 3; ++ch) rgb[3 * v + ch] = r.rgb[ch];
     if (T) T[v] = r.T;
@@ -1072,6 +1164,55 @@ int orc_frame_backward_splat(void* h, const double* dL_drgb, double* acc_out) {
 #pragma omp critical
     for (size_t k = 0; k < local.size(); ++k) acc_out[k] += local[k];
   }
+  return 0;
+}
+
+// Sky image of a view: sky [H][W][3] = M_sky(r) of each pixel's ray.  Where the two largest
+// |components| of r are within `margin` (relative) of each other the face choice is marked:
+// near [H][W] = 1 and alt [H][W][3] holds the lookup on the other face (else alt = sky).
+int orc_sky(const orc_view* vw, const double* cube, int R, double margin, double* sky,
+            double* alt, int32_t* near) {
+  const int W = vw->width, H = vw->height;
+#pragma omp parallel for schedule(static)
+  for (int p = 0; p < W * H; ++p) {
+    double r[3];
+    pixel_ray(*vw, p % W, p / W, r);
+    const int ax = major_axis(r);
+    cube_bilinear(cube_face(r, ax), R, cube, sky + 3 * (size_t)p, nullptr, nullptr);
+    int other = -1;
+    const double m = std::fabs(r[ax]);
+    for (int k = 0; k < 3; ++k)
+      if (k != ax && std::fabs(std::fabs(r[k]) - m) <= margin * m) other = k;
+    if (near) near[p] = other >= 0;
+    if (alt) {
+      if (other >= 0)
+        cube_bilinear(cube_face(r, other), R, cube, alt + 3 * (size_t)p, nullptr, nullptr);
+      else
+        for (int c = 0; c < 3; ++c) alt[3 * (size_t)p + c] = sky[3 * (size_t)p + c];
+    }
+  }
+  return 0;
+}
+
+// Adjoint of orc_sky: d_cube [6][R][R][3] += the bilinear transpose of dsky [H][W][3].
+int orc_sky_backward(const orc_view* vw, int R, const double* dsky, double* d_cube) {
+  const int W = vw->width, H = vw->height;
+  for (int p = 0; p < W * H; ++p) {
+    double r[3];
+    pixel_ray(*vw, p % W, p / W, r);
+    cube_bilinear(cube_face(r, major_axis(r)), R, nullptr, nullptr, d_cube, dsky + 3 * (size_t)p);
+  }
+  return 0;
+}
+
+// Per-pixel background [H][W][3] used instead of the view's constant (NULL: back to it).
+int orc_frame_set_background(void* h, const double* bg) {
+  Frame& f = *static_cast<Frame*>(h);
+  if (!bg) {
+    f.bg_px.clear();
+    return 0;
+  }
+  f.bg_px.assign(bg, bg + 3 * (size_t)f.vw.width * f.vw.height);
   return 0;
 }
 

@@ -12,7 +12,8 @@ SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
         os.path.join(ROOT, "tests", "test_oracle_gradients.py"),
         os.path.join(ROOT, "tests", "test_oracle_channels.py"),
-        os.path.join(ROOT, "tests", "test_oracle_training.py")]
+        os.path.join(ROOT, "tests", "test_oracle_training.py"),
+        os.path.join(ROOT, "tests", "test_oracle_sky.py")]
 
 # (name, exact text in oracle.cpp, replacement)
 MUTATIONS = [
@@ -59,6 +60,11 @@ MUTATIONS = [
     ("mask gradient without the opacity term", "double gm = o * grad[16];", "double gm = 0.0;"),
     ("densify statistic of u only", "out.densify[i] += std::sqrt(q[0] * q[0] + q[1] * q[1]);",
      "out.densify[i] += std::fabs(q[0]);"),
+    ("sky face table sign", "    sc = z >= 0 ? x : -x;", "    sc = z >= 0 ? -x : x;"),
+    ("sky bilinear weights swapped", "const double wx[2] = {1.0 - ax, ax}, wy[2] = {1.0 - ay, ay};",
+     "const double wx[2] = {ax, 1.0 - ax}, wy[2] = {1.0 - ay, ay};"),
+    ("backward ignores the per-pixel background", "  double R[3] = {bg[0], bg[1], bg[2]};",
+     "  double R[3] = {f.vw.background[0], f.vw.background[1], f.vw.background[2]};"),
     ("mask threshold inclusive", "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold)) {",
      "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold + 0.2)) {"),
 ]
