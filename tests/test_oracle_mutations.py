@@ -41,7 +41,7 @@ MUTATIONS = [
     ("no stop", "    if (stop) break;\n", "\n"),
     ("back-to-front order", "if (a.depth != b.depth) return a.depth < b.depth;",
      "if (a.depth != b.depth) return a.depth > b.depth;"),
-    ("background dropped", "res.rgb[ch] = C[ch] + T * f.vw.background[ch];", "res.rgb[ch] = C[ch];"),
+    ("background dropped", "res.rgb[ch] = C[ch] + T * bg[ch];", "res.rgb[ch] = C[ch];"),
     ("backward color-behind recursion",
      "R[ch] = ct.alpha * s.col[ch] + (1.0 - ct.alpha) * R[ch];", "R[ch] = s.col[ch];"),
     ("backward conic term sign", "a[3] += dalpha * ct.alpha * (-dx * dy);",
