@@ -218,6 +218,34 @@ g4d_status g4d_render_channels_backward(g4d_ctx *ctx, const g4d_gaussians *g,
                                         const g4d_grads *out, float *d_features, float *d_gate,
                                         void *stream);
 
+/* Sky of urban scenes (Sec. 5): I = I_gs + (1 - O_gs) M_sky(r) = C + T_final M_sky(r), a
+ * learnable cube map M_sky queried by the world direction r of each pixel's ray.
+ *   cube:       device [6][R][R][3] float32, faces +x, -x, +y, -y, +z, -z (OpenGL convention:
+ *               the largest |component| of r picks the face, ties to x then y; face coordinates
+ *               s = (sc / |ma| + 1) / 2, t = (tc / |ma| + 1) / 2; texel [face][j][i] centred at
+ *               ((i + 1/2) / R, (j + 1/2) / R); bilinear within the face, clamped at its edges);
+ *   resolution: R, 1 <= R <= G4D_MAX_SKY_RES.
+ * The sky replaces the views' constant background. */
+#define G4D_MAX_SKY_RES 4096
+typedef struct {
+  const float *cube;
+  int32_t resolution;
+} g4d_sky;
+
+/* g4d_render_forward with the sky as each pixel's background.  Saves the state
+ * g4d_render_sky_backward needs. */
+g4d_status g4d_render_sky_forward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                                  int32_t n_views, const g4d_settings *s, const g4d_sky *sky,
+                                  float *out_rgb, float *out_T, void *stream);
+
+/* Backward of the last g4d_render_sky_forward with the same inputs and *sky (else
+ * G4D_ESTATE): the parameter gradients into *out as g4d_render_backward, and dL/d(cube)
+ * [6][R][R][3] into d_cube (overwritten; may be NULL), summed over the views. */
+g4d_status g4d_render_sky_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                                   int32_t n_views, const g4d_settings *s, const g4d_sky *sky,
+                                   const float *dL_drgb, const g4d_grads *out, float *d_cube,
+                                   void *stream);
+
 /* Flags of g4d_render_step. */
 #define G4D_STEP_GRAPH 1
 

@@ -20,7 +20,7 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_preprocess", "g4d_render_forward", "g4d_render_backward", "g4d_sync_status",
             "g4d_get_stats", "g4d_eval_counters", "g4d_autotune", "g4d_profile",
             "g4d_stage_name", "g4d_render_step", "g4d_render_channels_forward",
-            "g4d_render_channels_backward"]
+            "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward"]
 G4D_STEP_GRAPH = 1
 G4D_NUM_STAGES = 11
 G4D_MAX_CHANNELS = 36
@@ -56,6 +56,10 @@ class g4d_settings(C.Structure):
 class g4d_channels(C.Structure):
     _fields_ = [("n_features", C.c_int32), ("features", C.c_void_p), ("gate", C.c_void_p),
                 ("depth", C.c_int32), ("flow", C.c_int32), ("flow_dt", C.c_float)]
+
+
+class g4d_sky(C.Structure):
+    _fields_ = [("cube", C.c_void_p), ("resolution", C.c_int32)]
 
 
 class g4d_stats(C.Structure):
@@ -103,6 +107,11 @@ def lib() -> C.CDLL:
                                                i32, C.POINTER(g4d_settings),
                                                C.POINTER(g4d_channels), vp, vp,
                                                C.POINTER(g4d_grads), vp, vp, vp]
+    L.g4d_render_sky_forward.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
+                                         C.POINTER(g4d_settings), C.POINTER(g4d_sky), vp, vp, vp]
+    L.g4d_render_sky_backward.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
+                                          C.POINTER(g4d_settings), C.POINTER(g4d_sky), vp,
+                                          C.POINTER(g4d_grads), vp, vp]
     L.g4d_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.g4d_stage_name.argtypes = [C.c_int]
     L.g4d_stage_name.restype = C.c_char_p

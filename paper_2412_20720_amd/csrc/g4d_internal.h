@@ -95,7 +95,15 @@ struct RasterArgs {
   float* out_ch;             // forward: per view [E][H][W]
   const float* dL_ch;        // backward: same layout (flow channels ignored)
   float* dfn;                // backward: dL/d(normalized features) [n_gauss][n_feat], atomics
+  const float* bg_px;        // optional per-pixel background, the image's layout (the sky)
 };
+
+// Sky (k_sky.hip): per-pixel background from a cube map [6][R][R][3] queried by each pixel's
+// ray, and the adjoint d_cube += bilinear transpose of T_final * dL/dI.
+void sky_forward(const DView* views, int n_views, int max_pixels, const float* cube, int R,
+                 float* bg, hipStream_t st);
+void sky_backward(const DView* views, int n_views, int max_pixels, int R, const float* px_T,
+                  const float* dL, float* d_cube, hipStream_t st);
 
 // Extra-channel helpers (k_channels.hip).
 void feature_normalize(int n, int d, const float* f, const float* gate, float* fn, float* fnorm,

@@ -36,6 +36,8 @@ struct SavedKey {
   std::vector<g4d_view> views;
   g4d_settings s{};
   g4d_channels ch{};  // n_features = depth = flow = 0 for a plain forward
+  const float* sky_cube = nullptr;
+  int32_t sky_res = 0;
 };
 
 }  // namespace
@@ -46,6 +48,7 @@ struct g4d_ctx {
   DevBuf views, tile_base, rec, tiles, dkey, vk[2], vv[2], voff, pk[2], pv[2], scan_tmp,
       sort_tmp, ranges, px_T, px_last, px_evals, grad2d, counters;
   DevBuf fn, fnorm, flow, dfn;     // extra channels
+  DevBuf skybg;                    // per-pixel sky background
   uint32_t* h_counters = nullptr;  // pinned: visible, pairs, overflow
   DView* h_views = nullptr;        // pinned staging
   int32_t* h_tile_base = nullptr;  // pinned staging
@@ -210,6 +213,12 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
   if (s->tile_size == 8 && s->px_per_lane > 1)
     return fail(ctx, G4D_EINVAL, "px_per_lane %d needs tile_size >= 16", s->px_per_lane);
   return G4D_OK;
+}
+
+int max_view_pixels(const g4d_view* views, int n_views) {
+  int64_t m = 0;
+  for (int v = 0; v < n_views; ++v) m = std::max(m, (int64_t)views[v].width * views[v].height);
+  return (int)m;
 }
 
 int n_ext_of(const g4d_channels* ch) {
@@ -418,7 +427,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
                     &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
                     &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
                     &ctx->grad2d, &ctx->counters, &ctx->fn, &ctx->fnorm, &ctx->flow,
-                    &ctx->dfn};
+                    &ctx->dfn, &ctx->skybg};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
@@ -461,10 +470,14 @@ g4d_status g4d_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* 
 // Forward of the whole batch; with ch, also the extra channels into out_ch.
 static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
                                int32_t n_views, const g4d_settings* s, const g4d_channels* ch,
-                               float* out_rgb, float* out_T, float* out_ch, void* stream) {
+                               const g4d_sky* sky, float* out_rgb, float* out_T, float* out_ch,
+                               void* stream) {
   g4d_status r = check_common(ctx, g, views, n_views, s);
   if (r != G4D_OK) return r;
   if (!out_rgb) return fail(ctx, G4D_EINVAL, "null out_rgb");
+  if (sky && (!sky->cube || sky->resolution < 1 || sky->resolution > G4D_MAX_SKY_RES))
+    return fail(ctx, G4D_EINVAL, "sky needs a cube map and 1 <= resolution <= %d",
+                G4D_MAX_SKY_RES);
   if (ch) {
     if ((r = check_channels(ctx, g, ch)) != G4D_OK) return r;
     if (!out_ch) return fail(ctx, G4D_EINVAL, "null out_ch");
@@ -584,7 +597,13 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     else
       fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
   }
+  if (sky) {
+    if ((r = ensure(ctx, ctx->skybg, sizeof(float) * 3 * ctx->n_pixels, 1.1)) != G4D_OK) return r;
+    sky_forward(P<DView>(ctx->views), n_views, max_view_pixels(views, n_views), sky->cube,
+                sky->resolution, P<float>(ctx->skybg), st);
+  }
   RasterArgs a{};
+  a.bg_px = sky ? P<float>(ctx->skybg) : nullptr;
   a.rec = P<float>(ctx->rec);
   a.pval = n_pairs > 0 ? P<uint32_t>(ctx->pv[pb]) : nullptr;
   a.ranges = P<uint2>(ctx->ranges);
@@ -633,6 +652,8 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   k.views.assign(views, views + n_views);
   k.s = *s;
   k.ch = ch ? *ch : g4d_channels{};
+  k.sky_cube = sky ? sky->cube : nullptr;
+  k.sky_res = sky ? sky->resolution : 0;
   ctx->saved = true;
   return G4D_OK;
 }
@@ -641,8 +662,9 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
 // channels' contributions and the feature and gate gradients.
 static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
                                 int32_t n_views, const g4d_settings* s, const g4d_channels* ch,
-                                const float* dL_drgb, const float* dL_dch, const g4d_grads* out,
-                                float* d_features, float* d_gate, void* stream) {
+                                const g4d_sky* sky, const float* dL_drgb, const float* dL_dch,
+                                const g4d_grads* out, float* d_features, float* d_gate,
+                                float* d_cube, void* stream) {
   g4d_status r = check_common(ctx, g, views, n_views, s);
   if (r != G4D_OK) return r;
   if (!dL_drgb || !out) return fail(ctx, G4D_EINVAL, "null dL_drgb or grads");
@@ -652,13 +674,22 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
       return fail(ctx, G4D_EINVAL, "null d_features");
   }
   if (!ctx->saved || !same_key(ctx->key, g, views, n_views, s) ||
-      (ch && !same_channels(ctx->key.ch, *ch)))
+      (ch && !same_channels(ctx->key.ch, *ch)) ||
+      (sky ? (ctx->key.sky_cube != sky->cube || ctx->key.sky_res != sky->resolution)
+           : ctx->key.sky_cube != nullptr))
     return fail(ctx, G4D_ESTATE, "backward without a matching forward on this context");
   hipStream_t st = static_cast<hipStream_t>(stream);
   G4D_HIP(hipSetDevice(ctx->device));
   const int64_t slots = (int64_t)g->n * n_views;
   const int D = ch ? ch->n_features : 0;
   if (d_gate && D > 0) fill_u32(reinterpret_cast<uint32_t*>(d_gate), D, 0u, st);
+  if (sky && d_cube) {
+    // the sky gradient depends on the pixels only (it is there even without Gaussians)
+    const int R = sky->resolution;
+    fill_u32(reinterpret_cast<uint32_t*>(d_cube), (int64_t)6 * R * R * 3, 0u, st);
+    sky_backward(P<DView>(ctx->views), n_views, max_view_pixels(views, n_views), R,
+                 P<float>(ctx->px_T), dL_drgb, d_cube, st);
+  }
   if (slots == 0) return G4D_OK;
   g4d_settings s_run = *s;
   if (ch) {
@@ -689,6 +720,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
     a.px_last = P<int32_t>(ctx->px_last);
     a.dL = dL_drgb;
     a.grad2d = P<float>(ctx->grad2d);
+    a.bg_px = sky ? P<float>(ctx->skybg) : nullptr;
     if (ch) {
       a.n_ext = n_ext_of(ch);
       a.n_feat = D;
@@ -721,14 +753,15 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
 g4d_status g4d_render_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
                               int32_t n_views, const g4d_settings* s, float* out_rgb,
                               float* out_T, void* stream) {
-  return forward_impl(ctx, g, views, n_views, s, nullptr, out_rgb, out_T, nullptr, stream);
+  return forward_impl(ctx, g, views, n_views, s, nullptr, nullptr, out_rgb, out_T, nullptr,
+                      stream);
 }
 
 g4d_status g4d_render_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
                                int32_t n_views, const g4d_settings* s, const float* dL_drgb,
                                const g4d_grads* out, void* stream) {
-  return backward_impl(ctx, g, views, n_views, s, nullptr, dL_drgb, nullptr, out, nullptr,
-                       nullptr, stream);
+  return backward_impl(ctx, g, views, n_views, s, nullptr, nullptr, dL_drgb, nullptr, out,
+                       nullptr, nullptr, nullptr, stream);
 }
 
 g4d_status g4d_render_channels_forward(g4d_ctx* ctx, const g4d_gaussians* g,
@@ -737,7 +770,7 @@ g4d_status g4d_render_channels_forward(g4d_ctx* ctx, const g4d_gaussians* g,
                                        float* out_rgb, float* out_T, float* out_ch, void* stream) {
   if (!ctx) return G4D_EINVAL;
   if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
-  return forward_impl(ctx, g, views, n_views, s, ch, out_rgb, out_T, out_ch, stream);
+  return forward_impl(ctx, g, views, n_views, s, ch, nullptr, out_rgb, out_T, out_ch, stream);
 }
 
 g4d_status g4d_render_channels_backward(g4d_ctx* ctx, const g4d_gaussians* g,
@@ -748,8 +781,26 @@ g4d_status g4d_render_channels_backward(g4d_ctx* ctx, const g4d_gaussians* g,
                                         void* stream) {
   if (!ctx) return G4D_EINVAL;
   if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
-  return backward_impl(ctx, g, views, n_views, s, ch, dL_drgb, dL_dch, out, d_features, d_gate,
-                       stream);
+  return backward_impl(ctx, g, views, n_views, s, ch, nullptr, dL_drgb, dL_dch, out, d_features,
+                       d_gate, nullptr, stream);
+}
+
+g4d_status g4d_render_sky_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                                  int32_t n_views, const g4d_settings* s, const g4d_sky* sky,
+                                  float* out_rgb, float* out_T, void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  if (!sky) return fail(ctx, G4D_EINVAL, "null sky");
+  return forward_impl(ctx, g, views, n_views, s, nullptr, sky, out_rgb, out_T, nullptr, stream);
+}
+
+g4d_status g4d_render_sky_backward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                                   int32_t n_views, const g4d_settings* s, const g4d_sky* sky,
+                                   const float* dL_drgb, const g4d_grads* out, float* d_cube,
+                                   void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  if (!sky) return fail(ctx, G4D_EINVAL, "null sky");
+  return backward_impl(ctx, g, views, n_views, s, nullptr, sky, dL_drgb, nullptr, out, nullptr,
+                       nullptr, d_cube, stream);
 }
 
 g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,

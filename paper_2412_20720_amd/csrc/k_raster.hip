@@ -326,9 +326,16 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   for (int p = 0; p < P; ++p) {
     if (!L.inside[p]) continue;
     const int64_t pix = (int64_t)L.py[p] * V.width + L.px[p];
-    rgb[pix] = fmaf(T[p], V.bg[0], C0[p]);
-    rgb[hw + pix] = fmaf(T[p], V.bg[1], C1[p]);
-    rgb[2 * hw + pix] = fmaf(T[p], V.bg[2], C2[p]);
+    float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
+    if (a.bg_px) {  // per-pixel background (the sky), same layout as the image
+      const float* b = a.bg_px + 3 * (int64_t)V.pix_base + pix;
+      bg0 = b[0];
+      bg1 = b[hw];
+      bg2 = b[2 * hw];
+    }
+    rgb[pix] = fmaf(T[p], bg0, C0[p]);
+    rgb[hw + pix] = fmaf(T[p], bg1, C1[p]);
+    rgb[2 * hw + pix] = fmaf(T[p], bg2, C2[p]);
     const int64_t gp = (int64_t)V.pix_base + pix;
     if (a.out_T) a.out_T[gp] = T[p];
     a.px_T[gp] = T[p];
@@ -451,7 +458,14 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
       for (int c = 0; c < CX; ++c)
         gx[c] = (dxp && L.inside[p] && c < n_grad) ? dxp[(size_t)c * hw] : 0.f;
     }
-    gR[p] = fmaf(g0[p], V.bg[0], fmaf(g1[p], V.bg[1], g2[p] * V.bg[2]));
+    float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
+    if (a.bg_px && L.inside[p]) {
+      const float* b = a.bg_px + 3 * (int64_t)V.pix_base + (int64_t)L.py[p] * V.width + L.px[p];
+      bg0 = b[0];
+      bg1 = b[hw];
+      bg2 = b[2 * hw];
+    }
+    gR[p] = fmaf(g0[p], bg0, fmaf(g1[p], bg1, g2[p] * bg2));
     lane_last = max(lane_last, last[p]);
   }
   const int hi_last = wave_max(lane_last);

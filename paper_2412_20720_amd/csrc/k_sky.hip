@@ -1,0 +1,151 @@
+// Sky composite of urban scenes (Sec. 5): I = I_gs + (1 - O_gs) M_sky(r), where M_sky is a
+// learnable cube map queried by the world direction r of each pixel's ray.  With
+// O_gs = 1 - T_final this is the image with M_sky(r) as a per-pixel background, so the forward
+// writes that background (k_sky) and the raster kernels read it; the adjoint of the lookup,
+// dL/dM_sky += T_final dL/dI spread with the bilinear weights, is k_sky_backward.
+//
+// Cube-map convention (OpenGL): faces +x, -x, +y, -y, +z, -z picked by the largest |component|
+// of r (ties to x, then y); face coordinates s = (sc / |ma| + 1) / 2, t = (tc / |ma| + 1) / 2;
+// texel (i, j) centred at ((i + 1/2) / R, (j + 1/2) / R); bilinear within the face, clamped at
+// its edges.  One thread per pixel of every view (grid y = view).
+#include <hip/hip_runtime.h>
+
+#include "g4d_internal.h"
+
+namespace g4d {
+namespace {
+
+struct CubeTap {
+  int idx[4];   // float offsets of the four texels (channel 0)
+  float w[4];   // their bilinear weights
+  int base;     // texel (face, y0, x0) before clamping, the same for a whole footprint
+};
+
+__device__ __forceinline__ CubeTap cube_tap(const DView& V, int px, int py, int R) {
+  const float dx = ((float)px + 0.5f - V.cx) / V.fx, dy = ((float)py + 0.5f - V.cy) / V.fy;
+  float r[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) r[j] = fmaf(V.W[j], dx, fmaf(V.W[3 + j], dy, V.W[6 + j]));
+  const float ax = fabsf(r[0]), ay = fabsf(r[1]), az = fabsf(r[2]);
+  int face;
+  float sc, tc, ma;
+  if (ax >= ay && ax >= az) {
+    face = r[0] >= 0.f ? 0 : 1;
+    ma = ax;
+    sc = r[0] >= 0.f ? -r[2] : r[2];
+    tc = -r[1];
+  } else if (ay >= az) {
+    face = r[1] >= 0.f ? 2 : 3;
+    ma = ay;
+    sc = r[0];
+    tc = r[1] >= 0.f ? r[2] : -r[2];
+  } else {
+    face = r[2] >= 0.f ? 4 : 5;
+    ma = az;
+    sc = r[2] >= 0.f ? r[0] : -r[0];
+    tc = -r[1];
+  }
+  const float im = 1.f / ma;
+  const float x = 0.5f * fmaf(sc, im, 1.f) * (float)R - 0.5f;
+  const float y = 0.5f * fmaf(tc, im, 1.f) * (float)R - 0.5f;
+  const float fx = floorf(x), fy = floorf(y);
+  const float wx = x - fx, wy = y - fy;
+  const int x0 = (int)fx, y0 = (int)fy;
+  const int xa = min(max(x0, 0), R - 1), xb = min(max(x0 + 1, 0), R - 1);
+  const int ya = min(max(y0, 0), R - 1), yb = min(max(y0 + 1, 0), R - 1);
+  CubeTap t;
+  const int fb = face * R * R;
+  t.idx[0] = 3 * (fb + ya * R + xa);
+  t.idx[1] = 3 * (fb + ya * R + xb);
+  t.idx[2] = 3 * (fb + yb * R + xa);
+  t.idx[3] = 3 * (fb + yb * R + xb);
+  t.w[0] = (1.f - wx) * (1.f - wy);
+  t.w[1] = wx * (1.f - wy);
+  t.w[2] = (1.f - wx) * wy;
+  t.w[3] = wx * wy;
+  t.base = (face * (R + 2) + (y0 + 1)) * (R + 2) + (x0 + 1);
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_sky(const DView* __restrict__ views,
+                                             const float* __restrict__ cube, int R,
+                                             float* __restrict__ bg) {
+  const DView& V = views[blockIdx.y];
+  const int64_t hw = (int64_t)V.width * V.height;
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pix >= hw) return;
+  const int px = (int)(pix % V.width), py = (int)(pix / V.width);
+  const CubeTap t = cube_tap(V, px, py, R);
+  float* o = bg + 3 * (int64_t)V.pix_base + pix;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v = fmaf(t.w[k], cube[t.idx[k] + c], v);
+    o[c * hw] = v;
+  }
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_sky_backward(const DView* __restrict__ views, int R,
+                                                      const float* __restrict__ px_T,
+                                                      const float* __restrict__ dL,
+                                                      float* __restrict__ d_cube) {
+  const DView& V = views[blockIdx.y];
+  const int64_t hw = (int64_t)V.width * V.height;
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = pix < hw;
+  const int px = valid ? (int)(pix % V.width) : 0, py = valid ? (int)(pix / V.width) : 0;
+  const CubeTap t = cube_tap(V, px, py, R);
+  float g[3] = {0.f, 0.f, 0.f};
+  if (valid) {
+    const float T = px_T[V.pix_base + pix];
+    const float* d = dL + 3 * (int64_t)V.pix_base + pix;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[c] = T * d[c * hw];
+  }
+  // Neighbouring pixels usually share one footprint: then the wave adds its 12 partial sums
+  // once; otherwise every lane adds its own.
+  const int base0 = __builtin_amdgcn_readfirstlane(t.base);
+  const bool same = __ballot(valid && t.base != base0) == 0ull;
+  if (same) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float s = wave_sum(t.w[k] * g[c]);
+        if (lane == 0 && s != 0.f) atomicAdd(d_cube + t.idx[k] + c, s);
+      }
+  } else if (valid) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (t.w[k] * g[c] != 0.f) atomicAdd(d_cube + t.idx[k] + c, t.w[k] * g[c]);
+  }
+}
+
+}  // namespace
+
+void sky_forward(const DView* views, int n_views, int max_pixels, const float* cube, int R,
+                 float* bg, hipStream_t st) {
+  if (n_views <= 0 || max_pixels <= 0) return;
+  hipLaunchKernelGGL(k_sky, dim3((unsigned)((max_pixels + 255) / 256), (unsigned)n_views),
+                     dim3(256), 0, st, views, cube, R, bg);
+}
+
+void sky_backward(const DView* views, int n_views, int max_pixels, int R, const float* px_T,
+                  const float* dL, float* d_cube, hipStream_t st) {
+  if (n_views <= 0 || max_pixels <= 0) return;
+  hipLaunchKernelGGL(k_sky_backward,
+                     dim3((unsigned)((max_pixels + 255) / 256), (unsigned)n_views), dim3(256), 0,
+                     st, views, R, px_T, dL, d_cube);
+}
+
+}  // namespace g4d

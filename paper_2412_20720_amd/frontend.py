@@ -122,6 +122,33 @@ class Renderer:
             None if df is None else df.data_ptr(), None if dg is None else dg.data_ptr(),
             _stream_handle(self.device)), self._ctx)
 
+    @staticmethod
+    def sky(cube: torch.Tensor) -> B.g4d_sky:
+        """Sky spec of a cube map [6, R, R, 3] (float32, contiguous, on the device)."""
+        if cube.dim() != 4 or cube.shape[0] != 6 or cube.shape[1] != cube.shape[2] or \
+                cube.shape[3] != 3 or cube.dtype != torch.float32 or not cube.is_contiguous():
+            raise ValueError("cube must be a contiguous float32 [6, R, R, 3] tensor")
+        return B.g4d_sky(cube.data_ptr(), int(cube.shape[1]))
+
+    def forward_sky(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, sky: B.g4d_sky,
+                    out_rgb: torch.Tensor, out_T: Optional[torch.Tensor]) -> None:
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        B.check(B.lib().g4d_render_sky_forward(
+            self._ctx, C.byref(g), va, len(va), C.byref(settings), C.byref(sky), out_rgb.data_ptr(),
+            None if out_T is None else out_T.data_ptr(), _stream_handle(self.device)), self._ctx)
+
+    def backward_sky(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, sky: B.g4d_sky,
+                     dL: torch.Tensor, grads: Dict[str, torch.Tensor]) -> None:
+        """grads: the parameter groups (optional mask/densify) and "cube" [6, R, R, 3]."""
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        gr = B.g4d_grads(*[grads[k].data_ptr() if grads.get(k) is not None else None
+                           for k in PARAM_NAMES + ("mask", "densify")])
+        dc = grads.get("cube")
+        B.check(B.lib().g4d_render_sky_backward(
+            self._ctx, C.byref(g), va, len(va), C.byref(settings), C.byref(sky), dL.data_ptr(),
+            C.byref(gr), None if dc is None else dc.data_ptr(), _stream_handle(self.device)),
+            self._ctx)
+
     def step(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
              out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
              grads: Dict[str, torch.Tensor], graph: bool = True) -> None:
@@ -257,6 +284,33 @@ class _RenderChannels(torch.autograd.Function):
                 (grads.get("features"), grads.get("gate")))
 
 
+class _RenderSky(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, mean4, scale4,
+                rot_l, rot_r, opacity, sh, cube):
+        g = renderer.gaussians(mean4, scale4, rot_l, rot_r, opacity, sh, sh_degree, t_degree)
+        va = B.make_views(views)
+        npix = Renderer.pixel_count(views)
+        rgb = torch.empty(3 * npix, device=renderer.device)
+        T = torch.empty(npix, device=renderer.device)
+        renderer.forward_sky(g, va, settings, Renderer.sky(cube), rgb, T)
+        ctx.renderer, ctx.views, ctx.settings = renderer, va, settings
+        ctx.degrees = (sh_degree, t_degree)
+        ctx.save_for_backward(mean4, scale4, rot_l, rot_r, opacity, sh, cube)
+        ctx.mark_non_differentiable(T)
+        return rgb, T
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_T):
+        *params, cube = ctx.saved_tensors
+        r: Renderer = ctx.renderer
+        g = r.gaussians(*params, *ctx.degrees)
+        grads = {k: torch.empty_like(p) for k, p in zip(PARAM_NAMES, params)}
+        grads["cube"] = torch.empty_like(cube)
+        r.backward_sky(g, ctx.views, ctx.settings, Renderer.sky(cube), d_rgb.contiguous(), grads)
+        return (None,) * 5 + tuple(grads[k] for k in PARAM_NAMES) + (grads["cube"],)
+
+
 def split_views(flat: torch.Tensor, views, channels: int) -> List[torch.Tensor]:
     out, off = [], 0
     for v in views:
@@ -306,3 +360,15 @@ def render_channels(mean4, scale4, rot_l, rot_r, opacity, sh, views: Sequence[di
                                        features, gate)
     return (split_views(rgb, views, 3), [t[0] for t in split_views(T, views, 1)],
             split_views(ch, views, E))
+
+
+def render_sky(mean4, scale4, rot_l, rot_r, opacity, sh, cube, views: Sequence[dict], *,
+               sh_degree: int, t_degree: int, renderer: Renderer,
+               settings: Optional[B.g4d_settings] = None):
+    """Differentiable render with a learnable cube-map sky [6, R, R, 3] as every pixel's
+    background (urban scenes).  Returns (images, transmittances) per view; gradients reach the
+    parameters and the cube map."""
+    s = settings if settings is not None else B.default_settings()
+    rgb, T = _RenderSky.apply(renderer, list(views), s, sh_degree, t_degree, mean4, scale4,
+                              rot_l, rot_r, opacity, sh, cube.contiguous())
+    return split_views(rgb, views, 3), [t[0] for t in split_views(T, views, 1)]

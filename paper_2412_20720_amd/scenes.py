@@ -253,6 +253,12 @@ def make_mask(scene: Scene, seed: int = 14) -> np.ndarray:
     return rng.uniform(0.0, 1.0, scene.n).astype(np.float32)
 
 
+def make_cube(resolution: int = 16, seed: int = 15) -> np.ndarray:
+    """A sky cube map [6, R, R, 3] ~ U(0, 1), float32 (the urban sky model is learned)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, (6, resolution, resolution, 3)).astype(np.float32)
+
+
 def subset(scene: Scene, idx) -> Scene:
     """Scene restricted to the Gaussians ``idx`` (same views)."""
     idx = np.asarray(idx)
