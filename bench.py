@@ -195,6 +195,7 @@ def main():
     if args.channels >= 0:
         chan = channel_step(r, g, views, settings, sc, p, dL, args, npix)
     train = training_step(r, views, settings, sc, p, dL, args, npix)
+    sky = sky_step(r, g, views, settings, sc, dL, args, npix)
 
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
@@ -234,6 +235,7 @@ def main():
         "alg_bound": alg_bound,
         "channels": chan,
         "training_fusion": train,
+        "sky": sky,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
                  "evaluated_pairs": evals, "composited_pairs": contrib},
@@ -320,6 +322,39 @@ def training_step(r, views, settings, sc, p, dL, args, npix):
         f"{npix / dt / 1e6:.1f} Mpix/s")
     return dict(mask_threshold=0.1, kept=float((mask > 0.1).float().mean()), value=npix / dt / 1e6,
                 unit="Mpix/s", ms_per_step=dt * 1e3)
+
+
+def sky_step(r, g, views, settings, sc, dL, args, npix):
+    """The step with a learnable 256 x 256 cube-map sky as the background (urban scenes):
+    sky lookup, composite, and the cube-map gradient in the backward."""
+    import torch
+    from paper_2412_20720_amd import scenes
+    from paper_2412_20720_amd.frontend import Renderer
+    dev = dL.device
+    cube = torch.from_numpy(scenes.make_cube(256)).to(dev)
+    sk = Renderer.sky(cube)
+    rgb = torch.empty(3 * npix, device=dev)
+    T = torch.empty(npix, device=dev)
+    names = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
+    grads = {k: torch.empty((g.n,) + s, device=dev) for k, s in
+             zip(names, ((4,), (4,), (4,), (4,), (), (g.t_degree + 1, (g.sh_degree + 1) ** 2, 3)))}
+    grads["cube"] = torch.empty_like(cube)
+
+    def step():
+        r.forward_sky(g, views, settings, sk, rgb, T)
+        r.backward_sky(g, views, settings, sk, dL, grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    r.sync()
+    log(f"bench: sky (256^2 cube map): {dt * 1e3:.3f} ms/step, {npix / dt / 1e6:.1f} Mpix/s")
+    return dict(resolution=256, value=npix / dt / 1e6, unit="Mpix/s", ms_per_step=dt * 1e3)
 
 
 def cpu_baseline(sc, n_views):

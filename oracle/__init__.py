@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
         L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Grads),
                                          C.c_void_p, C.c_void_p]
         L.orc_frame_backward_splat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_decode_compact.argtypes = [C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 5 + \
+            [C.c_double, C.c_double] + [C.c_void_p] * 12
         L.orc_sky.argtypes = [C.POINTER(_View), dp, C.c_int, C.c_double, dp, dp, C.c_void_p]
         L.orc_sky_backward.argtypes = [C.POINTER(_View), C.c_int, dp, dp]
         L.orc_frame_set_background.argtypes = [C.c_void_p, C.c_void_p]
@@ -172,6 +174,27 @@ def _make_view(view: Dict, exact_f64: bool) -> "_View":
                  (C.c_double * 12)(*[conv_s(x) for x in np.asarray(view["world_to_cam"]).ravel()]),
                  conv_s(view["t"]),
                  (C.c_double * 3)(*[conv_s(x) for x in np.asarray(view["background"]).ravel()]))
+
+
+def decode_compact(c: Dict) -> Dict[str, np.ndarray]:
+    """Full float64 parameters of a compact model (see ``scenes.make_compact``): mean4, scale4,
+    rot_l, rot_r, opacity, sh [n, t+1, (s+1)^2, 3]."""
+    n, ds, dt = int(c["n"]), int(c["sh_degree"]), int(c["t_degree"])
+    K = (dt + 1) * (ds + 1) ** 2 * 3
+    u8 = lambda k: np.ascontiguousarray(c[k], np.uint8)
+    cb = lambda k: np.ascontiguousarray(np.asarray(c[k], np.float32), np.float64)
+    out = dict(mean4=np.zeros((n, 4)), scale4=np.zeros((n, 4)), rot_l=np.zeros((n, 4)),
+               rot_r=np.zeros((n, 4)), opacity=np.zeros(n), sh=np.zeros((n, dt + 1, (ds + 1) ** 2, 3)))
+    keep = [np.ascontiguousarray(c["mean4_h"], np.uint16), u8("scale_idx"), u8("rot_l_idx"),
+            u8("rot_r_idx"), u8("opacity_q"), u8("dc_idx"), u8("rest_idx"), cb("scale_cb"),
+            cb("rot_cb"), cb("dc_cb"), cb("rest_cb")]
+    assert keep[-1].shape == (8, 256, K - 3)
+    lib().orc_decode_compact(
+        n, ds, dt, *[a.ctypes.data for a in keep[:5]],
+        float(np.float32(c["op_lo"])), float(np.float32(c["op_hi"])),
+        *[a.ctypes.data for a in keep[5:]], *[out[k].ctypes.data for k in
+                                              ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")])
+    return out
 
 
 def sky(view: Dict, cube: np.ndarray, margin: float = 1e-5, exact_f64: bool = False):

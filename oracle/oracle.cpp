@@ -40,6 +40,13 @@
 // densification in spacetime): per view, |dL/d mean2d| of every Gaussian alive in it; the
 // |dL/d mu_t| indicator is the mean4 gradient's time component.
 //
+// Compact 4DGS decode (Sec. 4.2 parameter compression; codebook sizes of Sec. 8.3): residual
+// vector quantization sums one codeword of each codebook, x = sum_k C_k[i_k]: scale (6 x 64,
+// in log space, s = exp(x) -- reading: the scale is quantized before its activation), rotors
+// (one 6 x 64 model shared by q_l and q_r, each with its own indices), 4DSH direct component
+// (6 x 64) and the rest (8 x 256); positions stored as IEEE half; opacity by 8-bit min-max
+// quantization, o = lo + (hi - lo) q / 255.
+//
 // Sky (optional, Sec. 5, urban scenes): I = I_gs + (1 - O_gs) M_sky(r) = C + T M_sky(r), a cube
 // map queried by the world direction r of the pixel's ray (the background of that pixel).
 // Readings: the OpenGL cube-map convention (faces +x, -x, +y, -y, +z, -z; the major axis of r
@@ -1213,6 +1220,59 @@ int orc_frame_set_background(void* h, const double* bg) {
     return 0;
   }
   f.bg_px.assign(bg, bg + 3 * (size_t)f.vw.width * f.vw.height);
+  return 0;
+}
+
+// Decode a compact model into full parameters (float64; see the file header).  mean4_h holds
+// IEEE half bit patterns.  Codebooks: scale [6][64][4], rot [6][64][4], dc [6][64][3],
+// rest [8][256][K - 3] with K = (t_degree + 1)(sh_degree + 1)^2 3; sh out [n][K] with the
+// direct component (n = 0, l = 0) first.
+int orc_decode_compact(int n, int sh_degree, int t_degree, const uint16_t* mean4_h,
+                       const uint8_t* scale_idx, const uint8_t* rot_l_idx,
+                       const uint8_t* rot_r_idx, const uint8_t* opacity_q, double op_lo,
+                       double op_hi, const uint8_t* dc_idx, const uint8_t* rest_idx,
+                       const double* scale_cb, const double* rot_cb, const double* dc_cb,
+                       const double* rest_cb, double* mean4, double* scale4, double* rot_l,
+                       double* rot_r, double* opacity, double* sh) {
+  const int K = (t_degree + 1) * (sh_degree + 1) * (sh_degree + 1) * 3;
+  const int KR = K - 3;
+  auto half_to_double = [](uint16_t h) {
+    const int sign = (h >> 15) & 1, e = (h >> 10) & 31, m = h & 1023;
+    double v;
+    if (e == 0)
+      v = std::ldexp((double)m, -24);  // subnormal
+    else if (e == 31)
+      v = m ? NAN : INFINITY;
+    else
+      v = std::ldexp((double)(m + 1024), e - 25);
+    return sign ? -v : v;
+  };
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < 4; ++k) mean4[4 * i + k] = half_to_double(mean4_h[4 * i + k]);
+    for (int k = 0; k < 4; ++k) {
+      double ls = 0.0, ql = 0.0, qr = 0.0;
+      for (int c = 0; c < 6; ++c) {
+        ls += scale_cb[(c * 64 + scale_idx[6 * i + c]) * 4 + k];
+        ql += rot_cb[(c * 64 + rot_l_idx[6 * i + c]) * 4 + k];
+        qr += rot_cb[(c * 64 + rot_r_idx[6 * i + c]) * 4 + k];
+      }
+      scale4[4 * i + k] = std::exp(ls);
+      rot_l[4 * i + k] = ql;
+      rot_r[4 * i + k] = qr;
+    }
+    opacity[i] = op_lo + (op_hi - op_lo) * (double)opacity_q[i] / 255.0;
+    double* o = sh + (size_t)i * K;
+    for (int ch = 0; ch < 3; ++ch) {
+      double v = 0.0;
+      for (int c = 0; c < 6; ++c) v += dc_cb[(c * 64 + dc_idx[6 * i + c]) * 3 + ch];
+      o[ch] = v;
+    }
+    for (int j = 0; j < KR; ++j) {
+      double v = 0.0;
+      for (int c = 0; c < 8; ++c) v += rest_cb[((size_t)c * 256 + rest_idx[8 * i + c]) * KR + j];
+      o[3 + j] = v;
+    }
+  }
   return 0;
 }
 

@@ -259,6 +259,41 @@ def make_cube(resolution: int = 16, seed: int = 15) -> np.ndarray:
     return rng.uniform(0.0, 1.0, (6, resolution, resolution, 3)).astype(np.float32)
 
 
+def make_compact(n: int, sh_degree: int = 3, t_degree: int = 1, extent: float = 2.0,
+                 seed: int = 16) -> Dict[str, np.ndarray]:
+    """A synthetic compact model with the layout of the compact 4DGS (residual VQ codebooks
+    of 6 x 64 for the log-scale, the rotors and the direct color component, 8 x 256 for the
+    rest of the 4DSH; half-precision positions; 8-bit min-max opacity).  The first codebook
+    of each model carries the bulk of the value and the others small residuals, so that the
+    decoded parameters follow the distributions of the workloads above."""
+    rng = np.random.default_rng(seed)
+    K = (t_degree + 1) * (sh_degree + 1) ** 2 * 3
+
+    def cb(shape, first, rest):
+        c = rng.normal(0.0, rest, shape)
+        c[0] = first(shape[1:])
+        return c.astype(np.float32)
+
+    y00 = 0.28209479177387814
+    m4 = np.concatenate([rng.uniform(-extent, extent, (n, 3)), rng.uniform(0.0, 1.0, (n, 1))], 1)
+    return dict(
+        n=n, sh_degree=sh_degree, t_degree=t_degree,
+        mean4_h=m4.astype(np.float16).view(np.uint16),
+        scale_idx=rng.integers(0, 64, (n, 6), dtype=np.uint8),
+        rot_l_idx=rng.integers(0, 64, (n, 6), dtype=np.uint8),
+        rot_r_idx=rng.integers(0, 64, (n, 6), dtype=np.uint8),
+        opacity_q=rng.integers(0, 256, n, dtype=np.uint8), op_lo=np.float32(0.02),
+        op_hi=np.float32(0.98),
+        dc_idx=rng.integers(0, 64, (n, 6), dtype=np.uint8),
+        rest_idx=rng.integers(0, 256, (n, 8), dtype=np.uint8),
+        scale_cb=cb((6, 64, 4), lambda s: np.stack([rng.normal(-3.0, 0.5, s[0])] * 3 +
+                                                   [rng.normal(-2.0, 0.5, s[0])], 1), 0.05),
+        rot_cb=cb((6, 64, 4), lambda s: rng.normal(0.0, 1.0, s), 0.1),
+        dc_cb=cb((6, 64, 3), lambda s: (rng.uniform(0.0, 1.0, s) - 0.5) / y00, 0.05),
+        rest_cb=cb((8, 256, K - 3), lambda s: rng.normal(0.0, 0.1, s), 0.02),
+    )
+
+
 def subset(scene: Scene, idx) -> Scene:
     """Scene restricted to the Gaussians ``idx`` (same views)."""
     idx = np.asarray(idx)

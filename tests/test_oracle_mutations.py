@@ -13,7 +13,8 @@ PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
         os.path.join(ROOT, "tests", "test_oracle_gradients.py"),
         os.path.join(ROOT, "tests", "test_oracle_channels.py"),
         os.path.join(ROOT, "tests", "test_oracle_training.py"),
-        os.path.join(ROOT, "tests", "test_oracle_sky.py")]
+        os.path.join(ROOT, "tests", "test_oracle_sky.py"),
+        os.path.join(ROOT, "tests", "test_oracle_compact.py")]
 
 # (name, exact text in oracle.cpp, replacement)
 MUTATIONS = [
@@ -65,6 +66,13 @@ MUTATIONS = [
      "const double wx[2] = {ax, 1.0 - ax}, wy[2] = {1.0 - ay, ay};"),
     ("backward ignores the per-pixel background", "  double R[3] = {bg[0], bg[1], bg[2]};",
      "  double R[3] = {f.vw.background[0], f.vw.background[1], f.vw.background[2]};"),
+    ("compact scale not exponentiated", "scale4[4 * i + k] = std::exp(ls);",
+     "scale4[4 * i + k] = ls;"),
+    ("compact right rotor with the left indices",
+     "qr += rot_cb[(c * 64 + rot_r_idx[6 * i + c]) * 4 + k];",
+     "qr += rot_cb[(c * 64 + rot_l_idx[6 * i + c]) * 4 + k];"),
+    ("half exponent bias", "v = std::ldexp((double)(m + 1024), e - 25);",
+     "v = std::ldexp((double)(m + 1024), e - 24);"),
     ("mask threshold inclusive", "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold)) {",
      "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold + 0.2)) {"),
 ]
