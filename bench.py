@@ -196,6 +196,7 @@ def main():
         chan = channel_step(r, g, views, settings, sc, p, dL, args, npix)
     train = training_step(r, views, settings, sc, p, dL, args, npix)
     sky = sky_step(r, g, views, settings, sc, dL, args, npix)
+    compact = compact_forward(r, views, settings, sc, args, npix)
 
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
@@ -236,6 +237,7 @@ def main():
         "channels": chan,
         "training_fusion": train,
         "sky": sky,
+        "compact": compact,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
                  "evaluated_pairs": evals, "composited_pairs": contrib},
@@ -355,6 +357,47 @@ def sky_step(r, g, views, settings, sc, dL, args, npix):
     r.sync()
     log(f"bench: sky (256^2 cube map): {dt * 1e3:.3f} ms/step, {npix / dt / 1e6:.1f} Mpix/s")
     return dict(resolution=256, value=npix / dt / 1e6, unit="Mpix/s", ms_per_step=dt * 1e3)
+
+
+def compact_forward(r, views, settings, sc, args, npix):
+    """Forward-only render of a compact model with the workload's Gaussian count and degrees
+    (residual-VQ codebooks, half positions, 8-bit opacity), decoded inside the preprocess,
+    against the forward of the same model decoded to full arrays."""
+    import torch
+    from paper_2412_20720_amd import scenes
+    dev = torch.device("cuda", 0)
+    c = scenes.make_compact(sc.n, sc.sh_degree, sc.t_degree)
+    cd = dict(c)
+    for k in ("mean4_h", "scale_idx", "rot_l_idx", "rot_r_idx", "opacity_q", "dc_idx", "rest_idx",
+              "scale_cb", "rot_cb", "dc_cb", "rest_cb"):
+        a = np.ascontiguousarray(c[k])
+        cd[k] = torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).to(dev)
+    d = r.decode_compact(cd)
+    g = r.gaussians(*[d[k] for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")],
+                    sc.sh_degree, sc.t_degree)
+    rgb = torch.empty(3 * npix, device=dev)
+    T = torch.empty(npix, device=dev)
+    out = {}
+    for name, fwd in (("compact", lambda: r.forward_compact(cd, views, settings, rgb, T)),
+                      ("full", lambda: r.forward(g, views, settings, rgb, T))):
+        for _ in range(args.warmup):
+            fwd()
+        torch.cuda.synchronize()
+        r.profile(True, collect=True, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fwd()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        st = r.profile(False, collect=True, reset=True)
+        out[name] = dict(ms=dt * 1e3, mpix_s=npix / dt / 1e6,
+                         preprocess_ms=st["preprocess"][0] / max(1, st["preprocess"][1]))
+    r.sync()
+    log(f"bench: compact forward {out['compact']['ms']:.3f} ms (preprocess "
+        f"{out['compact']['preprocess_ms']:.3f} ms), decoded full forward {out['full']['ms']:.3f} ms "
+        f"(preprocess {out['full']['preprocess_ms']:.3f} ms)")
+    return dict(forward_only=True, **out)
 
 
 def cpu_baseline(sc, n_views):

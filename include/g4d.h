@@ -246,6 +246,40 @@ g4d_status g4d_render_sky_backward(g4d_ctx *ctx, const g4d_gaussians *g, const g
                                    const float *dL_drgb, const g4d_grads *out, float *d_cube,
                                    void *stream);
 
+/* Compact 4DGS (Sec. 4.2 parameter compression; codebook sizes of Sec. 8.3).  Residual vector
+ * quantization stores per Gaussian one index into each codebook of a model and decodes the
+ * sum of the selected codewords:
+ *   scale4  = exp(sum_k scale_cb[k][scale_idx[i][k]])   (6 codebooks of 64 x 4, log space)
+ *   rot_l   = sum_k rot_cb[k][rot_l_idx[i][k]], rot_r likewise with rot_r_idx (one model of 6
+ *             codebooks of 64 x 4 shared by both rotors)
+ *   sh[i][0][0][:] = sum_k dc_cb[k][dc_idx[i][k]]   (6 x 64 x 3, the direct component)
+ *   the other K - 3 coefficients of sh[i], in order, = sum_k rest_cb[k][rest_idx[i][k]]
+ *             (8 codebooks of 256 x (K - 3)), K = (t_degree + 1)(sh_degree + 1)^2 3
+ *   mean4   = the IEEE half values mean4_h[i][0..3]
+ *   opacity = opacity_lo + (opacity_hi - opacity_lo) opacity_q[i] / 255 (8-bit min-max).
+ * Index arrays are row-major uint8 [N][6] ([N][8] for rest_idx), codebooks row-major float32;
+ * all arrays are device memory. */
+typedef struct {
+  int32_t n, sh_degree, t_degree;
+  const uint16_t *mean4_h;
+  const uint8_t *scale_idx, *rot_l_idx, *rot_r_idx, *opacity_q, *dc_idx, *rest_idx;
+  float opacity_lo, opacity_hi;
+  const float *scale_cb, *rot_cb, *dc_cb, *rest_cb;
+} g4d_compact;
+
+/* Decode a compact model into the full parameter arrays of g4d_gaussians (device, caller
+ * owned; for training or fine-tuning with g4d_render_forward/_backward). */
+g4d_status g4d_decode_compact(g4d_ctx *ctx, const g4d_compact *c, float *mean4, float *scale4,
+                              float *rot_l, float *rot_r, float *opacity, float *sh,
+                              void *stream);
+
+/* Forward render of a compact model, decoding inside the per-Gaussian preprocess (no full
+ * parameter arrays are read or written).  Same outputs as g4d_render_forward; it leaves no
+ * state for a backward (decode first to train). */
+g4d_status g4d_render_compact_forward(g4d_ctx *ctx, const g4d_compact *c, const g4d_view *views,
+                                      int32_t n_views, const g4d_settings *s, float *out_rgb,
+                                      float *out_T, void *stream);
+
 /* Flags of g4d_render_step. */
 #define G4D_STEP_GRAPH 1
 

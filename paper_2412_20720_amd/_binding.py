@@ -20,7 +20,8 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_preprocess", "g4d_render_forward", "g4d_render_backward", "g4d_sync_status",
             "g4d_get_stats", "g4d_eval_counters", "g4d_autotune", "g4d_profile",
             "g4d_stage_name", "g4d_render_step", "g4d_render_channels_forward",
-            "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward"]
+            "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward",
+            "g4d_decode_compact", "g4d_render_compact_forward"]
 G4D_STEP_GRAPH = 1
 G4D_NUM_STAGES = 11
 G4D_MAX_CHANNELS = 36
@@ -60,6 +61,15 @@ class g4d_channels(C.Structure):
 
 class g4d_sky(C.Structure):
     _fields_ = [("cube", C.c_void_p), ("resolution", C.c_int32)]
+
+
+class g4d_compact(C.Structure):
+    _fields_ = [("n", C.c_int32), ("sh_degree", C.c_int32), ("t_degree", C.c_int32),
+                ("mean4_h", C.c_void_p), ("scale_idx", C.c_void_p), ("rot_l_idx", C.c_void_p),
+                ("rot_r_idx", C.c_void_p), ("opacity_q", C.c_void_p), ("dc_idx", C.c_void_p),
+                ("rest_idx", C.c_void_p), ("opacity_lo", C.c_float), ("opacity_hi", C.c_float),
+                ("scale_cb", C.c_void_p), ("rot_cb", C.c_void_p), ("dc_cb", C.c_void_p),
+                ("rest_cb", C.c_void_p)]
 
 
 class g4d_stats(C.Structure):
@@ -112,6 +122,9 @@ def lib() -> C.CDLL:
     L.g4d_render_sky_backward.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
                                           C.POINTER(g4d_settings), C.POINTER(g4d_sky), vp,
                                           C.POINTER(g4d_grads), vp, vp]
+    L.g4d_decode_compact.argtypes = [vp, C.POINTER(g4d_compact), vp, vp, vp, vp, vp, vp, vp]
+    L.g4d_render_compact_forward.argtypes = [vp, C.POINTER(g4d_compact), C.POINTER(g4d_view), i32,
+                                             C.POINTER(g4d_settings), vp, vp, vp]
     L.g4d_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
     L.g4d_stage_name.argtypes = [C.c_int]
     L.g4d_stage_name.restype = C.c_char_p

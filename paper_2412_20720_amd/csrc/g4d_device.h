@@ -551,6 +551,59 @@ __device__ __forceinline__ void view_backward(const Geom& g, const float4 mean, 
   gmean[3] -= gdt2 + gdt;
 }
 
+// Compact 4DGS decode of one Gaussian (residual VQ: the sum of one codeword per codebook,
+// summed in codebook order; half positions; 8-bit min-max opacity).  NSH = the 4DSH
+// coefficient count K; the direct component fills sh[0..2], the rest sh[3..K-1].
+struct CompactPtrs {
+  const uint16_t* mean4_h;
+  const uint8_t *scale_idx, *rot_l_idx, *rot_r_idx, *opacity_q, *dc_idx, *rest_idx;
+  float op_lo, op_hi;
+  const float *scale_cb, *rot_cb, *dc_cb, *rest_cb;
+};
+
+template <int NSH>
+__device__ __forceinline__ void decode_compact(const CompactPtrs& c, int i, float4& mean,
+                                               float4& scale, float4& ql, float4& qr, float& op,
+                                               float* sh) {
+  const uint16_t* mh = c.mean4_h + 4 * (size_t)i;
+  mean = make_float4((float)__builtin_bit_cast(_Float16, mh[0]),
+                     (float)__builtin_bit_cast(_Float16, mh[1]),
+                     (float)__builtin_bit_cast(_Float16, mh[2]),
+                     (float)__builtin_bit_cast(_Float16, mh[3]));
+  float ls[4] = {0.f, 0.f, 0.f, 0.f}, l[4] = {0.f, 0.f, 0.f, 0.f}, r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float4 a = reinterpret_cast<const float4*>(c.scale_cb)[k * 64 + c.scale_idx[6 * (size_t)i + k]];
+    const float4 b = reinterpret_cast<const float4*>(c.rot_cb)[k * 64 + c.rot_l_idx[6 * (size_t)i + k]];
+    const float4 d = reinterpret_cast<const float4*>(c.rot_cb)[k * 64 + c.rot_r_idx[6 * (size_t)i + k]];
+    ls[0] += a.x; ls[1] += a.y; ls[2] += a.z; ls[3] += a.w;
+    l[0] += b.x; l[1] += b.y; l[2] += b.z; l[3] += b.w;
+    r[0] += d.x; r[1] += d.y; r[2] += d.z; r[3] += d.w;
+  }
+  scale = make_float4(expf(ls[0]), expf(ls[1]), expf(ls[2]), expf(ls[3]));
+  ql = make_float4(l[0], l[1], l[2], l[3]);
+  qr = make_float4(r[0], r[1], r[2], r[3]);
+  op = fmaf(c.op_hi - c.op_lo, (float)c.opacity_q[i] * (1.f / 255.f), c.op_lo);
+#pragma unroll
+  for (int j = 0; j < NSH; ++j) sh[j] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float* w = c.dc_cb + 3 * (k * 64 + c.dc_idx[6 * (size_t)i + k]);
+    sh[0] += w[0];
+    sh[1] += w[1];
+    sh[2] += w[2];
+  }
+  constexpr int KR = NSH - 3;
+  if constexpr (KR > 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float* w = c.rest_cb + (size_t)KR * (k * 256 + c.rest_idx[8 * (size_t)i + k]);
+#pragma unroll
+      for (int j = 0; j < KR; ++j) sh[3 + j] += w[j];
+    }
+  }
+}
+
 // Adjoint of geom_forward: from gM (4x4) to the scale and the raw rotors.
 __device__ __forceinline__ void geom_backward(const Geom& g, const float4 sc, const float gM[4][4],
                                               float gscale[4], float gql[4], float gqr[4]) {

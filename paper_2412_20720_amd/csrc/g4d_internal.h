@@ -57,6 +57,7 @@ struct GaussPtrs {
   const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
   const float* mask;      // optional volume mask (kept when mask > mask_thr)
   float mask_thr;
+  const CompactPtrs* compact = nullptr;  // set: decode a compact model in the preprocess
 };
 struct GradPtrs {
   float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
@@ -65,6 +66,9 @@ struct GradPtrs {
 
 void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
                         float* rec, uint32_t* tiles, uint32_t* dkey, hipStream_t st);
+void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
+                           float* mean4, float* scale4, float* rot_l, float* rot_r,
+                           float* opacity, float* sh, hipStream_t st);
 void preprocess_backward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
                          const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
                          hipStream_t st);

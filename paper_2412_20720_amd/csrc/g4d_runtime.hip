@@ -171,7 +171,7 @@ T* P(DevBuf& b) {
 bool finite(float x) { return std::isfinite(x); }
 
 g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
-                        int32_t n_views, const g4d_settings* s) {
+                        int32_t n_views, const g4d_settings* s, bool params = true) {
   if (!ctx) return G4D_EINVAL;
   if (!g || !views || !s) return fail(ctx, G4D_EINVAL, "null gaussians, views or settings");
   if (g->n < 0) return fail(ctx, G4D_EINVAL, "n = %d < 0", g->n);
@@ -179,7 +179,8 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     return fail(ctx, G4D_EINVAL, "sh_degree %d outside 0..%d", g->sh_degree, G4D_MAX_SH_DEGREE);
   if (g->t_degree < 0 || g->t_degree > G4D_MAX_T_DEGREE)
     return fail(ctx, G4D_EINVAL, "t_degree %d outside 0..%d", g->t_degree, G4D_MAX_T_DEGREE);
-  if (g->n > 0 && (!g->mean4 || !g->scale4 || !g->rot_l || !g->rot_r || !g->opacity || !g->sh))
+  if (params && g->n > 0 &&
+      (!g->mean4 || !g->scale4 || !g->rot_l || !g->rot_r || !g->opacity || !g->sh))
     return fail(ctx, G4D_EINVAL, "null Gaussian parameter array");
   if (g->mask && std::isnan(g->mask_threshold)) return fail(ctx, G4D_EINVAL, "mask_threshold NaN");
   if (n_views < 1 || n_views > G4D_MAX_VIEWS)
@@ -331,7 +332,8 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
 }
 
 g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
-                          const g4d_settings* s, hipStream_t st, bool zero_records = false) {
+                          const g4d_settings* s, hipStream_t st, bool zero_records = false,
+                          const CompactPtrs* cp = nullptr) {
   const int64_t slots = (int64_t)g->n * n_views;
   g4d_status r;
   if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
@@ -340,7 +342,9 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
   if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   {
     Stage t(ctx, 0, st);
-    preprocess_forward(gauss_ptrs(g), P<DView>(ctx->views), n_views, device_settings(s),
+    GaussPtrs gp = gauss_ptrs(g);
+    gp.compact = cp;
+    preprocess_forward(gp, P<DView>(ctx->views), n_views, device_settings(s),
                        P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
   }
   G4D_HIP(hipGetLastError());
@@ -471,8 +475,8 @@ g4d_status g4d_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* 
 static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
                                int32_t n_views, const g4d_settings* s, const g4d_channels* ch,
                                const g4d_sky* sky, float* out_rgb, float* out_T, float* out_ch,
-                               void* stream) {
-  g4d_status r = check_common(ctx, g, views, n_views, s);
+                               void* stream, const CompactPtrs* cp = nullptr) {
+  g4d_status r = check_common(ctx, g, views, n_views, s, cp == nullptr);
   if (r != G4D_OK) return r;
   if (!out_rgb) return fail(ctx, G4D_EINVAL, "null out_rgb");
   if (sky && (!sky->cube || sky->resolution < 1 || sky->resolution > G4D_MAX_SKY_RES))
@@ -509,7 +513,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   int64_t n_vis = 0, n_pairs = 0;
   int pb = 0;
   if (slots > 0) {
-    if ((r = run_preprocess(ctx, g, n_views, &s_run, st)) != G4D_OK) return r;
+    if ((r = run_preprocess(ctx, g, n_views, &s_run, st, false, cp)) != G4D_OK) return r;
     if (ch && ch->n_features > 0) {
       if ((r = ensure(ctx, ctx->fn, sizeof(float) * (size_t)g->n * ch->n_features, 1.1)) != G4D_OK)
         return r;
@@ -654,7 +658,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   k.ch = ch ? *ch : g4d_channels{};
   k.sky_cube = sky ? sky->cube : nullptr;
   k.sky_res = sky ? sky->resolution : 0;
-  ctx->saved = true;
+  ctx->saved = cp == nullptr;  // a compact forward has no parameter arrays to differentiate
   return G4D_OK;
 }
 
@@ -783,6 +787,57 @@ g4d_status g4d_render_channels_backward(g4d_ctx* ctx, const g4d_gaussians* g,
   if (!ch) return fail(ctx, G4D_EINVAL, "null channels");
   return backward_impl(ctx, g, views, n_views, s, ch, nullptr, dL_drgb, dL_dch, out, d_features,
                        d_gate, nullptr, stream);
+}
+
+static CompactPtrs compact_ptrs(const g4d_compact* c) {
+  return CompactPtrs{c->mean4_h,  c->scale_idx,  c->rot_l_idx, c->rot_r_idx, c->opacity_q,
+                     c->dc_idx,   c->rest_idx,   c->opacity_lo, c->opacity_hi, c->scale_cb,
+                     c->rot_cb,   c->dc_cb,      c->rest_cb};
+}
+
+static g4d_status check_compact(g4d_ctx* ctx, const g4d_compact* c) {
+  if (!c) return fail(ctx, G4D_EINVAL, "null compact model");
+  if (c->n < 0 || c->sh_degree < 0 || c->sh_degree > G4D_MAX_SH_DEGREE || c->t_degree < 0 ||
+      c->t_degree > G4D_MAX_T_DEGREE)
+    return fail(ctx, G4D_EINVAL, "compact model: bad n or degrees");
+  const bool rest = (c->t_degree + 1) * (c->sh_degree + 1) * (c->sh_degree + 1) > 1;
+  if (c->n > 0 && (!c->mean4_h || !c->scale_idx || !c->rot_l_idx || !c->rot_r_idx ||
+                   !c->opacity_q || !c->dc_idx || !c->scale_cb || !c->rot_cb || !c->dc_cb ||
+                   (rest && (!c->rest_idx || !c->rest_cb))))
+    return fail(ctx, G4D_EINVAL, "compact model: null array");
+  if (!std::isfinite(c->opacity_lo) || !std::isfinite(c->opacity_hi))
+    return fail(ctx, G4D_EINVAL, "compact model: opacity range not finite");
+  return G4D_OK;
+}
+
+g4d_status g4d_decode_compact(g4d_ctx* ctx, const g4d_compact* c, float* mean4, float* scale4,
+                              float* rot_l, float* rot_r, float* opacity, float* sh,
+                              void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  g4d_status r = check_compact(ctx, c);
+  if (r != G4D_OK) return r;
+  if (c->n > 0 && (!mean4 || !scale4 || !rot_l || !rot_r || !opacity || !sh))
+    return fail(ctx, G4D_EINVAL, "null output array");
+  G4D_HIP(hipSetDevice(ctx->device));
+  decode_compact_params(c->n, c->sh_degree, c->t_degree, compact_ptrs(c), mean4, scale4, rot_l,
+                        rot_r, opacity, sh, static_cast<hipStream_t>(stream));
+  G4D_HIP(hipGetLastError());
+  return G4D_OK;
+}
+
+g4d_status g4d_render_compact_forward(g4d_ctx* ctx, const g4d_compact* c, const g4d_view* views,
+                                      int32_t n_views, const g4d_settings* s, float* out_rgb,
+                                      float* out_T, void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  g4d_status r = check_compact(ctx, c);
+  if (r != G4D_OK) return r;
+  g4d_gaussians g{};
+  g.n = c->n;
+  g.sh_degree = c->sh_degree;
+  g.t_degree = c->t_degree;
+  const CompactPtrs cp = compact_ptrs(c);
+  return forward_impl(ctx, &g, views, n_views, s, nullptr, nullptr, out_rgb, out_T, nullptr,
+                      stream, &cp);
 }
 
 g4d_status g4d_render_sky_forward(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,

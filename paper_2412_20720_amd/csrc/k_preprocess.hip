@@ -12,14 +12,15 @@
 namespace g4d {
 namespace {
 
-template <int DS, int DT>
+// CP: the parameters come from a compact model, decoded here in registers (Sec. 4.2).
+template <int DS, int DT, bool CP>
 __global__ __launch_bounds__(256) void k_preprocess(
     int n, int n_views, const float4* __restrict__ mean4, const float4* __restrict__ scale4,
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
     uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey, const float* __restrict__ mask,
-    float mask_thr) {
+    float mask_thr, CompactPtrs cp) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n) return;
@@ -28,14 +29,23 @@ __global__ __launch_bounds__(256) void k_preprocess(
     for (int v = 0; v < n_views; ++v) tiles[(size_t)v * n + gi] = 0u;
     return;
   }
-  Geom g;
-  geom_forward(rot_l[gi], rot_r[gi], scale4[gi], g);
-  const float4 mean = mean4[gi];
-  const float op = opacity[gi];
+  float4 mean, sc4, qlr, qrr;
+  float op;
   float shc[NSH];
-  const float* shp = sh + (size_t)gi * NSH;
+  if constexpr (CP) {
+    decode_compact<NSH>(cp, gi, mean, sc4, qlr, qrr, op, shc);
+  } else {
+    mean = mean4[gi];
+    sc4 = scale4[gi];
+    qlr = rot_l[gi];
+    qrr = rot_r[gi];
+    op = opacity[gi];
+    const float* shp = sh + (size_t)gi * NSH;
 #pragma unroll
-  for (int k = 0; k < NSH; ++k) shc[k] = shp[k];
+    for (int k = 0; k < NSH; ++k) shc[k] = shp[k];
+  }
+  Geom g;
+  geom_forward(qlr, qrr, sc4, g);
   for (int v = 0; v < n_views; ++v) {
     const DView& V = views[v];
     const size_t slot = (size_t)v * n + gi;
@@ -138,12 +148,60 @@ template <int DS, int DT>
 void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S, float* rec,
                 uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
   const int blocks = (gp.n + 255) / 256;
-  hipLaunchKernelGGL((k_preprocess<DS, DT>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
-                     reinterpret_cast<const float4*>(gp.mean4),
-                     reinterpret_cast<const float4*>(gp.scale4),
-                     reinterpret_cast<const float4*>(gp.rot_l),
-                     reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S, rec,
-                     tiles, dkey, gp.mask, gp.mask_thr);
+  if (gp.compact)
+    hipLaunchKernelGGL((k_preprocess<DS, DT, true>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, views, S, rec, tiles,
+                       dkey, nullptr, 0.f, *gp.compact);
+  else
+    hipLaunchKernelGGL((k_preprocess<DS, DT, false>), dim3(blocks), dim3(256), 0, st, gp.n,
+                       n_views, reinterpret_cast<const float4*>(gp.mean4),
+                       reinterpret_cast<const float4*>(gp.scale4),
+                       reinterpret_cast<const float4*>(gp.rot_l),
+                       reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
+                       rec, tiles, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
+}
+
+template <int DS, int DT>
+__global__ __launch_bounds__(256) void k_decode_compact(int n, CompactPtrs cp,
+                                                        float4* __restrict__ mean4,
+                                                        float4* __restrict__ scale4,
+                                                        float4* __restrict__ rot_l,
+                                                        float4* __restrict__ rot_r,
+                                                        float* __restrict__ opacity,
+                                                        float* __restrict__ sh) {
+  constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= n) return;
+  float4 m, s4, a, b;
+  float op, shc[NSH];
+  decode_compact<NSH>(cp, gi, m, s4, a, b, op, shc);
+  mean4[gi] = m;
+  scale4[gi] = s4;
+  rot_l[gi] = a;
+  rot_r[gi] = b;
+  opacity[gi] = op;
+  float* o = sh + (size_t)gi * NSH;
+#pragma unroll
+  for (int k = 0; k < NSH; ++k) o[k] = shc[k];
+}
+
+template <int DS, int DT>
+void launch_decode(int n, const CompactPtrs& cp, float* mean4, float* scale4, float* rot_l,
+                   float* rot_r, float* opacity, float* sh, hipStream_t st) {
+  hipLaunchKernelGGL((k_decode_compact<DS, DT>), dim3((n + 255) / 256), dim3(256), 0, st, n, cp,
+                     reinterpret_cast<float4*>(mean4), reinterpret_cast<float4*>(scale4),
+                     reinterpret_cast<float4*>(rot_l), reinterpret_cast<float4*>(rot_r), opacity,
+                     sh);
+}
+
+template <int DS>
+void dispatch_decode_t(int n, int dt, const CompactPtrs& cp, float* mean4, float* scale4,
+                       float* rot_l, float* rot_r, float* opacity, float* sh, hipStream_t st) {
+  switch (dt) {
+    case 0: launch_decode<DS, 0>(n, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+    case 1: launch_decode<DS, 1>(n, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+    default: launch_decode<DS, 2>(n, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+  }
 }
 
 template <int DS, int DT>
@@ -189,6 +247,18 @@ void preprocess_forward(const GaussPtrs& gp, const DView* views, int n_views, DS
     case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, dkey, st); break;
     case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, dkey, st); break;
     default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+  }
+}
+
+void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
+                           float* mean4, float* scale4, float* rot_l, float* rot_r,
+                           float* opacity, float* sh, hipStream_t st) {
+  if (n <= 0) return;
+  switch (sh_degree) {
+    case 0: dispatch_decode_t<0>(n, t_degree, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+    case 1: dispatch_decode_t<1>(n, t_degree, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+    case 2: dispatch_decode_t<2>(n, t_degree, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
+    default: dispatch_decode_t<3>(n, t_degree, cp, mean4, scale4, rot_l, rot_r, opacity, sh, st); break;
   }
 }
 

@@ -149,6 +149,47 @@ class Renderer:
             C.byref(gr), None if dc is None else dc.data_ptr(), _stream_handle(self.device)),
             self._ctx)
 
+    # -- compact models ------------------------------------------------------------------
+    _COMPACT_ARRAYS = ("mean4_h", "scale_idx", "rot_l_idx", "rot_r_idx", "opacity_q", "dc_idx",
+                       "rest_idx", "scale_cb", "rot_cb", "dc_cb", "rest_cb")
+
+    def compact(self, c: Dict) -> B.g4d_compact:
+        """ABI view of a compact model: a dict with n, sh_degree, t_degree, op_lo, op_hi and
+        the device tensors mean4_h (int16 bit patterns of halves) [N, 4], uint8 index arrays
+        [N, 6] / [N, 8] and float32 codebooks (see include/g4d.h)."""
+        for k in self._COMPACT_ARRAYS:
+            t = c[k]
+            if t.device != self.device or not t.is_contiguous():
+                raise ValueError(f"{k} must be a contiguous tensor on {self.device}")
+        p = {k: c[k].data_ptr() for k in self._COMPACT_ARRAYS}
+        return B.g4d_compact(int(c["n"]), int(c["sh_degree"]), int(c["t_degree"]), p["mean4_h"],
+                             p["scale_idx"], p["rot_l_idx"], p["rot_r_idx"], p["opacity_q"],
+                             p["dc_idx"], p["rest_idx"], float(c["op_lo"]), float(c["op_hi"]),
+                             p["scale_cb"], p["rot_cb"], p["dc_cb"], p["rest_cb"])
+
+    def decode_compact(self, c: Dict) -> Dict[str, torch.Tensor]:
+        """Full float32 parameters of a compact model, on the device."""
+        n, ds, dt = int(c["n"]), int(c["sh_degree"]), int(c["t_degree"])
+        out = {"mean4": torch.empty((n, 4), device=self.device),
+               "scale4": torch.empty((n, 4), device=self.device),
+               "rot_l": torch.empty((n, 4), device=self.device),
+               "rot_r": torch.empty((n, 4), device=self.device),
+               "opacity": torch.empty(n, device=self.device),
+               "sh": torch.empty((n, dt + 1, (ds + 1) ** 2, 3), device=self.device)}
+        cc = self.compact(c)
+        B.check(B.lib().g4d_decode_compact(self._ctx, C.byref(cc),
+                                           *[out[k].data_ptr() for k in PARAM_NAMES],
+                                           _stream_handle(self.device)), self._ctx)
+        return out
+
+    def forward_compact(self, c: Dict, views, settings: B.g4d_settings, out_rgb: torch.Tensor,
+                        out_T: Optional[torch.Tensor]) -> None:
+        va = views if isinstance(views, C.Array) else B.make_views(views)
+        cc = self.compact(c)
+        B.check(B.lib().g4d_render_compact_forward(
+            self._ctx, C.byref(cc), va, len(va), C.byref(settings), out_rgb.data_ptr(),
+            None if out_T is None else out_T.data_ptr(), _stream_handle(self.device)), self._ctx)
+
     def step(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
              out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
              grads: Dict[str, torch.Tensor], graph: bool = True) -> None:
