@@ -106,8 +106,8 @@ struct RasterArgs {
 // ray, and the adjoint d_cube += bilinear transpose of T_final * dL/dI.
 void sky_forward(const DView* views, int n_views, int max_pixels, const float* cube, int R,
                  float* bg, hipStream_t st);
-void sky_backward(const DView* views, int n_views, int max_pixels, int R, const float* px_T,
-                  const float* dL, float* d_cube, hipStream_t st);
+void sky_backward(const DView* views, int n_views, int max_width, int max_height, int R,
+                  const float* px_T, const float* dL, float* d_cube, hipStream_t st);
 
 // Extra-channel helpers (k_channels.hip).
 void feature_normalize(int n, int d, const float* f, const float* gate, float* fn, float* fnorm,

@@ -691,8 +691,13 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
     // the sky gradient depends on the pixels only (it is there even without Gaussians)
     const int R = sky->resolution;
     fill_u32(reinterpret_cast<uint32_t*>(d_cube), (int64_t)6 * R * R * 3, 0u, st);
-    sky_backward(P<DView>(ctx->views), n_views, max_view_pixels(views, n_views), R,
-                 P<float>(ctx->px_T), dL_drgb, d_cube, st);
+    int mw = 0, mh = 0;
+    for (int v = 0; v < n_views; ++v) {
+      mw = std::max(mw, views[v].width);
+      mh = std::max(mh, views[v].height);
+    }
+    sky_backward(P<DView>(ctx->views), n_views, mw, mh, R, P<float>(ctx->px_T), dL_drgb, d_cube,
+                 st);
   }
   if (slots == 0) return G4D_OK;
   g4d_settings s_run = *s;

@@ -7,7 +7,7 @@
 // Cube-map convention (OpenGL): faces +x, -x, +y, -y, +z, -z picked by the largest |component|
 // of r (ties to x, then y); face coordinates s = (sc / |ma| + 1) / 2, t = (tc / |ma| + 1) / 2;
 // texel (i, j) centred at ((i + 1/2) / R, (j + 1/2) / R); bilinear within the face, clamped at
-// its edges.  One thread per pixel of every view (grid y = view).
+// its edges.  Grid y = view; the lookup takes one thread per pixel.
 #include <hip/hip_runtime.h>
 
 #include "g4d_internal.h"
@@ -86,10 +86,18 @@ __global__ __launch_bounds__(256) void k_sky(const DView* __restrict__ views,
   }
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
+// Adjoint: each thread walks a kPatchX x kPatchY patch of pixels row by row, keeps the 12
+// partial sums (4 texels x 3 channels) of the current bilinear footprint and adds them to the
+// cube-map gradient only when the footprint changes (neighbouring pixels mostly share one,
+// texels being larger than pixels), which divides the atomics by the pixels per footprint.
+constexpr int kPatchX = 8, kPatchY = 4;
+
+__device__ __forceinline__ void flush(float* d_cube, const int* idx, const float acc[4][3]) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (acc[k][c] != 0.f) atomicAdd(d_cube + idx[k] + c, acc[k][c]);
 }
 
 __global__ __launch_bounds__(256) void k_sky_backward(const DView* __restrict__ views, int R,
@@ -98,37 +106,43 @@ __global__ __launch_bounds__(256) void k_sky_backward(const DView* __restrict__ 
                                                       float* __restrict__ d_cube) {
   const DView& V = views[blockIdx.y];
   const int64_t hw = (int64_t)V.width * V.height;
-  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = pix < hw;
-  const int px = valid ? (int)(pix % V.width) : 0, py = valid ? (int)(pix / V.width) : 0;
-  const CubeTap t = cube_tap(V, px, py, R);
-  float g[3] = {0.f, 0.f, 0.f};
-  if (valid) {
-    const float T = px_T[V.pix_base + pix];
-    const float* d = dL + 3 * (int64_t)V.pix_base + pix;
+  const int px_per_row = (V.width + kPatchX - 1) / kPatchX;
+  const int64_t patch = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t patches = (int64_t)px_per_row * ((V.height + kPatchY - 1) / kPatchY);
+  if (patch >= patches) return;
+  const int x0 = (int)(patch % px_per_row) * kPatchX, y0 = (int)(patch / px_per_row) * kPatchY;
+  int cur = -1;
+  int idx[4] = {0, 0, 0, 0};
+  float acc[4][3] = {};
+  for (int dy = 0; dy < kPatchY; ++dy) {
+    const int py = y0 + dy;
+    if (py >= V.height) break;
+    for (int dx = 0; dx < kPatchX; ++dx) {
+      const int px = x0 + dx;
+      if (px >= V.width) break;
+      const int64_t pix = (int64_t)py * V.width + px;
+      const CubeTap t = cube_tap(V, px, py, R);
+      if (t.base != cur) {
+        if (cur >= 0) flush(d_cube, idx, acc);
+        cur = t.base;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g[c] = T * d[c * hw];
-  }
-  // Neighbouring pixels usually share one footprint: then the wave adds its 12 partial sums
-  // once; otherwise every lane adds its own.
-  const int base0 = __builtin_amdgcn_readfirstlane(t.base);
-  const bool same = __ballot(valid && t.base != base0) == 0ull;
-  if (same) {
-    const int lane = threadIdx.x & 63;
+        for (int k = 0; k < 4; ++k) {
+          idx[k] = t.idx[k];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+          for (int c = 0; c < 3; ++c) acc[k][c] = 0.f;
+        }
+      }
+      const float T = px_T[V.pix_base + pix];
+      const float* d = dL + 3 * (int64_t)V.pix_base + pix;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float s = wave_sum(t.w[k] * g[c]);
-        if (lane == 0 && s != 0.f) atomicAdd(d_cube + t.idx[k] + c, s);
+        const float g = T * d[c * hw];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k][c] = fmaf(t.w[k], g, acc[k][c]);
       }
-  } else if (valid) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        if (t.w[k] * g[c] != 0.f) atomicAdd(d_cube + t.idx[k] + c, t.w[k] * g[c]);
+    }
   }
+  if (cur >= 0) flush(d_cube, idx, acc);
 }
 
 }  // namespace
@@ -140,12 +154,13 @@ void sky_forward(const DView* views, int n_views, int max_pixels, const float* c
                      dim3(256), 0, st, views, cube, R, bg);
 }
 
-void sky_backward(const DView* views, int n_views, int max_pixels, int R, const float* px_T,
-                  const float* dL, float* d_cube, hipStream_t st) {
-  if (n_views <= 0 || max_pixels <= 0) return;
-  hipLaunchKernelGGL(k_sky_backward,
-                     dim3((unsigned)((max_pixels + 255) / 256), (unsigned)n_views), dim3(256), 0,
-                     st, views, R, px_T, dL, d_cube);
+void sky_backward(const DView* views, int n_views, int max_width, int max_height, int R,
+                  const float* px_T, const float* dL, float* d_cube, hipStream_t st) {
+  if (n_views <= 0 || max_width <= 0 || max_height <= 0) return;
+  const int64_t patches = (int64_t)((max_width + kPatchX - 1) / kPatchX) *
+                          ((max_height + kPatchY - 1) / kPatchY);
+  hipLaunchKernelGGL(k_sky_backward, dim3((unsigned)((patches + 255) / 256), (unsigned)n_views),
+                     dim3(256), 0, st, views, R, px_T, dL, d_cube);
 }
 
 }  // namespace g4d
