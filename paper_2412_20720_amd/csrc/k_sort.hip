@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
   __shared__ int32_t s_x0[4][64], s_x1[4][64], s_y0[4][64], s_tx[4][64], s_tb[4][64];
   __shared__ int32_t s_w[4][64], s_h[4][64];
   __shared__ uint32_t s_slot[4][64];
+  __shared__ uint32_t s_start[4][64], s_key0[4][64], s_val[4][64];  // runs of one round
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n_vis = *n_vis_dev;
   const int64_t first = ((int64_t)blockIdx.x * 4 + w) * 64;
@@ -360,20 +361,32 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
       }
     }
     uint32_t total;
-    const uint32_t pos = cursor + wave_excl_scan(cnt, total);
-    if (cnt > 0) {
-      const uint32_t key0 = (uint32_t)(s_tb[w][i] + ty * s_tx[w][i] + c0);
-      const uint32_t slot = s_slot[w][i];
-      for (uint32_t m = 0; m < cnt; ++m) {
-        const uint32_t dst = pos + m;
-        if (dst < off_end && (int64_t)dst < pair_cap) {
-          pkey[dst] = key0 + m;
-          pval[dst] = slot;
-        } else {
-          *overflow = 1u;
-        }
+    const uint32_t start = wave_excl_scan(cnt, total);
+    // Publish the runs, then write the round's pairs with consecutive lanes on consecutive
+    // addresses: pair e belongs to the last run starting at or before e.
+    s_start[w][lane] = start;
+    s_key0[w][lane] = (uint32_t)(s_tb[w][i] + ty * s_tx[w][i] + c0);
+    s_val[w][lane] = s_slot[w][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t e = lane; e < total; e += 64) {
+      int lo = 0, hi = 63;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[w][mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t dst = cursor + e;
+      if (dst < off_end && (int64_t)dst < pair_cap) {
+        pkey[dst] = s_key0[w][lo] + (e - s_start[w][lo]);
+        pval[dst] = s_val[w][lo];
+      } else {
+        *overflow = 1u;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     cursor += total;
   }
   // The preprocess counted exactly these pairs.  Should the two ever disagree, the shortfall
@@ -389,15 +402,34 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
   }
 }
 
+// Tile boundaries in the sorted keys, four keys per thread (one 16-byte load; the neighbours
+// on either side come from the caches).
 __global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev, int64_t cap,
                          int64_t n_tiles, uint2* ranges) {
   const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t k = key[i];
-  if ((int64_t)k >= n_tiles) return;  // dummy tile
-  if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
-  if (i == n - 1 || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (i0 >= n) return;
+  uint32_t k[6];  // key[i0 - 1 .. i0 + 4]
+  if (i0 + 4 <= n) {
+    const uint4 q = *reinterpret_cast<const uint4*>(key + i0);
+    k[1] = q.x;
+    k[2] = q.y;
+    k[3] = q.z;
+    k[4] = q.w;
+  } else {
+    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? key[i0 + j] : 0u;
+  }
+  k[0] = i0 > 0 ? key[i0 - 1] : 0u;
+  k[5] = i0 + 4 < n ? key[i0 + 4] : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = i0 + j;
+    if (i >= n) break;
+    const uint32_t kk = k[1 + j];
+    if ((int64_t)kk >= n_tiles) continue;  // dummy tile
+    if (i == 0 || k[j] != kk) ranges[kk].x = (uint32_t)i;
+    if (i == n - 1 || k[2 + j] != kk) ranges[kk].y = (uint32_t)(i + 1);
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
@@ -487,7 +519,7 @@ void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const 
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
                  uint2* ranges, hipStream_t st) {
   fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
-  const int64_t blocks = (pair_cap + 255) / 256;
+  const int64_t blocks = (pair_cap + 1023) / 1024;  // four keys per thread
   if (blocks == 0) return;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs, pair_cap,
                      n_tiles, ranges);
