@@ -195,9 +195,9 @@ typedef struct {
 
 /* g4d_render_forward plus the extra channels of *ch:
  *   out_ch: per view planar [E][H][W], views concatenated in order (caller-owned device memory).
- * Rasterization uses one pixel per lane and 64-entry LDS batches whatever s->px_per_lane and
- * s->lds_batch say (tile_size is honored); out_rgb and out_T are bit-identical to
- * g4d_render_forward's.  Saves the state g4d_render_channels_backward needs. */
+ * Rasterization uses 64-entry LDS batches whatever s->lds_batch says and two pixels per lane
+ * (one if s->px_per_lane is 1 or tile_size is 8); tile_size is honored.  out_rgb and out_T are
+ * bit-identical to g4d_render_forward's.  Saves the state g4d_render_channels_backward needs. */
 g4d_status g4d_render_channels_forward(g4d_ctx *ctx, const g4d_gaussians *g,
                                        const g4d_view *views, int32_t n_views,
                                        const g4d_settings *s, const g4d_channels *ch,

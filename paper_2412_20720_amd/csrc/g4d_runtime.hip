@@ -246,6 +246,19 @@ bool same_channels(const g4d_channels& a, const g4d_channels& b) {
          (!a.flow || std::memcmp(&a.flow_dt, &b.flow_dt, sizeof(float)) == 0);
 }
 
+// Settings the raster runs with.  The extra-channel raster takes 64-entry LDS batches and at
+// most two pixels per lane: its per-pixel channel registers leave one wave per SIMD at four
+// (measured slower on the 300k/16-view workload with 35 channels: 31.8 against 26.7 ms per
+// forward + backward step at two, 33.5 at one).
+g4d_settings run_settings(const g4d_settings* s, const g4d_channels* ch) {
+  g4d_settings r = *s;
+  if (ch) {
+    r.lds_batch = 64;
+    r.px_per_lane = r.tile_size == 8 ? 1 : (r.px_per_lane == 1 ? 1 : 2);
+  }
+  return r;
+}
+
 DSettings device_settings(const g4d_settings* s) {
   DSettings d{};
   d.near_z = s->near_z;
@@ -491,12 +504,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   ctx->saved = false;
   if ((r = upload_views(ctx, views, n_views, s, st)) != G4D_OK) return r;
   const int64_t slots = (int64_t)g->n * n_views;
-  // the extra-channel raster runs one pixel per lane with 64-entry batches
-  g4d_settings s_run = *s;
-  if (ch) {
-    s_run.px_per_lane = 1;
-    s_run.lds_batch = 64;
-  }
+  const g4d_settings s_run = run_settings(s, ch);
   const DSettings DS = device_settings(&s_run);
   const int n_ext = n_ext_of(ch);
   if ((r = ensure(ctx, ctx->counters, 4 * sizeof(uint32_t))) != G4D_OK) return r;
@@ -700,11 +708,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
                  st);
   }
   if (slots == 0) return G4D_OK;
-  g4d_settings s_run = *s;
-  if (ch) {
-    s_run.px_per_lane = 1;
-    s_run.lds_batch = 64;
-  }
+  const g4d_settings s_run = run_settings(s, ch);
   const DSettings DS = device_settings(&s_run);
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
   {

@@ -1,13 +1,17 @@
 // Per-Gaussian work of the extra render channels (Sec. 7 feature rendering, Sec. 5
 // rendered depth, Sec. 8.1 rendered flow); their compositing lives in the raster kernels.
 //
-//   feature_normalize: f_hat = s / |s| with s = gate * f (0 when s = 0), one thread per Gaussian.
+//   feature_normalize: f_hat = s / |s| with s = gate * f (0 when s = 0).
 //   flow_forward:      per visible (view, Gaussian) slot, the image displacement of the
 //                      conditional mean between t and t + dt.  The mean moves linearly in t,
 //                      mu(t') = mu(t) + Sigma_{1:3,4} / Sigma_44 (t' - t), so one slice suffices.
 //   feature_backward:  dL/ds = (dL/df_hat - f_hat (f_hat . dL/df_hat)) / |s|,
-//                      dL/df = gate * dL/ds, dL/dgate = sum_i f_i * dL/ds_i (wave sums, then
-//                      one atomic per channel and wave).
+//                      dL/df = gate * dL/ds, dL/dgate = sum_i f_i * dL/ds_i (per-lane sums
+//                      over the rows a wave visits, then one atomic per channel and wave).
+//
+// The two feature kernels map a row of D features to DP = (next power of two >= D) adjacent
+// lanes, 64 / DP rows per wave step, so that each load and store of the [N, D] arrays is one
+// contiguous run; the row's dot products are sums over its DP lanes.
 #include <hip/hip_runtime.h>
 
 #include "g4d_internal.h"
@@ -15,24 +19,34 @@
 namespace g4d {
 namespace {
 
+// Sum over the DP-lane group of the lane (DP a power of two, at most 64).
+template <int DP>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int o = DP / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <int DP>
 __global__ __launch_bounds__(256) void k_feature_normalize(int n, int d,
                                                            const float* __restrict__ f,
                                                            const float* __restrict__ gate,
                                                            float* __restrict__ fn,
                                                            float* __restrict__ fnorm) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float* fi = f + (size_t)i * d;
-  float n2 = 0.f;
-  for (int c = 0; c < d; ++c) {
-    const float s = (gate ? gate[c] : 1.f) * fi[c];
-    n2 = fmaf(s, s, n2);
+  constexpr int kRows = 64 / DP;
+  const int lane = threadIdx.x & 63, c = lane % DP, sub = lane / DP;
+  const float gc = c < d ? (gate ? gate[c] : 1.f) : 0.f;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t stride = ((int64_t)gridDim.x * blockDim.x >> 6) * kRows;
+  for (int64_t r0 = wave * kRows; r0 < n; r0 += stride) {
+    const int64_t i = r0 + sub;
+    const bool ok = i < n && c < d;
+    const float s = ok ? gc * f[i * d + c] : 0.f;
+    const float nrm = sqrtf(group_sum<DP>(s * s));
+    const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
+    if (ok) fn[i * d + c] = s * inv;
+    if (i < n && c == 0) fnorm[i] = nrm;
   }
-  const float nrm = sqrtf(n2);
-  const float inv = nrm > 0.f ? 1.f / nrm : 0.f;
-  float* o = fn + (size_t)i * d;
-  for (int c = 0; c < d; ++c) o[c] = (gate ? gate[c] : 1.f) * fi[c] * inv;
-  fnorm[i] = nrm;
 }
 
 __global__ __launch_bounds__(256) void k_flow(int n, int n_views, const float4* __restrict__ mean4,
@@ -81,43 +95,79 @@ __global__ __launch_bounds__(256) void k_flow(int n, int n_views, const float4* 
   }
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
-
+template <int DP>
 __global__ __launch_bounds__(256) void k_feature_backward(
     int n, int d, const float* __restrict__ f, const float* __restrict__ gate,
     const float* __restrict__ fn, const float* __restrict__ fnorm,
     const float* __restrict__ dfn, float* __restrict__ d_features, float* __restrict__ d_gate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
-  const float nrm = valid ? fnorm[i] : 0.f;
-  const bool live = valid && nrm > 0.f;
-  const size_t row = live ? (size_t)i * d : 0;
-  float dot = 0.f;
-  for (int c = 0; c < d; ++c)
-    if (live) dot = fmaf(fn[row + c], dfn[row + c], dot);
-  const float inv = live ? 1.f / nrm : 0.f;
-  // every lane stays in the loop (the wave sums below need all 64)
-  for (int c = 0; c < d; ++c) {
-    const float ds = live ? (dfn[row + c] - fn[row + c] * dot) * inv : 0.f;
-    if (valid) d_features[(size_t)i * d + c] = (gate ? gate[c] : 1.f) * ds;
-    if (d_gate) {
-      const float part = wave_sum(live ? f[(size_t)i * d + c] * ds : 0.f);
-      if ((threadIdx.x & 63) == 0 && part != 0.f) atomicAdd(d_gate + c, part);
-    }
+  constexpr int kRows = 64 / DP;
+  const int lane = threadIdx.x & 63, c = lane % DP, sub = lane / DP;
+  const float gc = c < d ? (gate ? gate[c] : 1.f) : 0.f;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t stride = ((int64_t)gridDim.x * blockDim.x >> 6) * kRows;
+  float gacc = 0.f;  // this lane's part of dL/dgate[c]
+  for (int64_t r0 = wave * kRows; r0 < n; r0 += stride) {
+    const int64_t i = r0 + sub;
+    const bool ok = i < n && c < d;
+    const float nrm = ok ? fnorm[i] : 0.f;
+    const bool live = ok && nrm > 0.f;
+    const float fh = live ? fn[i * d + c] : 0.f, dh = live ? dfn[i * d + c] : 0.f;
+    const float dot = group_sum<DP>(fh * dh);
+    const float ds = live ? (dh - fh * dot) * (1.f / nrm) : 0.f;
+    if (ok) d_features[i * d + c] = gc * ds;
+    if (d_gate && live) gacc = fmaf(f[i * d + c], ds, gacc);
   }
+  if (d_gate) {
+#pragma unroll
+    for (int o = 32; o >= DP; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
+    if (sub == 0 && c < d && gacc != 0.f) atomicAdd(d_gate + c, gacc);
+  }
+}
+
+// Lanes per feature row for D features.
+int row_lanes(int d) {
+  int dp = 1;
+  while (dp < d) dp <<= 1;
+  return dp;
+}
+
+// Waves for `rows` rows at 64 / DP rows per wave step, capped so that each wave visits several
+// rows (fewer dL/dgate atomics).
+unsigned feature_blocks(int64_t rows, int dp) {
+  const int64_t waves = (rows * dp + 63) / 64;
+  const int64_t blocks = (waves + 3) / 4;
+  return (unsigned)(blocks < 1024 ? blocks : 1024);
+}
+
+template <int DP>
+void launch_feature_normalize(int n, int d, const float* f, const float* gate, float* fn,
+                              float* fnorm, hipStream_t st) {
+  hipLaunchKernelGGL(k_feature_normalize<DP>, dim3(feature_blocks(n, DP)), dim3(256), 0, st, n, d,
+                     f, gate, fn, fnorm);
+}
+
+template <int DP>
+void launch_feature_backward(int n, int d, const float* f, const float* gate, const float* fn,
+                             const float* fnorm, const float* dfn, float* d_features,
+                             float* d_gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_feature_backward<DP>, dim3(feature_blocks(n, DP)), dim3(256), 0, st, n, d,
+                     f, gate, fn, fnorm, dfn, d_features, d_gate);
 }
 
 }  // namespace
 
 void feature_normalize(int n, int d, const float* f, const float* gate, float* fn, float* fnorm,
                        hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_feature_normalize, dim3((n + 255) / 256), dim3(256), 0, st, n, d, f, gate,
-                     fn, fnorm);
+  if (n <= 0 || d <= 0) return;
+  switch (row_lanes(d)) {
+    case 1: launch_feature_normalize<1>(n, d, f, gate, fn, fnorm, st); break;
+    case 2: launch_feature_normalize<2>(n, d, f, gate, fn, fnorm, st); break;
+    case 4: launch_feature_normalize<4>(n, d, f, gate, fn, fnorm, st); break;
+    case 8: launch_feature_normalize<8>(n, d, f, gate, fn, fnorm, st); break;
+    case 16: launch_feature_normalize<16>(n, d, f, gate, fn, fnorm, st); break;
+    case 32: launch_feature_normalize<32>(n, d, f, gate, fn, fnorm, st); break;
+    default: launch_feature_normalize<64>(n, d, f, gate, fn, fnorm, st); break;
+  }
 }
 
 void flow_forward(const GaussPtrs& g, const DView* views, int n_views, const uint32_t* tiles,
@@ -135,8 +185,17 @@ void feature_backward(int n, int d, const float* f, const float* gate, const flo
                       const float* fnorm, const float* dfn, float* d_features, float* d_gate,
                       hipStream_t st) {
   if (n <= 0 || d <= 0) return;
-  hipLaunchKernelGGL(k_feature_backward, dim3((n + 255) / 256), dim3(256), 0, st, n, d, f, gate,
-                     fn, fnorm, dfn, d_features, d_gate);
+#define G4D_FB(DP) launch_feature_backward<DP>(n, d, f, gate, fn, fnorm, dfn, d_features, d_gate, st)
+  switch (row_lanes(d)) {
+    case 1: G4D_FB(1); break;
+    case 2: G4D_FB(2); break;
+    case 4: G4D_FB(4); break;
+    case 8: G4D_FB(8); break;
+    case 16: G4D_FB(16); break;
+    case 32: G4D_FB(32); break;
+    default: G4D_FB(64); break;
+  }
+#undef G4D_FB
 }
 
 }  // namespace g4d

@@ -21,12 +21,16 @@
 // per-Gaussian values are then summed over the wave by a permlane-swap transpose-reduce and
 // one vector atomic (nine lanes) adds them to the (view, Gaussian) gradient slot.
 //
-// Extra channels (CX > 0, one pixel per lane): each staged entry also carries CX payload values
-// (normalized features, camera depth, flow; zero padding) in a second wave-private LDS array;
-// they are composited with the same weights, add g_x . payload to g . c in the backward, and
-// their per-entry partials are reduced like the nine above and added to the feature and depth
-// gradients.
+// Extra channels (CX > 0): each staged entry also carries CX payload values (normalized
+// features, camera depth, flow; zero padding) in a second wave-private LDS array; they are
+// composited with the same weights, add g_x . payload to g . c in the backward, and their
+// per-entry partials are reduced like the nine above and added to the feature and depth
+// gradients.  All pixels of a lane are evaluated together, so each payload value read from
+// LDS serves every pixel of the lane.
 #include <hip/hip_runtime.h>
+
+#include <climits>
+#include <type_traits>
 
 #include "g4d_internal.h"
 
@@ -35,6 +39,13 @@ namespace {
 
 constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
 constexpr float kInvNegHalfLog2e = -1.38629436111989061f;  // 1 / kNegHalfLog2e = -2 ln 2
+
+// alpha = min(alpha_max, opacity p_t G) with G = exp(-d2 / 2) <= 1, so an entry whose
+// opacity p_t lies below alpha_max cannot be clamped at any pixel.  A staged batch made only of
+// such entries runs a copy of the entry loop without the clamp; the margin 2^-12 covers the
+// rounding of d2 near 0 (where the computed G may exceed 1 by an ulp or two), so both copies
+// give bit-identical results.
+constexpr float kNoClampScale = 1.f - 1.f / 4096.f;
 
 // A lane's pixels are tested against an entry in groups of kSlotGroup: the group is skipped
 // when none of its pixels in the whole wave is covered; otherwise all of them are evaluated
@@ -83,6 +94,12 @@ __device__ __forceinline__ float dpp(float x) {
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
   return x;
 }
 
@@ -148,11 +165,14 @@ __device__ __forceinline__ bool fetch_entry(const RasterArgs& a, const WaveTile&
 }
 
 // Stage up to BATCH list entries starting at `base` (fetch rounds of 64 lanes) into `st`,
-// keeping only those that can reach the wave's block; returns how many were kept.
+// keeping only those that can reach the wave's block; returns how many were kept, and in
+// `clamp_free` whether none of them can reach alpha_max.
 template <int BATCH>
 __device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& t, int base,
-                                           int end, Staged* st) {
+                                           int end, Staged* st, bool& clamp_free) {
   int n = 0;
+  clamp_free = true;
+  const float no_clamp = a.S.alpha_max * kNoClampScale;
 #pragma unroll
   for (int r = 0; r < (BATCH + 63) / 64; ++r) {
     const int j = base + r * 64 + t.lane;
@@ -160,6 +180,7 @@ __device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& 
     Staged s;
     const bool keep = fetch_entry(a, t, (uint32_t)j, in, s);
     const uint64_t mask = __ballot(keep);
+    clamp_free = clamp_free && __ballot(keep && !(s.b.y < no_clamp)) == 0ull;
     if (keep) {
       const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -171,25 +192,40 @@ __device__ __forceinline__ int stage_batch(const RasterArgs& a, const WaveTile& 
 }
 
 // Copy the CX payload values of the n staged entries into xp[k * CX + c] (all lanes; the
-// caller synchronizes the wave before and after).
+// caller synchronizes the wave before and after).  Loads go out in rounds of kPayloadChunk per
+// lane before any of them is stored, so their latencies overlap.
+constexpr int kPayloadChunk = 12;
+
 template <int CX>
 __device__ __forceinline__ void stage_payload(const RasterArgs& a, const WaveTile& t,
                                               const Staged* st, int n, float* xp) {
   const size_t vbase = (size_t)t.v * (size_t)a.n_gauss;
-  for (int idx = t.lane; idx < n * CX; idx += 64) {
-    const int k = idx / CX, c = idx - k * CX;
-    const size_t slot = __float_as_uint(st[k].c.z);
-    float val = 0.f;
-    if (c < a.n_feat) {
-      val = a.fn[(slot - vbase) * (size_t)a.n_feat + c];
-    } else if (c < a.n_ext) {
-      const int e = c - a.n_feat;
-      if (a.has_depth && e == 0)
-        val = a.rec[slot * kRec + 11];
-      else
-        val = a.flow[slot * 2 + (e - a.has_depth)];
+  const int total = n * CX;
+  for (int base = 0; base < total; base += 64 * kPayloadChunk) {
+    float val[kPayloadChunk];
+#pragma unroll
+    for (int r = 0; r < kPayloadChunk; ++r) {
+      const int idx = base + 64 * r + t.lane;
+      const int k = idx / CX, c = idx - k * CX;
+      val[r] = 0.f;
+      if (idx < total) {
+        const size_t slot = __float_as_uint(st[k].c.z);
+        if (c < a.n_feat) {
+          val[r] = a.fn[(slot - vbase) * (size_t)a.n_feat + c];
+        } else if (c < a.n_ext) {
+          const int e = c - a.n_feat;
+          if (a.has_depth && e == 0)
+            val[r] = a.rec[slot * kRec + 11];
+          else
+            val[r] = a.flow[slot * 2 + (e - a.has_depth)];
+        }
+      }
     }
-    xp[idx] = val;
+#pragma unroll
+    for (int r = 0; r < kPayloadChunk; ++r) {
+      const int idx = base + 64 * r + t.lane;
+      if (idx < total) xp[idx] = val[r];
+    }
   }
 }
 
@@ -220,13 +256,16 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 template <int TILE, int BATCH, int PXX, int PXY, bool COUNT, int CX>
 __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
-  static_assert(CX == 0 || P == 1, "extra channels use one pixel per lane");
-  constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
+  // with extra channels a lane's pixels form one group (see the header)
+  constexpr int kGroup = CX > 0 ? P : (kSlotGroup < P ? kSlotGroup : P);
+  constexpr int XC = CX > 0 ? CX : 1;
   __shared__ Staged stage[4][BATCH];
   __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
-  float X[CX > 0 ? CX : 1];
+  float X[P][XC];
 #pragma unroll
-  for (int c = 0; c < (CX > 0 ? CX : 1); ++c) X[c] = 0.f;
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int c = 0; c < XC; ++c) X[p][c] = 0.f;
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
@@ -257,7 +296,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   float* xp = xstage[t.w];
   const int end = (int)t.range.y;
   for (int base = (int)t.range.x; base < end && !done; base += BATCH) {
-    const int n = stage_batch<BATCH>(a, t, base, end, st);
+    bool clamp_free;  // not used here: a second copy of the loop costs the forward occupancy
+    const int n = stage_batch<BATCH>(a, t, base, end, st, clamp_free);
     G4D_WAVE_SYNC();
     if constexpr (CX > 0) {
       stage_payload<CX>(a, t, st, n, xp);
@@ -267,6 +307,10 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
       const float4 e0 = st[k].a, e1 = st[k].b;
       const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
       bool any_stop = false;
+      bool any_take = false;
+      float wk[P];  // T alpha of this entry per pixel, 0 where it is not composited
+#pragma unroll
+      for (int p = 0; p < P; ++p) wk[p] = 0.f;
 #pragma unroll
       for (int g = 0; g < P; g += kGroup) {
         float pwg[kGroup];
@@ -295,11 +339,8 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           C0[p] = fmaf(wgt, e1.z, C0[p]);
           C1[p] = fmaf(wgt, e1.w, C1[p]);
           C2[p] = fmaf(wgt, e2.x, C2[p]);
-          if constexpr (CX > 0) {
-            const float* xk = xp + k * CX;
-#pragma unroll
-            for (int c = 0; c < CX; ++c) X[c] = fmaf(wgt, xk[c], X[c]);
-          }
+          wk[p] = wgt;
+          any_take |= take;
           T[p] = take ? Tn : T[p];
           last[p] = take ? __float_as_int(e2.y) : last[p];
           lo[p] = stop ? INFINITY : lo[p];
@@ -307,6 +348,17 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           if (COUNT) {
             evals[p] += in ? 1u : 0u;
             contrib[p] += take ? 1u : 0u;
+          }
+        }
+      }
+      if constexpr (CX > 0) {
+        if (__ballot(any_take) != 0ull) {
+          const float* xk = xp + k * CX;
+#pragma unroll
+          for (int c = 0; c < CX; ++c) {
+            const float x = xk[c];
+#pragma unroll
+            for (int p = 0; p < P; ++p) X[p][c] = fmaf(wk[p], x, X[p][c]);
           }
         }
       }
@@ -345,7 +397,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
       float* o = a.out_ch + (size_t)a.n_ext * (size_t)V.pix_base + pix;
 #pragma unroll
       for (int c = 0; c < CX; ++c)
-        if (c < a.n_ext) o[(size_t)c * hw] = X[c];
+        if (c < a.n_ext) o[(size_t)c * hw] = X[p][c];
     }
   }
 }
@@ -407,12 +459,12 @@ __device__ __forceinline__ void wave_reduce_rows(const float* q, float* r) {
 template <int TILE, int BATCH, int PXX, int PXY, int CX>
 __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
-  static_assert(CX == 0 || P == 1, "extra channels use one pixel per lane");
   static_assert(CX % 4 == 0, "extra channels come in groups of four");
-  constexpr int kGroup = kSlotGroup < P ? kSlotGroup : P;
+  constexpr int kGroup = CX > 0 ? P : (kSlotGroup < P ? kSlotGroup : P);
+  constexpr int XC = CX > 0 ? CX : 1;
   __shared__ Staged stage[4][BATCH];
   __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
-  float gx[CX > 0 ? CX : 1];  // upstream gradient of the extra channels (0: flow, padding)
+  float gx[P][XC];  // upstream gradient of the extra channels per pixel (0: flow, padding)
   WaveTile t;
   if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
@@ -425,7 +477,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   float rx[P], ry[P], rxx[P], rxy[P], ryy[P];
   const float ox = (float)t.bx + 4.f * PXX, oy = (float)t.by + 4.f * PXY;
   int last[P];
-  int lane_last = -1;
+  int lane_last = -1, lane_first = INT_MAX;
   const int64_t hw = (int64_t)V.width * V.height;
   const float* dl = a.dL + 3 * (int64_t)V.pix_base;
 #pragma unroll
@@ -456,7 +508,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
                                  : nullptr;
 #pragma unroll
       for (int c = 0; c < CX; ++c)
-        gx[c] = (dxp && L.inside[p] && c < n_grad) ? dxp[(size_t)c * hw] : 0.f;
+        gx[p][c] = (dxp && L.inside[p] && c < n_grad) ? dxp[(size_t)c * hw] : 0.f;
     }
     float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
     if (a.bg_px && L.inside[p]) {
@@ -467,27 +519,34 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
     }
     gR[p] = fmaf(g0[p], bg0, fmaf(g1[p], bg1, g2[p] * bg2));
     lane_last = max(lane_last, last[p]);
+    lane_first = min(lane_first, last[p]);
   }
   const int hi_last = wave_max(lane_last);
   if (hi_last < 0) return;
+  // entries at or before every pixel's last composited one need no per-pixel position test
+  const int lo_last = __builtin_amdgcn_readfirstlane(wave_min(lane_first));
   const float lo_cut = kNegHalfLog2e * S.cut2;
   Staged* st = stage[t.w];
   float* xp = xstage[t.w];
   const int lo_list = (int)t.range.x;
   for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
     const int lo = max(lo_list, hi - BATCH);
-    const int n = stage_batch<BATCH>(a, t, lo, hi, st);
+    bool clamp_free;
+    const int n = stage_batch<BATCH>(a, t, lo, hi, st, clamp_free);
     G4D_WAVE_SYNC();
     if constexpr (CX > 0) {
       stage_payload<CX>(a, t, st, n, xp);
       G4D_WAVE_SYNC();
     }
+    auto entries = [&](auto clamp_tag, auto check_tag) {
+      constexpr bool kClamp = decltype(clamp_tag)::value;
+      constexpr bool kCheckLast = decltype(check_tag)::value;
     for (int k = n - 1; k >= 0; --k) {
       const float4 e0 = st[k].a, e1 = st[k].b, e2 = st[k].c;
       const int jk = __float_as_int(e2.y);
-      float qx[CX > 0 ? CX : 1];
+      float qx[XC];
 #pragma unroll
-      for (int c = 0; c < (CX > 0 ? CX : 1); ++c) qx[c] = 0.f;
+      for (int c = 0; c < XC; ++c) qx[c] = 0.f;
       // Per pixel the lane adds sa = alpha dL/dalpha (unclamped branch only) into the moments
       // q[0..5] = sum sa [rx, ry, rx^2, rx ry, ry^2, 1] of the block-centred pixel position
       // and the color partials into q[6..8]; once per entry they are turned into the
@@ -504,10 +563,23 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           const int p = g + i;
           const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
           pwg[i] = mahalanobis(dx, dy, e0, e1.x);
-          ing[i] = jk <= last[p] && pwg[i] >= lo_cut;
+          ing[i] = (!kCheckLast || jk <= last[p]) && pwg[i] >= lo_cut;
           gin |= ing[i];
         }
         if (__ballot(gin) == 0ull) continue;
+        // g_x . payload per pixel, each payload value read once for the group
+        float gcx[kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) gcx[i] = 0.f;
+        if constexpr (CX > 0) {
+          const float* xk = xp + k * CX;
+#pragma unroll
+          for (int c = 0; c < CX; ++c) {
+            const float x = xk[c];
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) gcx[i] = fmaf(gx[g + i][c], x, gcx[i]);
+          }
+        }
 #pragma unroll
         for (int i = 0; i < kGroup; ++i) {
           const int p = g + i;
@@ -515,7 +587,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           const bool in = ing[i];
           const float G = fast_exp2(pw);
           const float araw = e1.y * G;
-          const float ac = fminf(S.alpha_max, araw);
+          const float ac = kClamp ? fminf(S.alpha_max, araw) : araw;
           const bool take = in && ac >= S.alpha_min;
           // alpha = 0 for an entry the pixel did not composite: then T, gR, q[5..8] and the
           // moments below are left exactly as they were, without selects
@@ -529,19 +601,14 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           q[8] = fmaf(g2[p], wgt, q[8]);
           float gc = fmaf(g0[p], e1.z, fmaf(g1[p], e1.w, g2[p] * e2.x));
           if constexpr (CX > 0) {
-            const float* xk = xp + k * CX;
-            float gcx = 0.f;
 #pragma unroll
-            for (int c = 0; c < CX; ++c) {
-              gcx = fmaf(gx[c], xk[c], gcx);
-              qx[c] = fmaf(gx[c], wgt, qx[c]);
-            }
-            gc += gcx;
+            for (int c = 0; c < CX; ++c) qx[c] = fmaf(gx[p][c], wgt, qx[c]);
+            gc += gcx[i];
           }
           const float diff = gc - gR[p];
           gR[p] = fmaf(alpha, diff, gR[p]);
           // dL/dalpha = Tb diff, so sa = alpha dL/dalpha = wgt diff
-          const float sa = araw < S.alpha_max ? wgt * diff : 0.f;
+          const float sa = (!kClamp || araw < S.alpha_max) ? wgt * diff : 0.f;
           T[p] = Tb;
           q[0] = fmaf(sa, rx[p], q[0]);
           q[1] = fmaf(sa, ry[p], q[1]);
@@ -594,6 +661,17 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
         }
       }
     }
+    };
+    // the walk reaches list positions hi - 1 down to lo; past lo_last some pixel of the wave
+    // has not begun its walk yet
+    const bool check = hi - 1 > lo_last;
+    if (clamp_free) {
+      if (check) entries(std::false_type{}, std::true_type{});
+      else entries(std::false_type{}, std::false_type{});
+    } else {
+      if (check) entries(std::true_type{}, std::true_type{});
+      else entries(std::true_type{}, std::false_type{});
+    }
     G4D_WAVE_SYNC();
   }
 }
@@ -617,14 +695,26 @@ void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
                        st, b);
 }
 
-// Extra channels: one pixel per lane, 64-entry batches, CX the smallest supported payload width
-// that holds the E channels (the rest is zero padding).
+// Extra channels: 64-entry batches, CX the smallest supported payload width that holds the E
+// channels (the rest is zero padding).
+template <int TILE, int PXX, int PXY>
+void dispatch_ext_width(const RasterArgs& a, hipStream_t st, bool backward) {
+  if (a.n_ext <= 4) launch_raster<TILE, 64, PXX, PXY, 4>(a, st, backward);
+  else if (a.n_ext <= 8) launch_raster<TILE, 64, PXX, PXY, 8>(a, st, backward);
+  else if (a.n_ext <= 16) launch_raster<TILE, 64, PXX, PXY, 16>(a, st, backward);
+  else launch_raster<TILE, 64, PXX, PXY, 36>(a, st, backward);
+}
+
+// One or two pixels per lane (the runtime caps the extra-channel raster at two).
 template <int TILE>
 void dispatch_ext(const RasterArgs& a, hipStream_t st, bool backward) {
-  if (a.n_ext <= 4) launch_raster<TILE, 64, 1, 1, 4>(a, st, backward);
-  else if (a.n_ext <= 8) launch_raster<TILE, 64, 1, 1, 8>(a, st, backward);
-  else if (a.n_ext <= 16) launch_raster<TILE, 64, 1, 1, 16>(a, st, backward);
-  else launch_raster<TILE, 64, 1, 1, 36>(a, st, backward);
+  if constexpr (TILE >= 16) {
+    if (a.S.px_per_lane == 2) {
+      dispatch_ext_width<TILE, 2, 1>(a, st, backward);
+      return;
+    }
+  }
+  dispatch_ext_width<TILE, 1, 1>(a, st, backward);
 }
 
 template <int TILE, int PXX, int PXY>

@@ -199,3 +199,23 @@ def test_channel_argument_and_state_errors(renderer, w0):
     grads["features"] = torch.empty_like(run.f)
     with pytest.raises(B.G4DError, match="ESTATE"):
         renderer.backward_channels(run.g, run.views, run.settings, other, dL, None, grads)
+
+
+@pytest.mark.parametrize("tile,px", [(8, 1), (16, 1), (16, 2), (32, 2), (32, 4)])
+def test_channels_every_pixels_per_lane(renderer, w0, tile, px):
+    # The channel raster evaluates all pixels of a lane together; each (tile, pixels per lane)
+    # instantiation against the oracle, images and gradients (px 4 runs with two per lane).
+    D = 32
+    feats, gate = features_for(w0, D)
+    log(f"w0 channels tile={tile} px_per_lane={px}")
+    run = ChannelRun(renderer, w0, feats, gate, tile_size=tile, px_per_lane=px).forward()
+    check_channels(w0, w0.views[0], run.channels()[0], feats, gate, True, True)
+    dls = scenes.make_dl_dimage(w0)
+    dlch = scenes.make_dl_dchannels(w0, D + 3)
+    g = run.backward(dls, dlch)
+    with oracle_frame(w0, w0.views[0]) as fr:
+        fr.set_channels(feats, gate, depth=True, flow=True, flow_dt=DT)
+        ref = fr.backward(dls[0], dL_dext=dlch[0])
+    errs = parity.grad_rel_errors(g, ref)
+    log(f"  gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
