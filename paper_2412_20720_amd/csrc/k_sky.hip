@@ -86,11 +86,15 @@ __global__ __launch_bounds__(256) void k_sky(const DView* __restrict__ views,
   }
 }
 
-// Adjoint: each thread walks a kPatchX x kPatchY patch of pixels row by row, keeps the 12
-// partial sums (4 texels x 3 channels) of the current bilinear footprint and adds them to the
-// cube-map gradient only when the footprint changes (neighbouring pixels mostly share one,
-// texels being larger than pixels), which divides the atomics by the pixels per footprint.
-constexpr int kPatchX = 8, kPatchY = 4;
+// Adjoint: each thread walks a kPatchX x kPatchY patch of pixels row by row and keeps the 12
+// partial sums (4 texels x 3 channels) of up to kSlots bilinear footprints; a footprint's sums
+// are added to the cube-map gradient when its slot is reused (round robin) or at the end.
+// Texels are larger than pixels, so a patch meets few footprints (about 2 x 2 for texels of
+// 8-16 pixels) and the device-scope atomics, not the arithmetic, set the cost: keeping the
+// footprints of the previous rows divides them by the patch height against a one-footprint
+// cache.  Slots are indexed with compile-time constants only (selects, no dynamic register
+// indexing).
+constexpr int kPatchX = 16, kPatchY = 8, kSlots = 4;
 
 __device__ __forceinline__ void flush(float* d_cube, const int* idx, const float acc[4][3]) {
 #pragma unroll
@@ -111,9 +115,19 @@ __global__ __launch_bounds__(256) void k_sky_backward(const DView* __restrict__ 
   const int64_t patches = (int64_t)px_per_row * ((V.height + kPatchY - 1) / kPatchY);
   if (patch >= patches) return;
   const int x0 = (int)(patch % px_per_row) * kPatchX, y0 = (int)(patch / px_per_row) * kPatchY;
-  int cur = -1;
-  int idx[4] = {0, 0, 0, 0};
-  float acc[4][3] = {};
+  int base[kSlots], idx[kSlots][4];
+  float acc[kSlots][4][3];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    base[s] = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      idx[s][k] = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[s][k][c] = 0.f;
+    }
+  }
+  int next = 0;  // slot to reuse next
   for (int dy = 0; dy < kPatchY; ++dy) {
     const int py = y0 + dy;
     if (py >= V.height) break;
@@ -122,27 +136,46 @@ __global__ __launch_bounds__(256) void k_sky_backward(const DView* __restrict__ 
       if (px >= V.width) break;
       const int64_t pix = (int64_t)py * V.width + px;
       const CubeTap t = cube_tap(V, px, py, R);
-      if (t.base != cur) {
-        if (cur >= 0) flush(d_cube, idx, acc);
-        cur = t.base;
+      int hit = -1;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          idx[k] = t.idx[k];
+      for (int s = 0; s < kSlots; ++s) hit = base[s] == t.base ? s : hit;
+      if (hit < 0) {
 #pragma unroll
-          for (int c = 0; c < 3; ++c) acc[k][c] = 0.f;
+        for (int s = 0; s < kSlots; ++s) {
+          if (s == next) {
+            if (base[s] >= 0) flush(d_cube, idx[s], acc[s]);
+            base[s] = t.base;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              idx[s][k] = t.idx[k];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) acc[s][k][c] = 0.f;
+            }
+          }
         }
+        hit = next;
+        next = next + 1 == kSlots ? 0 : next + 1;
       }
       const float T = px_T[V.pix_base + pix];
       const float* d = dL + 3 * (int64_t)V.pix_base + pix;
+      float g[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float g = T * d[c * hw];
+      for (int c = 0; c < 3; ++c) g[c] = T * d[c * hw];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k][c] = fmaf(t.w[k], g, acc[k][c]);
+      for (int s = 0; s < kSlots; ++s) {
+        const bool h = s == hit;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float w = h ? t.w[k] : 0.f;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[s][k][c] = fmaf(w, g[c], acc[s][k][c]);
+        }
       }
     }
   }
-  if (cur >= 0) flush(d_cube, idx, acc);
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    if (base[s] >= 0) flush(d_cube, idx[s], acc[s]);
 }
 
 }  // namespace
