@@ -50,16 +50,17 @@ def raster_source_hash():
 
 def profiled_traffic(workload_name, settings):
     """HBM bytes per raster_bwd launch from the committed counter summary, if it was taken on
-    this workload and settings with the current raster source (else None)."""
+    this workload and launch configuration with the current raster source (else None)."""
     path = os.path.join(ROOT, "profiles", "raster_bwd_w2_traffic.md")
-    if (workload_name != "w2_300k_16views_mixed" or not os.path.exists(path) or
-            (settings.tile_size, settings.lds_batch, settings.px_per_lane) != (32, 64, 4)):
+    if workload_name != "w2_300k_16views_mixed" or not os.path.exists(path):
         return None
-    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and
-                  l.split(": ", 1)[0] in ("source-hash", "raster_bwd-traffic-bytes"))
+    lines = open(path).read().splitlines()
+    fields = dict(l.split(": ", 1) for l in lines if ": " in l)
     if fields.get("source-hash") != raster_source_hash():
         return None
-    return int(fields["raster_bwd-traffic-bytes"])
+    key = (f"raster_bwd-traffic-bytes tile={settings.tile_size} batch={settings.lds_batch} "
+           f"px={settings.px_per_lane}")
+    return int(fields[key]) if key in fields else None
 
 
 def main():
