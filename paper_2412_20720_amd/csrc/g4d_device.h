@@ -315,12 +315,23 @@ __device__ __forceinline__ void color_forward(const float* sh, const DSettings& 
   }
 }
 
-// Box of the cutoff ellipse, widened by 5e-4 relative so that FP32 rounding never drops a
-// pixel whose exact Mahalanobis distance passes the cutoff.
-__device__ __forceinline__ void cutoff_extent(const ViewFwd& f, const DSettings& S, float& ex,
-                                              float& ey) {
-  ex = S.cutoff * sqrtf(f.cov[0]) * 1.0005f;
-  ey = S.cutoff * sqrtf(f.cov[2]) * 1.0005f;
+// Squared Mahalanobis radius within which a splat of opacity * p_t = opt can be composited:
+// the cutoff^2, or less where alpha = opt exp(-d2 / 2) drops below alpha_min first, at
+// d2 = 2 ln(opt / alpha_min).  That bound is widened by 1e-3 relative plus 2e-3 absolute, so
+// that no pixel whose FP32 alpha passes alpha_min is ever left out; a result <= 0 means the splat
+// cannot be composited anywhere.  Binning the splat with this radius instead of the cutoff
+// leaves every image and gradient unchanged and drops the (tile, splat) pairs and the per-pixel
+// evaluations that could only fail the alpha_min test.  The preprocess (counting) and the key
+// generation (writing) evaluate it on the same stored opt with the same instructions.
+__device__ __forceinline__ float reach2(float opt, const DSettings& S) {
+  return fminf(S.cut2, fmaf(2.002f, logf(opt / S.alpha_min), 2e-3f));
+}
+
+// Box of the ellipse d2 <= r2, widened by 5e-4 relative so that FP32 rounding never drops a
+// pixel whose exact Mahalanobis distance passes the bound.
+__device__ __forceinline__ void reach_extent(const ViewFwd& f, float r2, float& ex, float& ey) {
+  ex = sqrtf(r2 * f.cov[0]) * 1.0005f;
+  ey = sqrtf(r2 * f.cov[2]) * 1.0005f;
 }
 
 // Tiles whose pixel centres can lie inside [u - ex, u + ex] x [v - ey, v + ey]:
@@ -398,9 +409,11 @@ __device__ __noinline__ int tile_row_span(float u, float v, float a, float b, fl
   return c0 <= c1 ? (c0 << 16) | c1 : -1;
 }
 
-// Cutoff used for tile coverage: 1e-3 above cutoff^2, so that FP32 rounding in the coverage
-// test never drops a pixel whose exact Mahalanobis distance passes the cutoff.
-__device__ __forceinline__ float coverage_limit(const DSettings& S) { return S.cut2 * 1.001f; }
+// Bound used for tile coverage: 1e-3 above reach2, so that FP32 rounding in the coverage test
+// never drops a pixel whose exact Mahalanobis distance passes it.
+__device__ __forceinline__ float coverage_limit(float opt, const DSettings& S) {
+  return reach2(opt, S) * 1.001f;
+}
 
 // ------------------------------------------------------------------------------------------
 // Adjoint of one view.  Inputs: the screen-space gradient q[0..8] of (u, v, conic a, b, c,

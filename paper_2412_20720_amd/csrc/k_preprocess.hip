@@ -51,13 +51,15 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const size_t slot = (size_t)v * n + gi;
     ViewFwd f;
     uint32_t cnt = 0;
-    if (view_forward(g, mean, V, S, f)) {
+    // a splat that cannot reach alpha_min at any pixel of this view is not listed
+    if (view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f) {
+      const float opt = op * f.pt;
       color_forward<DS, DT>(shc, S, f);
       float ex, ey;
-      cutoff_extent(f, S, ex, ey);
+      reach_extent(f, reach2(opt, S), ex, ey);
       int x0, x1, y0, y1;
       if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1)) {
-        const float lim = coverage_limit(S);
+        const float lim = coverage_limit(opt, S);
         for (int ty = y0; ty <= y1; ++ty) {
           const int span = tile_row_span(f.u, f.v, f.conic[0], f.conic[1], f.conic[2], lim, ex,
                                          ey, ty, S.tile_shift, V.width, V.height, x0, x1);
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
       if (cnt > 0) {
         float4* r = reinterpret_cast<float4*>(rec + slot * kRec);
         r[0] = make_float4(f.u, f.v, f.conic[0], f.conic[1]);
-        r[1] = make_float4(f.conic[2], op * f.pt, f.color[0], f.color[1]);
+        r[1] = make_float4(f.conic[2], opt, f.color[0], f.color[1]);
         r[2] = make_float4(f.color[2], ex, ey, f.x[2]);
         dkey[slot] = __float_as_uint(f.x[2]);
       }

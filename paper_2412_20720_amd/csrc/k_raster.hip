@@ -10,7 +10,9 @@
 // Per pixel and entry i (front to back): d2 = Mahalanobis distance of the pixel centre,
 // skip if d2 > cutoff^2; alpha = min(alpha_max, opacity p_i(t) exp(-d2/2)); skip if
 // alpha < alpha_min; stop (entry not composited) if T (1 - alpha) < T_min; else
-// C += T alpha c_i, T *= 1 - alpha.  Output C + T background.
+// C += T alpha c_i, T *= 1 - alpha.  Output C + T background.  The first skip is tested
+// against the entry's reach (the cutoff, or the smaller d2 beyond which alpha < alpha_min,
+// slightly widened), which drops only pixels that the second skip would drop.
 //
 // Backward: each pixel walks its list in reverse from its last composited entry, rebuilding
 // the transmittance in front of an entry as T / (1 - alpha) and the color behind it as
@@ -69,7 +71,7 @@ constexpr int kSlotGroup = G4D_SLOT_GROUP;
 struct Staged {
   float4 a;  // u, v, k conic a, 2 k conic b
   float4 b;  // k conic c, opacity * p_t, r, g
-  float4 c;  // b, list position (bits), slot (bits), unused
+  float4 c;  // b, list position (bits), slot (bits), k reach2 (the lowest pw it can composite at)
 };
 
 __device__ __forceinline__ int find_view(const int32_t* __restrict__ tile_base, int n_views,
@@ -151,16 +153,17 @@ __device__ __forceinline__ bool fetch_entry(const RasterArgs& a, const WaveTile&
   const float4 r0 = r[0], r1 = r[1], r2 = r[2];
   bool keep = (r0.x + r2.y >= t.qx0) && (r0.x - r2.y <= t.qx1) &&
               (r0.y + r2.z >= t.qy0) && (r0.y - r2.z <= t.qy1);
+  const float reach = reach2(r1.y, a.S);
   if (keep) {
     // exact test: the ellipse's x-range over the block's rows must meet the block's columns
     float xl, xr;
-    keep = ellipse_band_xrange(r0.z, r0.w, r1.x, coverage_limit(a.S), r2.y, r2.z,
+    keep = ellipse_band_xrange(r0.z, r0.w, r1.x, reach * 1.001f, r2.y, r2.z,
                                t.qy0 - r0.y, t.qy1 - r0.y, xl, xr) &&
            r0.x + xr >= t.qx0 && r0.x + xl <= t.qx1;
   }
   s.a = make_float4(r0.x, r0.y, kNegHalfLog2e * r0.z, 2.f * kNegHalfLog2e * r0.w);
   s.b = make_float4(kNegHalfLog2e * r1.x, r1.y, r1.z, r1.w);
-  s.c = make_float4(r2.x, __int_as_float((int)j), __uint_as_float(slot), 0.f);
+  s.c = make_float4(r2.x, __int_as_float((int)j), __uint_as_float(slot), kNegHalfLog2e * reach);
   return keep;
 }
 
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     }
     for (int k = 0; k < n; ++k) {
       const float4 e0 = st[k].a, e1 = st[k].b;
-      const float2 e2 = make_float2(st[k].c.x, st[k].c.y);
+      const float4 e2 = st[k].c;
       bool any_stop = false;
       bool any_take = false;
       float wk[P];  // T alpha of this entry per pixel, 0 where it is not composited
@@ -321,7 +324,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           const int p = g + i;
           const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
           pwg[i] = mahalanobis(dx, dy, e0, e1.x);
-          ing[i] = pwg[i] >= lo[p];
+          // Pixel still live and within the cutoff.  The counting variant also applies the
+          // entry's reach, as the backward does, so that its count of evaluated pairs is the
+          // backward's; the timed forward leaves that test out (one more instruction per pixel
+          // costs it more than the skipped pixels save).
+          ing[i] = pwg[i] >= (COUNT ? __builtin_amdgcn_fmed3f(lo[p], e2.w, INFINITY) : lo[p]);
           gin |= ing[i];
         }
         if (__ballot(gin) == 0ull) continue;
@@ -525,7 +532,6 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   if (hi_last < 0) return;
   // entries at or before every pixel's last composited one need no per-pixel position test
   const int lo_last = __builtin_amdgcn_readfirstlane(wave_min(lane_first));
-  const float lo_cut = kNegHalfLog2e * S.cut2;
   Staged* st = stage[t.w];
   float* xp = xstage[t.w];
   const int lo_list = (int)t.range.x;
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
           const int p = g + i;
           const float dx = pxc[p] - e0.x, dy = pyc[p] - e0.y;
           pwg[i] = mahalanobis(dx, dy, e0, e1.x);
-          ing[i] = (!kCheckLast || jk <= last[p]) && pwg[i] >= lo_cut;
+          ing[i] = (!kCheckLast || jk <= last[p]) && pwg[i] >= e2.w;
           gin |= ing[i];
         }
         if (__ballot(gin) == 0ull) continue;

@@ -307,6 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
   __shared__ float s_ex[4][64], s_ey[4][64];
   __shared__ int32_t s_x0[4][64], s_x1[4][64], s_y0[4][64], s_tx[4][64], s_tb[4][64];
   __shared__ int32_t s_w[4][64], s_h[4][64];
+  __shared__ float s_lim[4][64];
   __shared__ uint32_t s_slot[4][64];
   __shared__ uint32_t s_start[4][64], s_key0[4][64], s_val[4][64];  // runs of one round
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
     s_c[w][lane] = p[R_C];
     s_ex[w][lane] = p[R_EX];
     s_ey[w][lane] = p[R_EY];
+    s_lim[w][lane] = coverage_limit(p[R_OPT], S);
     s_x0[w][lane] = x0;
     s_x1[w][lane] = x1;
     s_y0[w][lane] = y0;
@@ -348,7 +350,6 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const float lim = coverage_limit(S);
   uint32_t cursor = off0;
   for (uint32_t k0 = 0; k0 < n_rows; k0 += 64) {
     const uint32_t k = k0 + lane;
@@ -362,7 +363,8 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
       }
       i = lo;
       ty = s_y0[w][i] + (int)(k - s_rows[w][i]);
-      const int span = tile_row_span(s_u[w][i], s_v[w][i], s_a[w][i], s_b[w][i], s_c[w][i], lim,
+      const int span = tile_row_span(s_u[w][i], s_v[w][i], s_a[w][i], s_b[w][i], s_c[w][i],
+                                     s_lim[w][i],
                                      s_ex[w][i], s_ey[w][i], ty, S.tile_shift, s_w[w][i],
                                      s_h[w][i], s_x0[w][i], s_x1[w][i]);
       if (span >= 0) {

@@ -120,12 +120,18 @@ def test_w1_records_match_oracle_splats(renderer, w1):
     with oracle_frame(w1, w1.views[0]) as fr:
         sp = fr.splats()
     W, H = w1.views[0]["width"], w1.views[0]["height"]
-    # A splat is visible when it survives the culls and its cutoff ellipse reaches a pixel
-    # centre: the minimum Mahalanobis distance over the image's pixel-centre rectangle.
+    # A splat is listed when it survives the culls and can be composited at some pixel centre:
+    # the minimum Mahalanobis distance over the image's pixel-centre rectangle lies within the
+    # cutoff and within the radius where opacity p_t exp(-d2 / 2) still reaches alpha_min,
+    # d2 = 2 ln(opacity p_t / alpha_min).  The GPU widens that radius by 1e-3 relative and
+    # 2e-3 absolute: within the widening either outcome is admissible.
     d2min = min_d2_over_rect(sp["mean2d"], sp["conic"], 0.5, W - 0.5, 0.5, H - 0.5)
     gpu_vis = tiles > 0
-    must = (sp["alive"] == 1) & (d2min <= 9.0 * (1 - 1e-4))
-    may = ((sp["alive"] == 1) | (sp["optional"] == 1)) & (d2min <= 9.0 * (1 + 1e-2))
+    log_ratio = np.log(np.maximum(sp["opt"], 1e-300) * 255.0)
+    reach = np.minimum(9.0, 2.0 * log_ratio)
+    reach_wide = np.minimum(9.0, 2.002 * log_ratio + 2e-3)
+    must = (sp["alive"] == 1) & (d2min <= reach * (1 - 1e-4) - 1e-4)
+    may = ((sp["alive"] == 1) | (sp["optional"] == 1)) & (d2min <= reach_wide * (1 + 1e-2))
     log(f"visible gpu={gpu_vis.sum()} oracle={must.sum()}..{may.sum()}")
     assert not (must & ~gpu_vis).any() and not (gpu_vis & ~may).any()
     ref_vis = must
@@ -138,10 +144,14 @@ def test_w1_records_match_oracle_splats(renderer, w1):
     np.testing.assert_allclose(r[:, 5], s["opt"], rtol=1e-4, atol=1e-7)
     np.testing.assert_allclose(r[:, 6:9], s["color"], atol=2e-5)
     np.testing.assert_allclose(r[:, 11], s["depth"], rtol=2e-6)
-    # box half extents: at least 3 sigma, widened by at most 1e-3 relative
-    hx, hy = 3 * np.sqrt(s["cov2d"][:, 0]), 3 * np.sqrt(s["cov2d"][:, 2])
-    assert (r[:, 9] >= hx * (1 - 1e-5)).all() and (r[:, 9] <= hx * 1.001).all()
-    assert (r[:, 10] >= hy * (1 - 1e-5)).all() and (r[:, 10] <= hy * 1.001).all()
+    # box half extents: at least sqrt(reach) sigma (3 sigma for splats opaque enough to reach
+    # alpha_min beyond the cutoff), at most the widened radius plus 1e-3 relative
+    lr = np.log(s["opt"] * 255.0)
+    lo_r, hi_r = np.minimum(9.0, 2.0 * lr), np.minimum(9.0, 2.002 * lr + 2e-3)
+    assert (hi_r < 9.0).any() and (lo_r == 9.0).any()
+    for col, var in ((9, s["cov2d"][:, 0]), (10, s["cov2d"][:, 2])):
+        assert (r[:, col] >= np.sqrt(lo_r * var) * (1 - 1e-5)).all()
+        assert (r[:, col] <= np.sqrt(hi_r * var) * 1.001).all()
 
 
 def test_w1_sampled_pixels(renderer, w1):
