@@ -234,3 +234,34 @@ def test_argument_errors(renderer, w0):
     for bad_alpha in (dict(alpha_max=1.0), dict(alpha_min=0.0), dict(alpha_min=0.5, alpha_max=0.4)):
         with pytest.raises(B.G4DError, match="EINVAL"):
             renderer.forward(run.g, run.views, settings_for(w0, **bad_alpha), run.rgb, run.T)
+
+
+def test_w1_pair_counts_match_oracle(renderer, w1):
+    # The counting forward's per-pixel counts: composited pairs equal the oracle's wherever no
+    # decision of the pixel lies within the FP32/FP64 margin; evaluated pairs (within the
+    # entry's reach) lie between the composited ones and the oracle's pairs within the cutoff.
+    log("w1 pair counts")
+    run = GpuRun(renderer, w1)
+    npix = run.T.numel()
+    renderer.eval_counters(True)
+    run.forward()
+    cnt = renderer.eval_counters(False, npix).cpu().numpy().astype(np.int64)
+    W, H = w1.views[0]["width"], w1.views[0]["height"]
+    rng = np.random.default_rng(6)
+    xy = np.stack([rng.integers(0, W, 4000), rng.integers(0, H, 4000)], 1)
+    g = cnt[xy[:, 1] * W + xy[:, 0]]
+    evals, contrib = g & 0xFFFF, g >> 16
+    with oracle_frame(w1, w1.views[0]) as fr:
+        ref = fr.render(xy)
+    marks = ref["n_marks"]
+    clean = marks == 0
+    log(f"  composited: {contrib.sum()} gpu, {ref['n_contrib'].sum()} oracle; evaluated "
+        f"{evals.sum()} gpu, {ref['n_evals'].sum()} oracle within the cutoff; marked {int((~clean).sum())}")
+    assert clean.mean() > 0.5
+    assert np.array_equal(contrib[clean], ref["n_contrib"][clean])
+    # a flipped decision moves the count by one (alpha_min) or ends the walk one entry apart
+    assert np.all(np.abs(contrib - ref["n_contrib"]) <= 2 * marks)
+    assert np.all(contrib <= evals)
+    assert np.all(evals[clean] <= ref["n_evals"][clean])
+    assert np.all(evals <= ref["n_evals"] + 4 * marks)
+    assert evals.sum() < 0.9 * ref["n_evals"].sum()  # the reach drops pixels the cutoff keeps
