@@ -59,8 +59,16 @@ def profiled_traffic(workload_name, settings):
     if fields.get("source-hash") != raster_source_hash():
         return None
     key = (f"raster_bwd-traffic-bytes tile={settings.tile_size} batch={settings.lds_batch} "
-           f"px={settings.px_per_lane}")
+           f"bwd_px={backward_px(settings)}")
     return int(fields[key]) if key in fields else None
+
+
+def backward_px(settings):
+    """Pixels per lane the backward raster runs with (the library's default when 0)."""
+    if settings.bwd_px_per_lane:
+        return settings.bwd_px_per_lane
+    px = settings.px_per_lane or (1 if settings.tile_size == 8 else 4)
+    return 8 if settings.tile_size == 32 and px == 4 else px
 
 
 def main():
@@ -72,6 +80,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile size (0: autotune)")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--px", type=int, default=4)
+    ap.add_argument("--bwd-px", type=int, default=0, help="backward pixels per lane (0: default)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=1)
@@ -99,7 +108,8 @@ def main():
     names = ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh")
     g = r.gaussians(*[p[k] for k in names], sc.sh_degree, sc.t_degree)
     settings = B.default_settings(time_period=sc.time_period, tile_size=args.tile or 16,
-                                  lds_batch=args.batch, px_per_lane=args.px)
+                                  lds_batch=args.batch, px_per_lane=args.px,
+                                  bwd_px_per_lane=args.bwd_px)
     views = B.make_views(sc.views)
     npix = sc.pixels
     rgb = torch.empty(3 * npix, device=dev)
@@ -115,7 +125,7 @@ def main():
     if args.tile == 0:
         tuned_ms = r.autotune(g, views, settings, dL, rgb, T, grads, reps=2)
         log(f"bench: autotuned tile {settings.tile_size}, LDS batch {settings.lds_batch}, "
-            f"pixels/lane {settings.px_per_lane} ({tuned_ms:.2f} ms)")
+            f"pixels/lane {settings.px_per_lane}, backward {backward_px(settings)} ({tuned_ms:.2f} ms)")
 
     # Work counts of this workload (untimed, counted by the forward kernel itself).
     r.eval_counters(True)
@@ -230,7 +240,8 @@ def main():
         "config": {"workload": sc.name, "gaussians": sc.n, "views": len(sc.views),
                    "pixels": npix, "sh_degree": sc.sh_degree, "t_degree": sc.t_degree,
                    "tile": settings.tile_size, "lds_batch": settings.lds_batch,
-                   "px_per_lane": settings.px_per_lane, "autotuned": args.tile == 0},
+                   "px_per_lane": settings.px_per_lane, "bwd_px_per_lane": backward_px(settings),
+                   "autotuned": args.tile == 0},
         "per_view": per_view,
         "graph": graph,
         "roofline": roofline,

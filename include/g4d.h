@@ -113,11 +113,15 @@ typedef struct {
  *   px_per_lane 0     pixels per lane of the raster waves: 1 (8x8 block per wave), 2 (16x8)
  *                     or 4 (16x16); 2 and 4 need tile_size >= 16 (0 = library default:
  *                     4, or 1 for 8-pixel tiles)
+ *   bwd_px_per_lane 0 pixels per lane of the backward raster waves: 1, 2, 4 as above, or 8
+ *                     (16x32 blocks, tile_size 32 only); 0 = library default: 8 at 32-pixel
+ *                     tiles when the forward takes 4, else the forward's value.  The backward
+ *                     reads only per-pixel state of the forward, so the two may differ.
  * Tile size, batch and pixels per lane change the work decomposition only, never the image. */
 typedef struct {
   float near_z, marginal_min, cutoff_sigma, blur, jacobian_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
-  int32_t tile_size, lds_batch, px_per_lane;
+  int32_t tile_size, lds_batch, px_per_lane, bwd_px_per_lane;
 } g4d_settings;
 
 /* Work counters of the last forward (host). */

@@ -51,7 +51,8 @@ class g4d_settings(C.Structure):
                 ("blur", C.c_float), ("jacobian_margin", C.c_float), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("color_offset", C.c_float),
                 ("color_min", C.c_float), ("time_period", C.c_float), ("tile_size", C.c_int32),
-                ("lds_batch", C.c_int32), ("px_per_lane", C.c_int32)]
+                ("lds_batch", C.c_int32), ("px_per_lane", C.c_int32),
+                ("bwd_px_per_lane", C.c_int32)]
 
 
 class g4d_channels(C.Structure):

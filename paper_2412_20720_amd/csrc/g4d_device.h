@@ -50,7 +50,7 @@ struct DView {
 struct DSettings {
   float near_z, marginal_min, cutoff, cut2, blur, jac_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
-  int32_t tile, tile_shift, lds_batch, px_per_lane;
+  int32_t tile, tile_shift, lds_batch, px_per_lane, bwd_px_per_lane;
 };
 
 // ------------------------------------------------------------------------------------------

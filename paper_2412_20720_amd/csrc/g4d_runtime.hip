@@ -73,7 +73,7 @@ struct g4d_ctx {
   double stage_ms[G4D_NUM_STAGES] = {};
   int64_t stage_n[G4D_NUM_STAGES] = {};
   // autotuner cache: problem shape -> (tile, lds batch, pixels per lane, ms)
-  struct Tuned { int tile, batch, px; double ms; };
+  struct Tuned { int tile, batch, px, bwd_px; double ms; };
   std::map<std::string, Tuned> tuned;
   // graph mode: while `capturing`, no host synchronization, allocation or upload happens and
   // grids are sized from the capacities found by an earlier eager pass
@@ -213,6 +213,11 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     return fail(ctx, G4D_EINVAL, "px_per_lane %d not in {0, 1, 2, 4}", s->px_per_lane);
   if (s->tile_size == 8 && s->px_per_lane > 1)
     return fail(ctx, G4D_EINVAL, "px_per_lane %d needs tile_size >= 16", s->px_per_lane);
+  const int bp = s->bwd_px_per_lane;
+  if (bp != 0 && bp != 1 && bp != 2 && bp != 4 && bp != 8)
+    return fail(ctx, G4D_EINVAL, "bwd_px_per_lane %d not in {0, 1, 2, 4, 8}", bp);
+  if ((s->tile_size == 8 && bp > 1) || (s->tile_size != 32 && bp == 8))
+    return fail(ctx, G4D_EINVAL, "bwd_px_per_lane %d does not fit tile_size %d", bp, s->tile_size);
   return G4D_OK;
 }
 
@@ -255,6 +260,7 @@ g4d_settings run_settings(const g4d_settings* s, const g4d_channels* ch) {
   if (ch) {
     r.lds_batch = 64;
     r.px_per_lane = r.tile_size == 8 ? 1 : (r.px_per_lane == 1 ? 1 : 2);
+    r.bwd_px_per_lane = r.px_per_lane;
   }
   return r;
 }
@@ -277,6 +283,13 @@ DSettings device_settings(const g4d_settings* s) {
   d.tile_shift = s->tile_size == 8 ? 3 : (s->tile_size == 16 ? 4 : 5);
   d.lds_batch = s->lds_batch == 0 ? 64 : s->lds_batch;
   d.px_per_lane = s->px_per_lane == 0 ? (s->tile_size == 8 ? 1 : 4) : s->px_per_lane;
+  // The backward's default: 16x32 blocks where the forward takes 16x16 ones at 32-pixel
+  // tiles.  It amortizes the per-entry wave reduction and atomic over twice the pixels
+  // (measured on the 300k/16-view workload: raster_bwd 2.36 -> 2.16 ms; the forward, with no
+  // per-entry reduction, is slower at 8: 1.04 -> 1.17 ms).
+  d.bwd_px_per_lane = s->bwd_px_per_lane != 0
+                          ? s->bwd_px_per_lane
+                          : (s->tile_size == 32 && d.px_per_lane == 4 ? 8 : d.px_per_lane);
   return d;
 }
 
@@ -405,6 +418,7 @@ g4d_status g4d_default_settings(g4d_settings* s) {
   s->tile_size = 16;
   s->lds_batch = 0;
   s->px_per_lane = 0;
+  s->bwd_px_per_lane = 0;
   return G4D_OK;
 }
 
@@ -1016,44 +1030,54 @@ g4d_status g4d_autotune(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
     s->tile_size = it->second.tile;
     s->lds_batch = it->second.batch;
     s->px_per_lane = it->second.px;
+    s->bwd_px_per_lane = it->second.bwd_px;
     if (best_ms) *best_ms = it->second.ms;
     return G4D_OK;
   }
   hipEvent_t e0, e1;
   G4D_HIP(hipEventCreate(&e0));
   G4D_HIP(hipEventCreate(&e1));
-  g4d_ctx::Tuned best{16, 64, 4, 1e30};
-  const int tiles[] = {8, 16, 32}, batches[] = {32, 64, 128}, pxs[] = {1, 2, 4};
-  for (int tile : tiles)
-    for (int px : pxs) {
+  g4d_ctx::Tuned best{16, 64, 4, 4, 1e30};
+  // Candidates: tile x pixels per lane x backward pixels per lane (the forward's, or 8 at
+  // 32-pixel tiles) x LDS batch.
+  struct Cand { int tile, px, bwd_px; };
+  std::vector<Cand> cands;
+  for (int tile : {8, 16, 32})
+    for (int px : {1, 2, 4}) {
       if (tile == 8 && px > 1) continue;
-      for (int batch : batches) {
-        g4d_settings trial = *s;
-        trial.tile_size = tile;
-        trial.lds_batch = batch;
-        trial.px_per_lane = px;
-        // one untimed pass sizes every buffer for this tile size
-        if ((r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream)) != G4D_OK ||
-            (r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream)) != G4D_OK)
-          break;
-        G4D_HIP(hipEventRecord(e0, st));
-        for (int k = 0; k < reps && r == G4D_OK; ++k) {
-          r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream);
-          if (r == G4D_OK)
-            r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream);
-        }
-        if (r != G4D_OK) break;
-        G4D_HIP(hipEventRecord(e1, st));
-        G4D_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        G4D_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double per = ms / reps;
-        if (std::getenv("G4D_TUNE_VERBOSE"))
-          fprintf(stderr, "g4d_autotune: tile %d batch %d px/lane %d: %.3f ms\n", tile, batch, px, per);
-        if (per < best.ms) best = {tile, batch, px, per};
+      cands.push_back({tile, px, px});
+      if (tile == 32) cands.push_back({tile, px, 8});
+    }
+  for (const Cand& c : cands) {
+    for (int batch : {32, 64, 128}) {
+      g4d_settings trial = *s;
+      trial.tile_size = c.tile;
+      trial.lds_batch = batch;
+      trial.px_per_lane = c.px;
+      trial.bwd_px_per_lane = c.bwd_px;
+      // one untimed pass sizes every buffer for this tile size
+      if ((r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream)) != G4D_OK ||
+          (r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream)) != G4D_OK)
+        break;
+      G4D_HIP(hipEventRecord(e0, st));
+      for (int k = 0; k < reps && r == G4D_OK; ++k) {
+        r = g4d_render_forward(ctx, g, views, n_views, &trial, out_rgb, out_T, stream);
+        if (r == G4D_OK)
+          r = g4d_render_backward(ctx, g, views, n_views, &trial, dL_drgb, grads, stream);
       }
       if (r != G4D_OK) break;
+      G4D_HIP(hipEventRecord(e1, st));
+      G4D_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      G4D_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / reps;
+      if (std::getenv("G4D_TUNE_VERBOSE"))
+        fprintf(stderr, "g4d_autotune: tile %d batch %d px/lane %d (backward %d): %.3f ms\n",
+                c.tile, batch, c.px, c.bwd_px, per);
+      if (per < best.ms) best = {c.tile, batch, c.px, c.bwd_px, per};
     }
+    if (r != G4D_OK) break;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (r != G4D_OK) return r;
@@ -1061,6 +1085,7 @@ g4d_status g4d_autotune(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
   s->tile_size = best.tile;
   s->lds_batch = best.batch;
   s->px_per_lane = best.px;
+  s->bwd_px_per_lane = best.bwd_px;
   if (best_ms) *best_ms = best.ms;
   return G4D_OK;
 }

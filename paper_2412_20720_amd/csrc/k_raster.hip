@@ -682,18 +682,37 @@ __global__ __launch_bounds__(256) void k_raster_bwd(RasterArgs a) {
   }
 }
 
+// Grid of 4-wave workgroups, one wave per (8 PXX) x (8 PXY) block of every tile, padded to a
+// multiple of the 8 XCDs (see xcd_logical_block); returns 0 when there is nothing to draw.
+template <int TILE, int PXX, int PXY>
+unsigned raster_grid(RasterArgs& b) {
+  static_assert(TILE % (8 * PXX) == 0 && TILE % (8 * PXY) == 0, "block must tile the tile");
+  constexpr int QPT = (TILE / (8 * PXX)) * (TILE / (8 * PXY));
+  const int64_t waves = (int64_t)b.n_tiles * QPT;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks == 0) return 0u;
+  b.blocks_per_xcd = (int)((blocks + 7) / 8);
+  return 8u * (unsigned)b.blocks_per_xcd;
+}
+
+template <int TILE, int BATCH, int PXX, int PXY, int CX = 0>
+void launch_backward(const RasterArgs& a, hipStream_t st) {
+  RasterArgs b = a;
+  const unsigned grid = raster_grid<TILE, PXX, PXY>(b);
+  if (grid == 0u) return;
+  hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY, CX>), dim3(grid), dim3(256), 0, st, b);
+}
+
 template <int TILE, int BATCH, int PXX, int PXY, int CX = 0>
 void launch_raster(const RasterArgs& a, hipStream_t st, bool backward) {
-  constexpr int QPT = (TILE / (8 * PXX)) * (TILE / (8 * PXY));
-  const int64_t waves = (int64_t)a.n_tiles * QPT;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks == 0) return;
+  if (backward) {
+    launch_backward<TILE, BATCH, PXX, PXY, CX>(a, st);
+    return;
+  }
   RasterArgs b = a;
-  b.blocks_per_xcd = (int)((blocks + 7) / 8);
-  const unsigned grid = 8u * (unsigned)b.blocks_per_xcd;
-  if (backward)
-    hipLaunchKernelGGL((k_raster_bwd<TILE, BATCH, PXX, PXY, CX>), dim3(grid), dim3(256), 0, st, b);
-  else if (CX == 0 && b.px_evals)
+  const unsigned grid = raster_grid<TILE, PXX, PXY>(b);
+  if (grid == 0u) return;
+  if (CX == 0 && b.px_evals)
     hipLaunchKernelGGL((k_raster_fwd<TILE, BATCH, PXX, PXY, true, 0>), dim3(grid), dim3(256), 0, st,
                        b);
   else
@@ -732,11 +751,24 @@ void dispatch_batch(const RasterArgs& a, hipStream_t st, bool backward) {
   }
 }
 
+// 16x32 blocks (8 pixels per lane), backward only and at 32-pixel tiles.
+template <int TILE>
+void dispatch_backward8(const RasterArgs& a, hipStream_t st) {
+  if constexpr (TILE == 32) {
+    switch (a.S.lds_batch) {
+      case 32: launch_backward<TILE, 32, 2, 4>(a, st); break;
+      case 128: launch_backward<TILE, 128, 2, 4>(a, st); break;
+      default: launch_backward<TILE, 64, 2, 4>(a, st); break;
+    }
+  }
+}
+
 template <int TILE>
 void dispatch_px(const RasterArgs& a, hipStream_t st, bool backward) {
-  switch (a.S.px_per_lane) {
+  switch (backward ? a.S.bwd_px_per_lane : a.S.px_per_lane) {
     case 2: dispatch_batch<TILE, 2, 1>(a, st, backward); break;
     case 4: dispatch_batch<TILE, 2, 2>(a, st, backward); break;
+    case 8: dispatch_backward8<TILE>(a, st); break;
     default: dispatch_batch<TILE, 1, 1>(a, st, backward); break;
   }
 }

@@ -58,7 +58,7 @@ def test_struct_layouts_match_c(B, tmp_path):
 
 def test_default_settings(B):
     s = B.default_settings()
-    assert s.tile_size == 16 and s.lds_batch == 0
+    assert s.tile_size == 16 and s.lds_batch == 0 and s.px_per_lane == 0 and s.bwd_px_per_lane == 0
     assert abs(s.marginal_min - 1 / 255) < 1e-9 and abs(s.alpha_min - 1 / 255) < 1e-9
     assert abs(s.alpha_max - 0.99) < 1e-7 and abs(s.T_min - 1e-4) < 1e-10
     assert abs(s.cutoff_sigma - 3.0) < 1e-7 and abs(s.blur - 0.3) < 1e-7

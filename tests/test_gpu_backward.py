@@ -123,3 +123,30 @@ def test_backward_state_errors(renderer):
     renderer.backward(run.g, run.views, run.settings, dL, grads)
     torch.cuda.synchronize()
     assert all(float(grads[k].abs().max()) == 0.0 for k in PARAMS)
+
+
+@pytest.mark.parametrize("tile,px,bwd_px", [(32, 4, 8), (32, 4, 4), (32, 2, 8), (32, 1, 8),
+                                            (16, 4, 2), (16, 1, 4)])
+def test_backward_block_shapes(renderer, tile, px, bwd_px):
+    # The backward's block shape is independent of the forward's (it reads only per-pixel
+    # state); every combination gives the oracle's gradients.
+    sc = scenes.make_workload(0)
+    dl = scenes.make_dl_dimage(sc)
+    log(f"w0 tile {tile} forward px {px} backward px {bwd_px}")
+    run = GpuRun(renderer, sc, tile_size=tile, px_per_lane=px, bwd_px_per_lane=bwd_px).forward()
+    g = run.backward(dl)
+    with oracle_frame(sc, sc.views[0]) as fr:
+        ref = fr.backward(dl[0])
+    errs = parity.grad_rel_errors(g, ref)
+    log(f"  gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
+
+
+def test_backward_block_shape_errors(renderer):
+    from paper_2412_20720_amd import _binding as B
+    sc = scenes.make_workload(0)
+    run = GpuRun(renderer, sc).forward()
+    for tile, bwd_px in ((16, 8), (8, 2), (32, 3)):
+        s = B.default_settings(time_period=sc.time_period, tile_size=tile, bwd_px_per_lane=bwd_px)
+        with pytest.raises(B.G4DError, match="EINVAL"):
+            renderer.forward(run.g, run.views, s, run.rgb, run.T)
