@@ -409,6 +409,24 @@ __device__ __noinline__ int tile_row_span(float u, float v, float a, float b, fl
   return c0 <= c1 ? (c0 << 16) | c1 : -1;
 }
 
+// Inclusive and exclusive prefix sums over the 64 lanes of a wave (all lanes active); the
+// exclusive one also returns the wave total.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
+  const uint32_t inc = wave_incl_scan(x);
+  total = __shfl(inc, 63, 64);
+  return inc - x;
+}
+
 // Bound used for tile coverage: 1e-3 above reach2, so that FP32 rounding in the coverage test
 // never drops a pixel whose exact Mahalanobis distance passes it.
 __device__ __forceinline__ float coverage_limit(float opt, const DSettings& S) {

@@ -13,6 +13,17 @@ namespace g4d {
 namespace {
 
 // CP: the parameters come from a compact model, decoded here in registers (Sec. 4.2).
+// Covered tiles are counted by the whole wave together: each lane's splat contributes its rows
+// of tiles (of the reach box), the rows of the 64 splats are numbered by a wave scan and dealt
+// out 64 per round, and each lane adds its row's run of tile columns to the row owner's count
+// in LDS.  A wave so takes about (rows of its splats) / 64 rounds per view instead of the rows of
+// its largest splat, and the count uses the very function the key generation writes with.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int DS, int DT, bool CP>
 __global__ __launch_bounds__(256) void k_preprocess(
     int n, int n_views, const float4* __restrict__ mean4, const float4* __restrict__ scale4,
@@ -22,25 +33,34 @@ __global__ __launch_bounds__(256) void k_preprocess(
     uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey, const float* __restrict__ mask,
     float mask_thr, CompactPtrs cp) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
+  __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64], s_lim[4][64];
+  __shared__ float s_ex[4][64], s_ey[4][64];
+  __shared__ int32_t s_y0[4][64], s_x0[4][64], s_x1[4][64];
+  __shared__ uint32_t s_row0[4][64], s_cnt[4][64];
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi >= n) return;
-  if (mask && !(mask[gi] > mask_thr)) {
-    // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool in_range = gi < n;
+  // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
+  const bool live = in_range && !(mask && !(mask[gi] > mask_thr));
+  if (in_range && !live)
     for (int v = 0; v < n_views; ++v) tiles[(size_t)v * n + gi] = 0u;
-    return;
-  }
+  if (__ballot(live) == 0ull) return;  // the whole wave: the lanes below work together
+  // Lanes past the end read the last Gaussian (unconditional loads of read-only data, which
+  // the compiler may repeat per view instead of holding 4DSH coefficients in registers); only
+  // live lanes list anything.
+  const int gl = in_range ? gi : n - 1;
   float4 mean, sc4, qlr, qrr;
   float op;
   float shc[NSH];
   if constexpr (CP) {
-    decode_compact<NSH>(cp, gi, mean, sc4, qlr, qrr, op, shc);
+    decode_compact<NSH>(cp, gl, mean, sc4, qlr, qrr, op, shc);
   } else {
-    mean = mean4[gi];
-    sc4 = scale4[gi];
-    qlr = rot_l[gi];
-    qrr = rot_r[gi];
-    op = opacity[gi];
-    const float* shp = sh + (size_t)gi * NSH;
+    mean = mean4[gl];
+    sc4 = scale4[gl];
+    qlr = rot_l[gl];
+    qrr = rot_r[gl];
+    op = opacity[gl];
+    const float* shp = sh + (size_t)gl * NSH;
 #pragma unroll
     for (int k = 0; k < NSH; ++k) shc[k] = shp[k];
   }
@@ -50,31 +70,64 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const DView& V = views[v];
     const size_t slot = (size_t)v * n + gi;
     ViewFwd f;
-    uint32_t cnt = 0;
     // a splat that cannot reach alpha_min at any pixel of this view is not listed
-    if (view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f) {
-      const float opt = op * f.pt;
+    const bool vis = live && view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f;
+    float opt = 0.f, ex = 0.f, ey = 0.f;
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    uint32_t rows = 0;
+    if (vis) {
+      opt = op * f.pt;
       color_forward<DS, DT>(shc, S, f);
-      float ex, ey;
       reach_extent(f, reach2(opt, S), ex, ey);
-      int x0, x1, y0, y1;
-      if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1)) {
-        const float lim = coverage_limit(opt, S);
-        for (int ty = y0; ty <= y1; ++ty) {
-          const int span = tile_row_span(f.u, f.v, f.conic[0], f.conic[1], f.conic[2], lim, ex,
-                                         ey, ty, S.tile_shift, V.width, V.height, x0, x1);
-          if (span >= 0) cnt += (uint32_t)((span & 0xFFFF) - (span >> 16) + 1);
+      if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1))
+        rows = (uint32_t)(y1 - y0 + 1);
+    }
+    uint32_t total;
+    const uint32_t row0 = wave_excl_scan(rows, total);
+    uint32_t cnt = 0;
+    if (total > 0u) {
+      s_u[w][lane] = f.u;
+      s_v[w][lane] = f.v;
+      s_a[w][lane] = f.conic[0];
+      s_b[w][lane] = f.conic[1];
+      s_c[w][lane] = f.conic[2];
+      s_lim[w][lane] = coverage_limit(opt, S);
+      s_ex[w][lane] = ex;
+      s_ey[w][lane] = ey;
+      s_y0[w][lane] = y0;
+      s_x0[w][lane] = x0;
+      s_x1[w][lane] = x1;
+      s_row0[w][lane] = row0;
+      s_cnt[w][lane] = 0u;
+      wave_sync();
+      for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+        const uint32_t k = k0 + (uint32_t)lane;
+        if (k < total) {
+          int lo = 0, hi = 63;  // the last lane whose rows start at or before k owns row k
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_row0[w][mid] <= k) lo = mid; else hi = mid - 1;
+          }
+          const int ty = s_y0[w][lo] + (int)(k - s_row0[w][lo]);
+          const int span = tile_row_span(s_u[w][lo], s_v[w][lo], s_a[w][lo], s_b[w][lo],
+                                         s_c[w][lo], s_lim[w][lo], s_ex[w][lo], s_ey[w][lo], ty,
+                                         S.tile_shift, V.width, V.height, s_x0[w][lo],
+                                         s_x1[w][lo]);
+          if (span >= 0) atomicAdd(&s_cnt[w][lo], (uint32_t)((span & 0xFFFF) - (span >> 16) + 1));
         }
       }
-      if (cnt > 0) {
-        float4* r = reinterpret_cast<float4*>(rec + slot * kRec);
-        r[0] = make_float4(f.u, f.v, f.conic[0], f.conic[1]);
-        r[1] = make_float4(f.conic[2], opt, f.color[0], f.color[1]);
-        r[2] = make_float4(f.color[2], ex, ey, f.x[2]);
-        dkey[slot] = __float_as_uint(f.x[2]);
-      }
+      wave_sync();
+      cnt = s_cnt[w][lane];
+      wave_sync();  // the next view overwrites the arrays
     }
-    tiles[slot] = cnt;
+    if (cnt > 0) {
+      float4* r = reinterpret_cast<float4*>(rec + slot * kRec);
+      r[0] = make_float4(f.u, f.v, f.conic[0], f.conic[1]);
+      r[1] = make_float4(f.conic[2], opt, f.color[0], f.color[1]);
+      r[2] = make_float4(f.color[2], ex, ey, f.x[2]);
+      dkey[slot] = __float_as_uint(f.x[2]);
+    }
+    if (live) tiles[slot] = cnt;
   }
 }
 

@@ -35,15 +35,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
 
 // Exclusive scan of one value per thread over a 256-thread block; also returns the total.
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, uint32_t* lds4) {
@@ -291,11 +282,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // So a splat that covers thousands of tiles is spread over many lanes, and the pairs come out
 // in depth order, each splat's tiles in row-major order.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
-  const uint32_t inc = wave_incl_scan(x);
-  total = __shfl(inc, 63, 64);
-  return inc - x;
-}
 
 __global__ __launch_bounds__(kThreads) void k_keygen(
     const float* __restrict__ rec, const uint32_t* __restrict__ vval,
