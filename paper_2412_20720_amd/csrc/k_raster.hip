@@ -340,8 +340,11 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
           const float alpha = fminf(S.alpha_max, e1.y * fast_exp2(pw));
           const bool ok = in && alpha >= S.alpha_min;
           const float Tn = fmaf(-T[p], alpha, T[p]);
-          const bool stop = ok && Tn < S.T_min;
-          const bool take = ok && !stop;
+          // Tn >= T_min on the bit patterns: both are non-negative floats (alpha <= alpha_max
+          // < 1), where the integer order is the float order, so the stop is exactly the
+          // negation and follows from the take with a mask operation
+          const bool take = ok && __float_as_int(Tn) >= __float_as_int(S.T_min);
+          const bool stop = ok && !take;
           const float wgt = take ? T[p] * alpha : 0.f;
           C0[p] = fmaf(wgt, e1.z, C0[p]);
           C1[p] = fmaf(wgt, e1.w, C1[p]);
