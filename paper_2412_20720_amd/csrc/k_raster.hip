@@ -466,12 +466,13 @@ __device__ __forceinline__ void wave_reduce_rows(const float* q, float* r) {
 // Per Gaussian the wave accumulates q = [dL/du, dL/dv, S_xx, S_xy, S_yy, dL/d(opacity p_t),
 // dL/drgb] with S_.. the second moments of (dx, dy) weighted by dL/dalpha alpha; after the
 // reduction they become dL/da = -S_xx / 2, dL/db = -S_xy, dL/dc = -S_yy / 2.
-// The RGB backward is built for at least 4 waves per SIMD (at most 128 VGPRs): at 8 pixels per
-// lane that spills a few rarely used registers and still wins, 2.16 -> 2.05 ms on the
-// 300k/16-view workload, against 3 waves per SIMD unbounded.  The extra-channel variants hold
-// the payload gradients in registers and keep the compiler's choice.
+// Occupancy floors, measured on the 300k/16-view workload: the RGB backward is built for at
+// least 4 waves per SIMD (at most 128 VGPRs; at 8 pixels per lane a few rarely used registers
+// spill and it still wins, 2.16 -> 2.05 ms against 3 waves unbounded; 5 waves spill heavily,
+// 5.3 ms), the extra-channel backward for 3 (its 35-channel variant drops from 197 to 168
+// VGPRs with a few spills, 15.05 -> 13.64 ms; 3 blocks of its 48 KB of LDS fit a CU anyway).
 template <int TILE, int BATCH, int PXX, int PXY, int CX>
-__global__ __launch_bounds__(256, CX == 0 ? 4 : 1) void k_raster_bwd(RasterArgs a) {
+__global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs a) {
   constexpr int P = PXX * PXY;
   static_assert(CX % 4 == 0, "extra channels come in groups of four");
   constexpr int kGroup = CX > 0 ? P : (kSlotGroup < P ? kSlotGroup : P);
