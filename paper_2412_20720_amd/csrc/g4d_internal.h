@@ -29,9 +29,12 @@ void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_
                   hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
-// n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.
+// n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.  Keys of
+// 32 or 16 bits (the tile ids of a batch with fewer than 2^16 tiles move as 16-bit keys).
 size_t radix_scratch_bytes(int64_t n_cap);
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
+               int bits, void* scratch, hipStream_t st);
+int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
                int bits, void* scratch, hipStream_t st);
 
 // One (tile id, slot) pair per covered tile, records visited in depth order.  Tile ids are
@@ -40,10 +43,16 @@ void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const 
             int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
             int n_tiles, const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval,
             uint32_t* overflow, hipStream_t st);
+void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
+            int n_tiles, const DView* views, DSettings S, uint16_t* pkey, uint32_t* pval,
+            uint32_t* overflow, hipStream_t st);
 
 // ranges[tile] = [first, last+1) of the tile's pairs in the sorted key array (keys >= n_tiles
 // are skipped).
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
+                 int64_t n_tiles, uint2* ranges, hipStream_t st);
+void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
                  int64_t n_tiles, uint2* ranges, hipStream_t st);
 
 // *out = min(*n, cap) on the device.

@@ -597,19 +597,32 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       }
     }
     if (n_pairs > 0) {
-      {
-        Stage t(ctx, 4, st);
-        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
-               ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
-               P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pv[0]), cnt + 2, st);
-        clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
-      }
-      uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
+      // n_tiles + 1 keys: the dummy tile id n_tiles must sort too.  With at most 2^16 of them
+      // the keys move as 16-bit words (the pair buffers are sized for 32).
+      const int key_bits = bits_for(ctx->n_tiles + 1);
+      const bool key16 = key_bits <= 16;
       uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
       {
+        Stage t(ctx, 4, st);
+        if (key16)
+          keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
+                 ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
+                 P<uint16_t>(ctx->pk[0]), pv[0], cnt + 2, st);
+        else
+          keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
+                 ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
+                 P<uint32_t>(ctx->pk[0]), pv[0], cnt + 2, st);
+        clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
+      }
+      {
         Stage t(ctx, 5, st);
-        // n_tiles + 1 keys: the dummy tile id n_tiles must sort too
-        pb = radix_sort(pk, pv, cnt + 3, pair_grid, bits_for(ctx->n_tiles + 1), ctx->sort_tmp.p, st);
+        if (key16) {
+          uint16_t* pk[2] = {P<uint16_t>(ctx->pk[0]), P<uint16_t>(ctx->pk[1])};
+          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, ctx->sort_tmp.p, st);
+        } else {
+          uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
+          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, ctx->sort_tmp.p, st);
+        }
       }
       G4D_HIP(hipGetLastError());
     }
@@ -617,7 +630,10 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   ctx->pair_buf = pb;
   {
     Stage t(ctx, 6, st);
-    if (n_pairs > 0)
+    if (n_pairs > 0 && bits_for(ctx->n_tiles + 1) <= 16)
+      tile_ranges(P<uint16_t>(ctx->pk[pb]), cnt + 3, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
+                  st);
+    else if (n_pairs > 0)
       tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 3, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
                   st);
     else

@@ -175,7 +175,8 @@ void scan_generic(In in, Out out, const uint32_t* n_dev, int64_t n_cap, uint32_t
 // stable scatter.  Each wave owns a contiguous 1024-item run of its block; ranks inside a
 // wave come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ key,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ key,
                                                          const uint32_t* n_dev, int shift,
                                                          uint32_t mask, uint32_t* hist,
                                                          int nblocks) {
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
 #pragma unroll 4
   for (int r = 0; r < kRadixPerThread; ++r) {
     const int64_t i = base + r * 64 + lane;
-    if (i < n) atomicAdd(&wh[w][(key[i] >> shift) & mask], 1u);
+    if (i < n) atomicAdd(&wh[w][((uint32_t)key[i] >> shift) & mask], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kThreads)
@@ -206,14 +207,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
   return peers;
 }
 
+template <typename K>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* n_dev, int shift, uint32_t mask,
     const uint32_t* __restrict__ hist, int nblocks) {
   __shared__ uint32_t wcount[4][kRadix];
   __shared__ uint32_t bstart[kRadix];
   __shared__ uint32_t goff[kRadix];
-  __shared__ uint32_t sk[kRadixItems];
+  __shared__ K sk[kRadixItems];
   __shared__ uint32_t sv[kRadixItems];
   __shared__ uint32_t lds4[4];
   const int64_t n = *n_dev;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   for (int r = 0; r < kRadixPerThread; ++r) {
     const int64_t i = base + r * 64 + lane;
     const bool valid = i < n;
-    k[r] = valid ? kin[i] : 0u;
+    k[r] = valid ? (uint32_t)kin[i] : 0u;
     v[r] = valid ? vin[i] : 0u;
     const uint32_t d = (k[r] >> shift) & mask;
     const uint64_t peers = match_digit(d, __ballot(valid));
@@ -259,17 +261,17 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     if (i < n) {
       const uint32_t d = (k[r] >> shift) & mask;
       const uint32_t pos = bstart[d] + wcount[w][d] + rank[r];
-      sk[pos] = k[r];
+      sk[pos] = (K)k[r];
       sv[pos] = v[r];
     }
   }
   __syncthreads();
   const int cnt = (int)((n - bbase) < kRadixItems ? (n - bbase) : kRadixItems);
   for (int p = threadIdx.x; p < cnt; p += kThreads) {
-    const uint32_t kk = sk[p];
+    const uint32_t kk = (uint32_t)sk[p];
     const uint32_t d = (kk >> shift) & mask;
     const uint32_t dst = goff[d] + ((uint32_t)p - bstart[d]);
-    kout[dst] = kk;
+    kout[dst] = (K)kk;
     vout[dst] = sv[p];
   }
 }
@@ -283,11 +285,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
 // in depth order, each splat's tiles in row-major order.
 // ------------------------------------------------------------------------------------------
 
+template <typename K>
 __global__ __launch_bounds__(kThreads) void k_keygen(
     const float* __restrict__ rec, const uint32_t* __restrict__ vval,
     const uint32_t* __restrict__ voff, const uint32_t* n_vis_dev, const uint32_t* n_pairs_dev,
     int64_t pair_cap, int n_per_view, int n_tiles, const DView* __restrict__ views, DSettings S,
-    uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* overflow) {
+    K* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* overflow) {
   __shared__ uint32_t s_rows[4][65];
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64];
@@ -376,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
       }
       const uint32_t dst = cursor + e;
       if (dst < off_end && (int64_t)dst < pair_cap) {
-        pkey[dst] = s_key0[w][lo] + (e - s_start[w][lo]);
+        pkey[dst] = (K)(s_key0[w][lo] + (e - s_start[w][lo]));
         pval[dst] = s_val[w][lo];
       } else {
         *overflow = 1u;
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
     if (lane == 0) *overflow = 2u;
     for (uint32_t dst = cursor + lane; dst < off_end; dst += 64)
       if ((int64_t)dst < pair_cap) {
-        pkey[dst] = (uint32_t)n_tiles;
+        pkey[dst] = (K)n_tiles;
         pval[dst] = 0u;
       }
   }
@@ -402,23 +405,29 @@ __global__ __launch_bounds__(kThreads) void k_keygen(
 
 // Tile boundaries in the sorted keys, four keys per thread (one 16-byte load; the neighbours
 // on either side come from the caches).
-__global__ void k_ranges(const uint32_t* __restrict__ key, const uint32_t* n_dev, int64_t cap,
+// Four keys per thread (one 4-key vector load), compared with their neighbours.
+template <typename K> struct Key4;
+template <> struct Key4<uint32_t> { using T = uint4; };
+template <> struct Key4<uint16_t> { using T = ushort4; };
+
+template <typename K>
+__global__ void k_ranges(const K* __restrict__ key, const uint32_t* n_dev, int64_t cap,
                          int64_t n_tiles, uint2* ranges) {
   const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
   const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   if (i0 >= n) return;
   uint32_t k[6];  // key[i0 - 1 .. i0 + 4]
   if (i0 + 4 <= n) {
-    const uint4 q = *reinterpret_cast<const uint4*>(key + i0);
+    const typename Key4<K>::T q = *reinterpret_cast<const typename Key4<K>::T*>(key + i0);
     k[1] = q.x;
     k[2] = q.y;
     k[3] = q.z;
     k[4] = q.w;
   } else {
-    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? key[i0 + j] : 0u;
+    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? (uint32_t)key[i0 + j] : 0u;
   }
-  k[0] = i0 > 0 ? key[i0 - 1] : 0u;
-  k[5] = i0 + 4 < n ? key[i0 + 4] : 0u;
+  k[0] = i0 > 0 ? (uint32_t)key[i0 - 1] : 0u;
+  k[5] = i0 + 4 < n ? (uint32_t)key[i0 + 4] : 0u;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t i = i0 + j;
@@ -482,7 +491,8 @@ size_t radix_scratch_bytes(int64_t n_cap) {
   return sizeof(uint32_t) * (size_t)(table + 16) + scan_scratch_bytes(table);
 }
 
-int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+template <typename K>
+int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
                void* scratch, hipStream_t st) {
   const int64_t blocks = (n_cap + kRadixItems - 1) / kRadixItems;
   if (blocks == 0 || bits <= 0) return 0;
@@ -492,10 +502,10 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_
   for (int shift = 0; shift < bits; shift += kRadixBits) {
     const int nb = (bits - shift) < kRadixBits ? (bits - shift) : kRadixBits;
     const uint32_t mask = (1u << nb) - 1u;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur], n_dev,
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur], n_dev,
                        shift, mask, hist, (int)blocks);
     scan_generic(InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr, scan_tmp, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur],
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur],
                        val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
                        (int)blocks);
     cur ^= 1;
@@ -503,24 +513,63 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_
   return cur;
 }
 
+int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+               void* scratch, hipStream_t st) {
+  return radix_sort_t<uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
+}
+
+int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+               void* scratch, hipStream_t st) {
+  return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, scratch, st);
+}
+
+template <typename K>
+void keygen_t(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
+              int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
+              int n_tiles, const DView* views, DSettings S, K* pkey, uint32_t* pval,
+              uint32_t* overflow, hipStream_t st) {
+  const int64_t waves = (n_vis_cap + 63) / 64;
+  const int64_t blocks = (waves + 3) / 4;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_keygen<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, rec, vval, voff,
+                     n_vis, n_pairs, pair_cap, n_slots_per_view, n_tiles, views, S, pkey, pval,
+                     overflow);
+}
+
 void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
             int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
             int n_tiles, const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval,
             uint32_t* overflow, hipStream_t st) {
-  const int64_t waves = (n_vis_cap + 63) / 64;
-  const int64_t blocks = (waves + 3) / 4;
+  keygen_t<uint32_t>(rec, vval, voff, n_vis, n_vis_cap, n_pairs, pair_cap, n_slots_per_view,
+                     n_tiles, views, S, pkey, pval, overflow, st);
+}
+
+void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
+            int n_tiles, const DView* views, DSettings S, uint16_t* pkey, uint32_t* pval,
+            uint32_t* overflow, hipStream_t st) {
+  keygen_t<uint16_t>(rec, vval, voff, n_vis, n_vis_cap, n_pairs, pair_cap, n_slots_per_view,
+                     n_tiles, views, S, pkey, pval, overflow, st);
+}
+
+template <typename K>
+void tile_ranges_t(const K* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
+                   uint2* ranges, hipStream_t st) {
+  fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
+  const int64_t blocks = (pair_cap + 1023) / 1024;  // four keys per thread
   if (blocks == 0) return;
-  hipLaunchKernelGGL(k_keygen, dim3((unsigned)blocks), dim3(kThreads), 0, st, rec, vval, voff, n_vis,
-                     n_pairs, pair_cap, n_slots_per_view, n_tiles, views, S, pkey, pval, overflow);
+  hipLaunchKernelGGL(k_ranges<K>, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs,
+                     pair_cap, n_tiles, ranges);
 }
 
 void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
                  uint2* ranges, hipStream_t st) {
-  fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
-  const int64_t blocks = (pair_cap + 1023) / 1024;  // four keys per thread
-  if (blocks == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs, pair_cap,
-                     n_tiles, ranges);
+  tile_ranges_t<uint32_t>(pkey, n_pairs, pair_cap, n_tiles, ranges, st);
+}
+
+void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
+                 uint2* ranges, hipStream_t st) {
+  tile_ranges_t<uint16_t>(pkey, n_pairs, pair_cap, n_tiles, ranges, st);
 }
 
 void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st) {

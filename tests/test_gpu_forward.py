@@ -265,3 +265,16 @@ def test_w1_pair_counts_match_oracle(renderer, w1):
     assert np.all(evals[clean] <= ref["n_evals"][clean])
     assert np.all(evals <= ref["n_evals"] + 4 * marks)
     assert evals.sum() < 0.9 * ref["n_evals"].sum()  # the reach drops pixels the cutoff keeps
+
+
+def test_wide_tile_ids_match_narrow(renderer, w1):
+    # Four 1352x1014 views at 8-pixel tiles make 85,852 tiles: the tile ids exceed 16 bits and
+    # sort as 32-bit keys; at 32-pixel tiles (5,504 tiles) they sort as 16-bit keys.  The
+    # decomposition never changes the image.
+    import torch
+    views = [w1.views[0]] * 4
+    log("w1 x4 views, tile 8 (32-bit keys) against tile 32 (16-bit keys)")
+    wide = GpuRun(renderer, w1, views=views, tile_size=8).forward()
+    assert renderer.stats()["n_tiles"] == 4 * 169 * 127
+    narrow = GpuRun(renderer, w1, views=views, tile_size=32).forward()
+    assert torch.equal(wide.rgb, narrow.rgb) and torch.equal(wide.T, narrow.T)
