@@ -62,10 +62,17 @@ struct InFlag {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i] > 0u ? 1u : 0u; }
 };
-struct InGather {
+// Gathers cnt[idx[i]] and keeps it at keep[i], so that a second pass over the same items
+// reads them contiguously instead of gathering again (each gather costs a cache line).
+struct InGatherKeep {
   const uint32_t* cnt;
   const uint32_t* idx;
-  __device__ uint32_t operator()(int64_t i) const { return cnt[idx[i]]; }
+  uint32_t* keep;
+  __device__ uint32_t operator()(int64_t i) const {
+    const uint32_t c = cnt[idx[i]];
+    keep[i] = c;
+    return c;
+  }
 };
 struct InPlain {
   const uint32_t* p;
@@ -99,11 +106,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(In in, const uint32_t*
   const int64_t base = (int64_t)blockIdx.x * kItems;
   uint32_t acc = 0;
   if (base < n) {
-#pragma unroll 4
+    // all of the thread's loads are issued before any is used (a gathered input costs two
+    // dependent memory round trips per block, not two per row)
+    uint32_t v[kPerThread];
+#pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
       const int64_t i = base + r * kThreads + threadIdx.x;
-      if (i < n) acc += in(i);
+      v[r] = (i < n) ? in(i) : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) acc += v[r];
   }
   uint32_t total;
   block_excl_scan(acc, total, lds);
@@ -133,41 +145,82 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* sums, int count, u
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
-template <class In, class Out>
+// Row r of a block holds items base + r * kThreads + t.  Every row is loaded first, each is
+// scanned within its wave, and one barrier publishes the per-(row, wave) totals from which
+// each item's block prefix follows.  With kOwnPrefix the block adds up the totals of the
+// blocks before it (`sums` as the reduce pass left them) instead of reading a prefix scanned
+// by k_scan_sums, and the block holding the last item writes the grand total.
+template <class In, class Out, bool kOwnPrefix>
 __global__ __launch_bounds__(kThreads) void k_scan_apply(In in, Out out, const uint32_t* n_dev,
-                                                         int64_t n_host, const uint32_t* sums) {
-  __shared__ uint32_t lds[4];
+                                                         int64_t n_host, const uint32_t* sums,
+                                                         uint32_t* total) {
+  __shared__ uint4 lds[kPerThread];  // [row] -> totals of the 4 waves
+  __shared__ uint32_t lds_pre[4];
   const int64_t n = count_of(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kItems;
-  if (base >= n) return;
-  uint32_t carry = sums[blockIdx.x];
+  if (base >= n) {
+    if (kOwnPrefix && blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0u;
+    return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t v[kPerThread], inc[kPerThread];
+#pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t i = base + r * kThreads + threadIdx.x;
-    const uint32_t v = (i < n) ? in(i) : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(v, total, lds);
-    if (i < n) out(i, carry + ex, v);
-    carry += total;
-    if (base + (r + 1) * kThreads >= n) break;
+    v[r] = (i < n) ? in(i) : 0u;
   }
+  if (kOwnPrefix) {
+    uint32_t part = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kThreads) part += sums[k];
+    part = wave_incl_scan(part);
+    if (lane == 63) lds_pre[w] = part;
+  }
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    inc[r] = wave_incl_scan(v[r]);
+    if (lane == 63) reinterpret_cast<uint32_t*>(&lds[r])[w] = inc[r];
+  }
+  __syncthreads();
+  uint32_t carry =
+      kOwnPrefix ? lds_pre[0] + lds_pre[1] + lds_pre[2] + lds_pre[3] : sums[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const uint4 t = lds[r];
+    const uint32_t pre = (w > 0 ? t.x : 0u) + (w > 1 ? t.y : 0u) + (w > 2 ? t.z : 0u);
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < n) out(i, carry + pre + inc[r] - v[r], v[r]);
+    carry += t.x + t.y + t.z + t.w;
+  }
+  if (kOwnPrefix && total && threadIdx.x == 0 && base + kItems >= n) *total = carry;
 }
+
+// Up to this many blocks each apply block sums the totals before it (at most 8 KB of reads
+// from L2 per block), which saves the one-block k_scan_sums launch.
+constexpr int64_t kOwnPrefixBlocks = 2048;
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v);
 
-template <class In, class Out>
-void scan_generic(In in, Out out, const uint32_t* n_dev, int64_t n_cap, uint32_t* total,
-                  void* scratch, hipStream_t st) {
+// The reduce pass reads items through `in_sum`, the apply pass through `in`; both must yield
+// the same values.
+template <class InSum, class In, class Out>
+void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n_cap,
+                  uint32_t* total, void* scratch, hipStream_t st) {
   const int64_t blocks = (n_cap + kItems - 1) / kItems;
   if (blocks == 0) {
     if (total) fill_u32(total, 1, 0u, st);
     return;
   }
   uint32_t* sums = static_cast<uint32_t*>(scratch);
-  hipLaunchKernelGGL(k_scan_reduce<In>, dim3((unsigned)blocks), dim3(kThreads), 0, st, in, n_dev,
-                     n_cap, sums);
+  hipLaunchKernelGGL(k_scan_reduce<InSum>, dim3((unsigned)blocks), dim3(kThreads), 0, st, in_sum,
+                     n_dev, n_cap, sums);
+  if (blocks <= kOwnPrefixBlocks) {
+    hipLaunchKernelGGL((k_scan_apply<In, Out, true>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                       st, in, out, n_dev, n_cap, sums, total);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, (int)blocks, total);
-  hipLaunchKernelGGL((k_scan_apply<In, Out>), dim3((unsigned)blocks), dim3(kThreads), 0, st, in,
-                     out, n_dev, n_cap, sums);
+  hipLaunchKernelGGL((k_scan_apply<In, Out, false>), dim3((unsigned)blocks), dim3(kThreads), 0,
+                     st, in, out, n_dev, n_cap, sums, nullptr);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -475,14 +528,16 @@ size_t scan_scratch_bytes(int64_t n) {
 void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
                      uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
                      hipStream_t st) {
-  scan_generic(InFlag{tiles}, OutCompact{dkey, out_key, out_val}, nullptr, n_slots, n_out, scratch,
-               st);
+  scan_generic(InFlag{tiles}, InFlag{tiles}, OutCompact{dkey, out_key, out_val}, nullptr, n_slots,
+               n_out, scratch, st);
 }
 
 void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_dev,
                   int64_t n_cap, uint32_t* offsets, uint32_t* total, void* scratch,
                   hipStream_t st) {
-  scan_generic(InGather{tiles, val}, OutStore{offsets}, n_dev, n_cap, total, scratch, st);
+  // the reduce pass leaves the gathered counts in `offsets`; the apply pass scans them in place
+  scan_generic(InGatherKeep{tiles, val, offsets}, InPlain{offsets}, OutStore{offsets}, n_dev, n_cap,
+               total, scratch, st);
 }
 
 size_t radix_scratch_bytes(int64_t n_cap) {
@@ -504,7 +559,8 @@ int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_c
     const uint32_t mask = (1u << nb) - 1u;
     hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur], n_dev,
                        shift, mask, hist, (int)blocks);
-    scan_generic(InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr, scan_tmp, st);
+    scan_generic(InPlain{hist}, InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr,
+                 scan_tmp, st);
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur],
                        val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
                        (int)blocks);
