@@ -79,7 +79,7 @@ void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs
                            float* mean4, float* scale4, float* rot_l, float* rot_r,
                            float* opacity, float* sh, hipStream_t st);
 void preprocess_backward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
-                         const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                         const uint32_t* tiles, float* grad2d, const GradPtrs& out,
                          hipStream_t st);
 
 struct RasterArgs {

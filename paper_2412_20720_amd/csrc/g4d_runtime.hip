@@ -58,6 +58,10 @@ struct g4d_ctx {
   std::vector<DView> uploaded_views;
   void* uploaded_to = nullptr;
   int64_t pair_cap = 0;
+  // the whole grad2d allocation holds zeros: the last backward ran to its preprocess adjoint,
+  // which zeroes every slot the raster adjoint accumulated into (false after a reallocation or
+  // an interrupted backward; the next backward then clears the whole allocation)
+  bool grad2d_zero = false;
   // state left by the last forward
   bool saved = false;
   SavedKey key;
@@ -740,11 +744,14 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   if (slots == 0) return G4D_OK;
   const g4d_settings s_run = run_settings(s, ch);
   const DSettings DS = device_settings(&s_run);
+  const size_t grad2d_cap = ctx->grad2d.cap;
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
   {
     Stage t(ctx, 8, st);
-    fill_u32(P<uint32_t>(ctx->grad2d), kGrad2d * slots, 0u, st);
+    if (!ctx->grad2d_zero || ctx->grad2d.cap != grad2d_cap)
+      fill_u32(P<uint32_t>(ctx->grad2d), (int64_t)(ctx->grad2d.cap / sizeof(uint32_t)), 0u, st);
   }
+  ctx->grad2d_zero = false;
   if (D > 0) {
     if ((r = ensure(ctx, ctx->dfn, sizeof(float) * (size_t)g->n * D, 1.1)) != G4D_OK) return r;
     fill_u32(P<uint32_t>(ctx->dfn), (int64_t)g->n * D, 0u, st);
@@ -785,7 +792,9 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
     Stage t(ctx, 10, st);
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
                         P<float>(ctx->grad2d), gp, st);
+    G4D_HIP(hipGetLastError());
   }
+  ctx->grad2d_zero = true;
   if (D > 0)
     feature_backward(g->n, D, ch->features, ch->gate, P<float>(ctx->fn), P<float>(ctx->fnorm),
                      P<float>(ctx->dfn), d_features, d_gate, st);

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, const uint32_t* __restrict__ tiles,
-    const float* __restrict__ grad2d, GradPtrs out) {
+    float* __restrict__ grad2d, GradPtrs out) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n) return;
@@ -165,8 +165,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   for (int v = 0; v < n_views; ++v) {
     const size_t slot = (size_t)v * n + gi;
     if (tiles[slot] == 0u) continue;
-    const float4* gp = reinterpret_cast<const float4*>(grad2d + slot * kGrad2d);
+    float4* gp = reinterpret_cast<float4*>(grad2d + slot * kGrad2d);
     const float4 q0 = gp[0], q1 = gp[1], q2 = gp[2];
+    // the raster adjoint accumulates only into listed slots, so zeroing each listed slot once
+    // it is read keeps the whole array zero for the next backward
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    gp[0] = z;
+    gp[1] = z;
+    gp[2] = z;
     dens += sqrtf(fmaf(q0.x, q0.x, q0.y * q0.y));
     ++nvis;
     const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
@@ -261,7 +267,7 @@ void dispatch_decode_t(int n, int dt, const CompactPtrs& cp, float* mean4, float
 
 template <int DS, int DT>
 void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                const uint32_t* tiles, const float* grad2d, const GradPtrs& out, hipStream_t st) {
+                const uint32_t* tiles, float* grad2d, const GradPtrs& out, hipStream_t st) {
   const int blocks = (gp.n + 255) / 256;
   hipLaunchKernelGGL((k_preprocess_bwd<DS, DT>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
                      reinterpret_cast<const float4*>(gp.mean4),
@@ -283,7 +289,7 @@ void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 
 template <int DS>
 void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S,
-                    const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                    const uint32_t* tiles, float* grad2d, const GradPtrs& out,
                     hipStream_t st) {
   switch (gp.t_degree) {
     case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, grad2d, out, st); break;
@@ -318,7 +324,7 @@ void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs
 }
 
 void preprocess_backward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                         const uint32_t* tiles, const float* grad2d, const GradPtrs& out,
+                         const uint32_t* tiles, float* grad2d, const GradPtrs& out,
                          hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {

@@ -150,3 +150,30 @@ def test_backward_block_shape_errors(renderer):
         s = B.default_settings(time_period=sc.time_period, tile_size=tile, bwd_px_per_lane=bwd_px)
         with pytest.raises(B.G4DError, match="EINVAL"):
             renderer.forward(run.g, run.views, s, run.rgb, run.T)
+
+
+def test_backward_state_across_calls(renderer):
+    # The per-slot screen-space accumulators of the raster adjoint start every backward at
+    # zero: the full clear runs only after a reallocation, and otherwise the preprocess adjoint
+    # zeroes each slot it reads.  On one context: a second backward of the same forward equals
+    # the first, and a larger scene whose slots still fit the first allocation (10% headroom)
+    # equals the same scene on a fresh context.
+    from paper_2412_20720_amd.frontend import Renderer
+    sc = scenes.make_workload(0)
+    small = scenes.subset(sc, np.arange(sc.n - 150))
+    dl = scenes.make_dl_dimage(sc)
+    run = GpuRun(renderer, small).forward()
+    g1 = run.backward(dl)
+    g2 = run.backward(dl)
+    errs = parity.grad_rel_errors(g2, g1)
+    log(f"second backward of one forward: rel diff {errs}")
+    assert all(e <= 1e-5 for e in errs.values()), errs
+    g_same = GpuRun(renderer, sc).forward().backward(dl)
+    fresh = Renderer(0)
+    try:
+        g_fresh = GpuRun(fresh, sc).forward().backward(dl)
+    finally:
+        fresh.close()
+    errs = parity.grad_rel_errors(g_same, g_fresh)
+    log(f"larger scene on the used context vs a fresh one: rel diff {errs}")
+    assert all(e <= 1e-5 for e in errs.values()), errs
