@@ -20,9 +20,11 @@ constexpr int kPerThread = kItems / kThreads;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 // Items per workgroup of a radix pass (a multiple of 4 x 64).  Measured on the 300k/16-view
-// workload (35.7M pairs, 14-bit tile ids): 4096 sorts the tiles in 0.632 ms, 2048 in 0.649,
-// 8192 in 0.797 (two workgroups per CU for its 70 KB of LDS); splitting the 14 bits evenly
-// (7 + 7) instead of 8 + 6 gains nothing (0.636).
+// workload with 32-bit tile keys (35.7M pairs, 14-bit tile ids): 4096 sorts the tiles in
+// 0.632 ms, 2048 in 0.649, 8192 in 0.797 (two workgroups per CU for its 70 KB of LDS);
+// splitting the 14 bits evenly (7 + 7) instead of 8 + 6 gains nothing (0.636).  With 16-bit
+// keys (26.1M pairs, 15-bit ids): 4096 in 0.398 ms, 2048 in 0.422, 8192 in 0.513; the depth
+// sort (1.8M slots, 32-bit keys) takes 0.149, 0.143 and 0.201 ms.
 #ifndef G4D_RADIX_ITEMS
 #define G4D_RADIX_ITEMS 4096
 #endif
