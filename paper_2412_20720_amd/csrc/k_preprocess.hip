@@ -162,25 +162,48 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   float gop = 0.f;
   float dens = 0.f;  // sum over listed views of |dL/d(u, v)|
   int nvis = 0;
-  for (int v = 0; v < n_views; ++v) {
-    const size_t slot = (size_t)v * n + gi;
-    if (tiles[slot] == 0u) continue;
-    float4* gp = reinterpret_cast<float4*>(grad2d + slot * kGrad2d);
-    const float4 q0 = gp[0], q1 = gp[1], q2 = gp[2];
-    // the raster adjoint accumulates only into listed slots, so zeroing each listed slot once
-    // it is read keeps the whole array zero for the next backward
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    gp[0] = z;
-    gp[1] = z;
-    gp[2] = z;
-    dens += sqrtf(fmaf(q0.x, q0.x, q0.y * q0.y));
-    ++nvis;
-    const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
-    const DView& V = views[v];
-    ViewFwd f;
-    view_forward<false>(g, mean, V, S, f);
-    color_forward<DS, DT>(shc, S, f);
-    view_backward<DS, DT>(g, mean, op, shc, V, S, f, q, gM, gmean, gop, gsh);
+  // Views in chunks of 32: the chunk's listing flags are loaded together, and each view's
+  // gradient slot is loaded one view ahead, so that its latency overlaps the current view's
+  // arithmetic (one wave per SIMD leaves nothing else to hide it).
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int v0 = 0; v0 < n_views; v0 += 32) {
+    const int nv = n_views - v0 < 32 ? n_views - v0 : 32;
+    uint32_t listed = 0;
+    for (int j = 0; j < nv; ++j)
+      listed |= (tiles[(size_t)(v0 + j) * n + gi] != 0u ? 1u : 0u) << j;
+    float4 p0 = z, p1 = z, p2 = z;
+    if (listed & 1u) {
+      const float4* gp = reinterpret_cast<const float4*>(grad2d + ((size_t)v0 * n + gi) * kGrad2d);
+      p0 = gp[0];
+      p1 = gp[1];
+      p2 = gp[2];
+    }
+    for (int j = 0; j < nv; ++j) {
+      const float4 q0 = p0, q1 = p1, q2 = p2;
+      if (j + 1 < nv && ((listed >> (j + 1)) & 1u)) {
+        const float4* gp =
+            reinterpret_cast<const float4*>(grad2d + ((size_t)(v0 + j + 1) * n + gi) * kGrad2d);
+        p0 = gp[0];
+        p1 = gp[1];
+        p2 = gp[2];
+      }
+      if (!((listed >> j) & 1u)) continue;
+      const int v = v0 + j;
+      // the raster adjoint accumulates only into listed slots, so zeroing each listed slot once
+      // it is read keeps the whole array zero for the next backward
+      float4* gz = reinterpret_cast<float4*>(grad2d + ((size_t)v * n + gi) * kGrad2d);
+      gz[0] = z;
+      gz[1] = z;
+      gz[2] = z;
+      dens += sqrtf(fmaf(q0.x, q0.x, q0.y * q0.y));
+      ++nvis;
+      const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
+      const DView& V = views[v];
+      ViewFwd f;
+      view_forward<false>(g, mean, V, S, f);
+      color_forward<DS, DT>(shc, S, f);
+      view_backward<DS, DT>(g, mean, op, shc, V, S, f, q, gM, gmean, gop, gsh);
+    }
   }
   float gs[4], gql[4], gqr[4];
   geom_backward(g, sc, gM, gs, gql, gqr);
