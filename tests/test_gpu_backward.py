@@ -177,3 +177,33 @@ def test_backward_state_across_calls(renderer):
     errs = parity.grad_rel_errors(g_same, g_fresh)
     log(f"larger scene on the used context vs a fresh one: rel diff {errs}")
     assert all(e <= 1e-5 for e in errs.values()), errs
+
+
+def test_more_than_32_views(renderer):
+    # The preprocess adjoint walks the views in chunks of 32 (listing flags loaded per chunk,
+    # gradient slots one view ahead): 34 small views of one call give the sum of the 34
+    # one-view backwards, and match the oracle's summed gradients.
+    sc = scenes.make_workload(0)
+    rng = np.random.default_rng(17)
+    views = []
+    for j in range(34):
+        a = 2.0 * np.pi * j / 34
+        eye = (3.0 * np.sin(a), 0.4 * np.cos(3 * a), 3.0 * np.cos(a))
+        views.append(scenes.pinhole(40, 32, 50.0, scenes.look_at(eye, (0, 0, 0)),
+                                    float(rng.uniform(0.0, 1.0))))
+    dls = [rng.normal(size=(3, 32, 40)).astype(np.float32) for _ in views]
+    g_all = GpuRun(renderer, sc, views=views).forward().backward(dls)
+    g_sum = None
+    for v, d in zip(views, dls):
+        g = GpuRun(renderer, sc, views=[v]).forward().backward([d])
+        g_sum = g if g_sum is None else {k: g_sum[k] + g[k] for k in g}
+    errs = parity.grad_rel_errors(g_all, g_sum)
+    log(f"34 views in one call vs 34 calls: rel diff {errs}")
+    assert all(e <= 1e-5 for e in errs.values()), errs
+    ref = None
+    for v, d in zip(views, dls):
+        with oracle_frame(sc, v) as fr:
+            ref = fr.backward(d, ref)
+    errs = parity.grad_rel_errors(g_all, ref)
+    log(f"34 views vs oracle: rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
