@@ -140,6 +140,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # The timed steps record events around the two raster kernels only (the roofline's
+    # kernels; each recorded stage idles the GPU briefly between kernels).
+    r.profile_mask(["raster_fwd", "raster_bwd"])
     r.profile(True, collect=True, reset=True)   # start stage timing from zero
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -151,6 +154,14 @@ def main():
     r.sync()
     value = npix / dt / 1e6
     log(f"bench: batched {dt * 1e3:.3f} ms/step, {value:.1f} Mpix/s")
+    timed_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
+    # Every stage, from a separate (untimed) pass of the same step.
+    r.profile_mask(None)
+    r.profile(True, collect=True, reset=True)
+    for _ in range(max(1, min(args.steps, 5))):
+        step()
+    stages = r.profile(False, collect=True, reset=True)
+    r.sync()
     stage_ms = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
     for k, v in stage_ms.items():
         log(f"  {k:15s} {v:8.3f} ms/launch")
@@ -210,17 +221,17 @@ def main():
     compact = compact_forward(r, views, settings, sc, args, npix)
 
     # Roofline of the dominant kernel (largest time per step), from the live HIP events.
-    dom = max(("raster_fwd", "raster_bwd"), key=lambda k: stage_ms.get(k, 0.0))
+    dom = max(("raster_fwd", "raster_bwd"), key=lambda k: timed_ms.get(k, 0.0))
     per_comp = BWD_FLOPS_PER_COMPOSITED if dom == "raster_bwd" else FWD_FLOPS_PER_COMPOSITED
     flops = FLOPS_PER_EVALUATED * evals + per_comp * contrib
-    achieved = flops / (stage_ms[dom] * 1e-3)
+    achieved = flops / (timed_ms[dom] * 1e-3)
     traffic = profiled_traffic(sc.name, settings) if dom == "raster_bwd" else None
     roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
                     units={"evaluated_pairs": evals, "composited_pairs": contrib},
                     flops_per_unit={"evaluated_pair": FLOPS_PER_EVALUATED,
                                     "composited_pair_extra": per_comp},
-                    flops_per_launch=flops, ms_per_launch=stage_ms[dom])
+                    flops_per_launch=flops, ms_per_launch=timed_ms[dom])
 
     # Whole-path bound from the algorithmic work alone (forward + backward raster flops at the
     # FP32 VALU peak).
@@ -287,6 +298,7 @@ def channel_step(r, g, views, settings, sc, p, dL, args, npix):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    r.profile_mask(["raster_fwd", "raster_bwd"])
     r.profile(True, collect=True, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -295,6 +307,7 @@ def channel_step(r, g, views, settings, sc, p, dL, args, npix):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     stages = r.profile(False, collect=True, reset=True)
+    r.profile_mask(None)
     r.sync()
     st = {k: v[0] / max(1, v[1]) for k, v in stages.items() if v[1] > 0}
     log(f"bench: channels D={D} + depth + flow: {dt * 1e3:.3f} ms/step, {npix / dt / 1e6:.1f} Mpix/s "
@@ -395,6 +408,7 @@ def compact_forward(r, views, settings, sc, args, npix):
         for _ in range(args.warmup):
             fwd()
         torch.cuda.synchronize()
+        r.profile_mask(["preprocess"])
         r.profile(True, collect=True, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -403,6 +417,7 @@ def compact_forward(r, views, settings, sc, args, npix):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         st = r.profile(False, collect=True, reset=True)
+        r.profile_mask(None)
         out[name] = dict(ms=dt * 1e3, mpix_s=npix / dt / 1e6,
                          preprocess_ms=st["preprocess"][0] / max(1, st["preprocess"][1]))
     r.sync()

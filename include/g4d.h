@@ -340,6 +340,12 @@ g4d_status g4d_autotune(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *vi
  * clears the totals. */
 g4d_status g4d_profile(g4d_ctx *ctx, int enable, double *ms, int64_t *launches, int reset);
 
+/* Stages that g4d_profile records while enabled: bit s for stage s (the default, set at
+ * g4d_create, is every stage).  Each recorded stage adds two HIP event records to the stream,
+ * and each leaves the GPU idle for some microseconds between kernels, so timed work records
+ * only the stages it reports.  Bits of nonexistent stages are ignored. */
+g4d_status g4d_profile_mask(g4d_ctx *ctx, uint32_t stage_mask);
+
 /* Name of a stage index of g4d_profile ("" if out of range). */
 const char *g4d_stage_name(int stage);
 

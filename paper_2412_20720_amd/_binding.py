@@ -21,7 +21,7 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_get_stats", "g4d_eval_counters", "g4d_autotune", "g4d_profile",
             "g4d_stage_name", "g4d_render_step", "g4d_render_channels_forward",
             "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward",
-            "g4d_decode_compact", "g4d_render_compact_forward"]
+            "g4d_decode_compact", "g4d_render_compact_forward", "g4d_profile_mask"]
 G4D_STEP_GRAPH = 1
 G4D_NUM_STAGES = 11
 G4D_MAX_CHANNELS = 36
@@ -127,6 +127,7 @@ def lib() -> C.CDLL:
     L.g4d_render_compact_forward.argtypes = [vp, C.POINTER(g4d_compact), C.POINTER(g4d_view), i32,
                                              C.POINTER(g4d_settings), vp, vp, vp]
     L.g4d_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+    L.g4d_profile_mask.argtypes = [vp, C.c_uint32]
     L.g4d_stage_name.argtypes = [C.c_int]
     L.g4d_stage_name.restype = C.c_char_p
     for name in EXPORTED:

@@ -69,8 +69,9 @@ struct g4d_ctx {
   int64_t n_tiles = 0, n_pixels = 0;
   g4d_stats stats{};
   bool count_evals = false;
-  // stage profiling
+  // stage profiling (stages whose bit is set in stage_mask)
   bool profiling = false;
+  uint32_t stage_mask = 0xFFFFFFFFu;
   std::vector<hipEvent_t> ev_free;
   struct Interval { int stage; hipEvent_t a, b; };
   std::vector<Interval> pending;
@@ -153,7 +154,8 @@ struct Stage {
   hipStream_t st;
   hipEvent_t a = nullptr;
   Stage(g4d_ctx* c_, int s_, hipStream_t st_) : c(c_), stage(s_), st(st_) {
-    if (c->profiling && !c->capturing && (a = take_event(c))) (void)hipEventRecord(a, st);
+    if (c->profiling && !c->capturing && ((c->stage_mask >> s_) & 1u) && (a = take_event(c)))
+      (void)hipEventRecord(a, st);
   }
   ~Stage() {
     if (!a) return;
@@ -1112,6 +1114,12 @@ g4d_status g4d_autotune(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
   s->px_per_lane = best.px;
   s->bwd_px_per_lane = best.bwd_px;
   if (best_ms) *best_ms = best.ms;
+  return G4D_OK;
+}
+
+g4d_status g4d_profile_mask(g4d_ctx* ctx, uint32_t stage_mask) {
+  if (!ctx) return G4D_EINVAL;
+  ctx->stage_mask = stage_mask;
   return G4D_OK;
 }
 

@@ -245,6 +245,17 @@ class Renderer:
                 self._ctx)
         return ms.value
 
+    def profile_mask(self, stages=None) -> None:
+        """Record only the named stages while profiling (None: every stage)."""
+        if stages is None:
+            mask = 0xFFFFFFFF
+        else:
+            names = [B.lib().g4d_stage_name(k).decode() for k in range(B.G4D_NUM_STAGES)]
+            mask = 0
+            for s in stages:
+                mask |= 1 << names.index(s)
+        B.check(B.lib().g4d_profile_mask(self._ctx, mask), self._ctx)
+
     def profile(self, enable: bool, collect: bool = True, reset: bool = True):
         """Stage timing (HIP events on the call's stream): returns {stage: (ms, launches)}."""
         ms = (C.c_double * B.G4D_NUM_STAGES)()

@@ -278,3 +278,25 @@ def test_wide_tile_ids_match_narrow(renderer, w1):
     assert renderer.stats()["n_tiles"] == 4 * 169 * 127
     narrow = GpuRun(renderer, w1, views=views, tile_size=32).forward()
     assert torch.equal(wide.rgb, narrow.rgb) and torch.equal(wide.T, narrow.T)
+
+
+def test_stage_profile_and_mask(renderer, w0):
+    # Stage timing records every stage by default; with a mask, only the named stages.
+    dl = scenes.make_dl_dimage(w0)
+    run = GpuRun(renderer, w0)
+    renderer.profile_mask(None)
+    renderer.profile(True, collect=True, reset=True)
+    run.forward().backward(dl)
+    every = renderer.profile(False, collect=True, reset=True)
+    log(f"every stage: {every}")
+    assert all(n >= 1 for _, n in every.values()), every
+    renderer.profile_mask(["raster_bwd"])
+    try:
+        renderer.profile(True, collect=True, reset=True)
+        run.forward().backward(dl)
+        only = renderer.profile(False, collect=True, reset=True)
+    finally:
+        renderer.profile_mask(None)
+    log(f"raster_bwd only: {only}")
+    assert only["raster_bwd"][1] == 1 and only["raster_bwd"][0] > 0
+    assert all(n == 0 for k, (_, n) in only.items() if k != "raster_bwd"), only
