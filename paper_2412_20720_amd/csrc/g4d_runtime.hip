@@ -53,6 +53,7 @@ struct g4d_ctx {
   DView* h_views = nullptr;        // pinned staging
   int32_t* h_tile_base = nullptr;  // pinned staging
   hipEvent_t staging_done = nullptr;
+  hipEvent_t counts_ready = nullptr;  // the forward's visible and pair counts reached the host
   bool staging_pending = false;
   // the view table now on the device (skips the upload when a call repeats it)
   std::vector<DView> uploaded_views;
@@ -442,7 +443,8 @@ g4d_status g4d_create(g4d_ctx** out, int device) {
       hipHostMalloc((void**)&ctx->h_counters, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_views, sizeof(DView) * G4D_MAX_VIEWS, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_tile_base, sizeof(int32_t) * (G4D_MAX_VIEWS + 1), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->counts_ready, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     g4d_destroy(ctx);
     return G4D_EHIP;
@@ -471,6 +473,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->h_views) (void)hipHostFree(ctx->h_views);
   if (ctx->h_tile_base) (void)hipHostFree(ctx->h_tile_base);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  if (ctx->counts_ready) (void)hipEventDestroy(ctx->counts_ready);
   for (auto& iv : ctx->pending) {
     (void)hipEventDestroy(iv.a);
     (void)hipEventDestroy(iv.b);
@@ -580,46 +583,58 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
                    cnt + 1, ctx->scan_tmp.p, st);
     }
     G4D_HIP(hipGetLastError());
-    int64_t vis_grid = slots, pair_grid;
+    int64_t pair_grid;
+    // n_tiles + 1 keys: the dummy tile id n_tiles must sort too.  With at most 2^16 of them
+    // the keys move as 16-bit words (the pair buffers are sized for 32).
+    const int key_bits = bits_for(ctx->n_tiles + 1);
+    const bool key16 = key_bits <= 16;
+    auto run_keygen = [&](int64_t vis_grid) {
+      Stage t(ctx, 4, st);
+      if (key16)
+        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
+               ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
+               P<uint16_t>(ctx->pk[0]), P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+      else
+        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
+               ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
+               P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+      clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
+    };
     if (ctx->capturing) {
       // counts stay on the device; grids cover the capacities
       n_pairs = pair_grid = ctx->pair_cap;
+      if (n_pairs > 0) run_keygen(slots);
     } else {
+      // The counts go to the host; with pair buffers from an earlier call the key generation
+      // is queued behind the copy at once (grid over every slot, writes clamped to the
+      // capacity), so that the GPU does not idle while the host reads the counts.  Should the
+      // pairs exceed that capacity, the buffers grow and the key generation runs again.
+      const bool early = ctx->pair_cap > 0;
       G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-      G4D_HIP(hipStreamSynchronize(st));
-      n_vis = vis_grid = ctx->h_counters[0];
+      G4D_HIP(hipEventRecord(ctx->counts_ready, st));
+      if (early) run_keygen(slots);
+      G4D_HIP(hipEventSynchronize(ctx->counts_ready));
+      n_vis = ctx->h_counters[0];
       n_pairs = pair_grid = ctx->h_counters[1];
       if (n_pairs > (int64_t)UINT32_MAX - 1)
         return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^32-2", (long long)n_pairs);
-      if (n_pairs > 0) {
+      const bool fits = early && n_pairs <= ctx->pair_cap;
+      if (n_pairs > 0 && !fits) {
         for (int b = 0; b < 2; ++b) {
           if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
           if ((r = ensure(ctx, ctx->pv[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
         }
-        ctx->pair_cap = (int64_t)(ctx->pk[0].cap / sizeof(uint32_t));
-        if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
-            G4D_OK)
-          return r;
+        ctx->pair_cap = (int64_t)(std::min(ctx->pk[0].cap, ctx->pv[0].cap) / sizeof(uint32_t));
+        if (early) fill_u32(cnt + 2, 1, 0u, st);  // the early pass flagged the overflow
+        run_keygen(n_vis);
       }
+      if (n_pairs > 0 &&
+          (r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
+              G4D_OK)
+        return r;
     }
     if (n_pairs > 0) {
-      // n_tiles + 1 keys: the dummy tile id n_tiles must sort too.  With at most 2^16 of them
-      // the keys move as 16-bit words (the pair buffers are sized for 32).
-      const int key_bits = bits_for(ctx->n_tiles + 1);
-      const bool key16 = key_bits <= 16;
       uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
-      {
-        Stage t(ctx, 4, st);
-        if (key16)
-          keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
-                 ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
-                 P<uint16_t>(ctx->pk[0]), pv[0], cnt + 2, st);
-        else
-          keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
-                 ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
-                 P<uint32_t>(ctx->pk[0]), pv[0], cnt + 2, st);
-        clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
-      }
       {
         Stage t(ctx, 5, st);
         if (key16) {

@@ -300,3 +300,27 @@ def test_stage_profile_and_mask(renderer, w0):
     log(f"raster_bwd only: {only}")
     assert only["raster_bwd"][1] == 1 and only["raster_bwd"][0] > 0
     assert all(n == 0 for k, (_, n) in only.items() if k != "raster_bwd"), only
+
+
+def test_pair_buffers_grow_between_calls(renderer, w0):
+    # The key generation is queued before the host has read the pair count, into the pair
+    # buffers of the previous call; a call with many more pairs grows them and generates the
+    # keys again (the overflow flag of the first pass is cleared: sync() would raise).  Images
+    # on the used context equal those of a fresh context.
+    from paper_2412_20720_amd.frontend import Renderer
+    small = scenes.subset(w0, np.arange(200))
+    used, fresh = Renderer(0), Renderer(0)
+    try:
+        img_small = GpuRun(used, small).forward().images()[0]
+        n_small = used.stats()["n_pairs"]
+        img_full = GpuRun(used, w0).forward().images()[0]
+        n_full = used.stats()["n_pairs"]
+        again = GpuRun(used, small).forward().images()[0]
+        ref_full = GpuRun(fresh, w0).forward().images()[0]
+        log(f"pairs: small {n_small}, full {n_full} (fresh {fresh.stats()['n_pairs']})")
+        assert n_full > 2 * n_small and n_full == fresh.stats()["n_pairs"]
+        assert np.array_equal(img_full, ref_full)
+        assert np.array_equal(again, img_small)
+    finally:
+        used.close()
+        fresh.close()
