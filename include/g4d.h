@@ -114,7 +114,7 @@ typedef struct {
  *                     or 4 (16x16); 2 and 4 need tile_size >= 16 (0 = library default:
  *                     4, or 1 for 8-pixel tiles)
  *   bwd_px_per_lane 0 pixels per lane of the backward raster waves: 1, 2, 4 as above, or 8
- *                     (16x32 blocks, tile_size 32 only); 0 = library default: 8 at 32-pixel
+ *                     (32x16 blocks, tile_size 32 only); 0 = library default: 8 at 32-pixel
  *                     tiles when the forward takes 4, else the forward's value.  The backward
  *                     reads only per-pixel state of the forward, so the two may differ.
  * Tile size, batch and pixels per lane change the work decomposition only, never the image. */

@@ -290,7 +290,7 @@ DSettings device_settings(const g4d_settings* s) {
   d.tile_shift = s->tile_size == 8 ? 3 : (s->tile_size == 16 ? 4 : 5);
   d.lds_batch = s->lds_batch == 0 ? 64 : s->lds_batch;
   d.px_per_lane = s->px_per_lane == 0 ? (s->tile_size == 8 ? 1 : 4) : s->px_per_lane;
-  // The backward's default: 16x32 blocks where the forward takes 16x16 ones at 32-pixel
+  // The backward's default: 32x16 blocks where the forward takes 16x16 ones at 32-pixel
   // tiles.  It amortizes the per-entry wave reduction and atomic over twice the pixels
   // (measured on the 300k/16-view workload: raster_bwd 2.36 -> 2.16 ms; the forward, with no
   // per-entry reduction, is slower at 8: 1.04 -> 1.17 ms).
