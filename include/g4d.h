@@ -83,8 +83,8 @@ typedef struct {
 
 /* (host) One view: pinhole intrinsics K = (fx, fy, cx, cy), extrinsic world->camera
  * E = [R | tau] row-major 3x4 with OpenCV axes (x right, y down, z forward), time t and
- * background color (Sec. 3.1 "given a pixel (u, v) in view I with extrinsic E and intrinsic K";
- * Sec. 3.2 adds the timestamp t).  Pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
+ * background color (Sec. 3.1 renders a pixel (u, v) of a view from its extrinsic E and
+ * intrinsic K; Sec. 3.2 adds the timestamp t).  Pixel (i, j) is sampled at (i + 0.5, j + 0.5). */
 typedef struct {
   int32_t width, height;
   float fx, fy, cx, cy;
@@ -151,16 +151,17 @@ const char *g4d_last_error(const g4d_ctx *ctx);
  * Sec. 3.1 eq:meansplatting, eq:covsplatting; 4DSH color).  Writes
  *   records [n_views][N][G4D_RECORD_FLOATS]:
  *     0 u, 1 v (screen mean, px), 2..4 conic (a, b, c) = inverse 2D covariance,
- *     5 opacity * p(t), 6..8 rgb, 9..10 half extents of the cutoff ellipse box (px),
- *     11 camera-space depth;
- *   tiles [n_views][N] int32: number of screen tiles the splat's box covers, 0 if culled.
+ *     5 opacity * p(t), 6..8 rgb, 9..10 half extents (px) of the box of the reach ellipse
+ *     (where alpha can still reach alpha_min, within the cutoff), 11 camera-space depth;
+ *   tiles [n_views][N] int32: number of screen tiles with a pixel centre inside the reach
+ *     ellipse, 0 if culled or if the splat can reach no pixel.
  * Either output may be NULL. */
 g4d_status g4d_preprocess(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
                           int32_t n_views, const g4d_settings *s, float *records, int32_t *tiles,
                           void *stream);
 
-/* Forward render of n_views views in one batch (Sec. 3.2, eq:4dblending with the tile-based
- * rasterizer of Sec. 3.2 "adapt the highly efficient tile-based rasterizer"):
+/* Forward render of n_views views in one batch (Sec. 3.2, eq:4dblending, composited with the
+ * tile-based rasterizer that Sec. 3.2 takes over from 3D Gaussian splatting):
  *   out_rgb: per view planar [3][H][W], views concatenated in order;
  *   out_T:   per view [H][W] final transmittance (may be NULL).
  * Saves the state its backward needs in ctx. */

@@ -2,8 +2,8 @@
 // key generation, an LDS-staged wavefront LSD radix sort and tile-range detection.
 //
 // Binning follows the tile-based rasterizer the paper adopts (Sec. 3.2): every splat is
-// listed in each screen tile its cutoff box touches, and each tile's list is ordered by
-// camera depth (Sec. 3.1, "sorted according to their depth").  Here the depth order is made
+// listed in each screen tile its reach ellipse touches, and each tile's list is ordered by
+// camera depth, front to back (Sec. 3.1 composites the splats in depth order).  Here the depth order is made
 // once per visible splat (a 32-bit depth sort of the compacted slots); the (tile, splat)
 // pairs are then emitted in depth order and stably sorted by tile id alone, so each tile's
 // list inherits the depth order (ties keep the slot order, i.e. the Gaussian index).
