@@ -1,0 +1,317 @@
+"""Pins of the oracle's clamps, culls and view direction against closed forms.
+
+Each test fixes one branch of the render that the smooth closed forms elsewhere never reach:
+
+- the opacity clamp alpha = min(alpha_max, o p(t) p(u, v | t)) of the compositing rule
+  (Sec. 3.1 eq. alphablending, Sec. 3.2 eq. eq:4dblending) and its frozen derivative;
+- the 4DSH view direction, from the camera centre to the conditional (sliced) mean
+  (Sec. 3.2, "4D spherindrical harmonics" and the conditional mean equation);
+- the off-screen clamp of the perspective Jacobian in the EWA covariance
+  (Sec. 3.1 eq. covsplatting);
+- the near-plane cull and the temporal marginal cull (Sec. 8.1 implementation details);
+- the colour clamp at color_min and its zero derivative.
+
+Expected values are computed here from geometry (camera centre = the look-at eye, a numeric
+Jacobian of the pinhole map at the clamped point, the (x, t)-plane closed form of the slice)
+rather than from the oracle's own formulas.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+Y00 = 0.5 / math.sqrt(math.pi)
+C1 = math.sqrt(3.0 / (4.0 * math.pi))  # degree-1 real SH: (Y_1^-1, Y_1^0, Y_1^1) = C1 (y, z, x)
+
+# No cutoff, skip, stop, blur or clamps unless a test turns one on.
+CF = dict(cutoff_sigma=1e6, alpha_min=0.0, T_min=0.0, alpha_max=1.0, blur=0.0, color_min=-1e30,
+          marginal_min=0.0, jacobian_margin=1e6)
+
+
+def look_at64(eye, target, up=(0.0, 1.0, 0.0)):
+    """[R | tau] in float64: rows (right, down, forward), tau = -R eye (OpenCV axes)."""
+    eye = np.asarray(eye, np.float64)
+    f = np.asarray(target, np.float64) - eye
+    f /= np.linalg.norm(f)
+    r = np.cross(f, np.asarray(up, np.float64))
+    r /= np.linalg.norm(r)
+    d = np.cross(f, r)
+    R = np.stack([r, d, f])
+    return np.concatenate([R, (-R @ eye)[:, None]], axis=1)
+
+
+def view(W, H, f, E, t, bg=(0.0, 0.0, 0.0), cx=None, cy=None):
+    return dict(width=W, height=H, fx=f, fy=f, cx=W / 2 if cx is None else cx,
+                cy=H / 2 if cy is None else cy, world_to_cam=np.asarray(E, np.float64), t=t,
+                background=np.array(bg, np.float64))
+
+
+def one_gaussian(mean4, scale4, ql=(1, 0, 0, 0), qr=(1, 0, 0, 0), opacity=1.0, sh=None):
+    sh = np.zeros((1, 1, 1, 3)) if sh is None else np.asarray(sh, np.float64)[None]
+    return dict(mean4=np.array([mean4], np.float64), scale4=np.array([scale4], np.float64),
+                rot_l=np.array([ql], np.float64), rot_r=np.array([qr], np.float64),
+                opacity=np.array([opacity], np.float64), sh=sh)
+
+
+def dc_for(rgb):
+    """Degree-0 coefficients whose color (offset 0.5) is rgb."""
+    return (np.asarray(rgb, np.float64) - 0.5)[None, None, :] / Y00
+
+
+# ------------------------------------------------------------------------------------------
+# Opacity clamp (Sec. 3.1 eq. alphablending): alpha = min(alpha_max, o p(t) G)
+# ------------------------------------------------------------------------------------------
+def test_alpha_max_clamp_image_and_frozen_derivative(oracle_lib):
+    # An isotropic Gaussian on the optical axis with o p(t) = 1: alpha = min(0.99, G) with
+    # G = exp(-r^2 / (2 sigma_px^2)), sigma_px^2 = (f sigma / z)^2 + blur.  The core pixels
+    # where G > 0.99 are clamped.
+    sigma, z, f, blur = 0.8, 3.0, 60.0, 0.3
+    W = H = 41
+    rgb, bg = np.array([0.9, 0.4, 0.2]), np.array([0.1, 0.3, 0.6])
+    sc = one_gaussian([0, 0, 0, 0.5], [sigma] * 3 + [0.4], opacity=1.0, sh=dc_for(rgb))
+    vw = view(W, H, f, look_at64((0, 0, z), (0, 0, 0)), 0.5, bg=bg)
+    st = dict(CF, blur=blur, alpha_max=0.99)
+    s2 = (f * sigma / z) ** 2 + blur
+    ys, xs = np.mgrid[0:H, 0:W]
+    r2 = (xs + 0.5 - W / 2) ** 2 + (ys + 0.5 - H / 2) ** 2
+    G = np.exp(-0.5 * r2 / s2)
+    a = np.minimum(0.99, G)
+    clamped = G > 0.99 * (1 + 1e-6)
+    assert clamped.sum() >= 9
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        out = fr.render()
+        for ch in range(3):
+            np.testing.assert_allclose(out["rgb"][ch], a * rgb[ch] + (1 - a) * bg[ch], atol=1e-12)
+        # Upstream gradient on the clamped pixels only: no geometry or opacity gradient (the
+        # clamped alpha is constant); the color gradient is sum T alpha dC/dk = 0.99 Y00 per
+        # pixel and unit upstream value.
+        g = np.zeros((3, H, W))
+        g[:, clamped] = 1.0
+        grads = fr.backward(g)
+    for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity"):
+        assert np.abs(grads[k]).max() <= 1e-15, (k, grads[k])
+    np.testing.assert_allclose(grads["sh"][0, 0, 0], [0.99 * Y00 * clamped.sum()] * 3, rtol=1e-12)
+
+
+def test_alpha_max_clamp_central_differences(oracle_lib):
+    # The same Gaussian under the default settings, upstream gradient on every pixel: central
+    # differences of the forward (the clamp is crossed by no pixel for a tiny step) agree with
+    # the backward, which must drop the clamped pixels' geometry terms.
+    sigma, z, f = 0.8, 3.0, 60.0
+    W = H = 41
+    rgb, bg = np.array([0.9, 0.4, 0.2]), np.array([0.1, 0.3, 0.6])
+    vw = view(W, H, f, look_at64((0.05, 0.02, z), (0, 0, 0)), 0.5, bg=bg)
+    rng = np.random.default_rng(41)
+    g = rng.normal(size=(3, H, W))
+    st = dict(oracle.SMOOTH_SETTINGS)
+
+    def loss(arr):
+        with oracle.Frame(arr, 0, 0, vw, st, exact_f64=True) as fr:
+            return float((fr.render()["rgb"] * g).sum())
+
+    sc = one_gaussian([0.01, -0.02, 0.03, 0.5], [sigma, 0.8 * sigma, 1.1 * sigma, 0.4],
+                      ql=(0.9, 0.1, -0.2, 0.05), qr=(0.95, -0.1, 0.05, 0.1), opacity=1.0,
+                      sh=dc_for(rgb))
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        grads = fr.backward(g)
+    for name in ("mean4", "scale4", "rot_l", "rot_r", "opacity"):
+        for j in range(sc[name].size):
+            h = 1e-6
+            p = {k: v.copy() for k, v in sc.items()}
+            m = {k: v.copy() for k, v in sc.items()}
+            p[name].reshape(-1)[j] += h
+            m[name].reshape(-1)[j] -= h
+            fd = (loss(p) - loss(m)) / (2 * h)
+            an = grads[name].reshape(-1)[j]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (name, j, fd, an)
+
+
+# ------------------------------------------------------------------------------------------
+# View direction of the 4DSH (Sec. 3.2): from the camera centre to the sliced mean
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("theta,t", [(0.4, 0.9), (-0.6, 0.1)])
+def test_view_direction_from_camera_centre_to_sliced_mean(oracle_lib, theta, t):
+    # Rotors q_l = q_r = (cos th, 0, 0, sin th) rotate the (x, t) plane by 2 th, so the sliced
+    # mean moves along x: mu_c = mu_x + Sigma_xt / Sigma_tt (t - mu_t) (closed form).  The
+    # camera is rotated and looks past the origin, so its centre (the look-at eye) differs
+    # from -tau.  Degree-1 SH: color = 0.5 + Y00 k_00 + C1 (k_1-1 d_y + k_10 d_z + k_11 d_x).
+    s4 = np.array([0.3, 0.2, 0.1, 0.8])
+    m4 = np.array([0.1, -0.2, 0.3, 0.5])
+    q = (math.cos(theta), 0.0, 0.0, math.sin(theta))
+    rng = np.random.default_rng(42)
+    k = rng.normal(0.0, 1.0, (4, 3))  # [basis 0..3][channel]
+    sc = one_gaussian(m4, s4, ql=q, qr=q, opacity=0.7, sh=k)
+    eye = np.array([1.3, -0.8, 3.1])
+    vw = view(64, 48, 50.0, look_at64(eye, (0.2, 0.1, -0.3)), t)
+    c, s = math.cos(2 * theta), math.sin(2 * theta)
+    sxt = c * s * (s4[0] ** 2 - s4[3] ** 2)
+    stt = s * s * s4[0] ** 2 + c * c * s4[3] ** 2
+    mu_c = m4[:3] + np.array([sxt / stt * (t - m4[3]), 0.0, 0.0])
+    assert np.linalg.norm(mu_c - m4[:3]) > 0.02
+    d = (mu_c - eye) / np.linalg.norm(mu_c - eye)
+    want = 0.5 + Y00 * k[0] + C1 * (k[1] * d[1] + k[2] * d[2] + k[3] * d[0])
+    with oracle.Frame(sc, 1, 0, vw, CF, exact_f64=True) as fr:
+        sp = fr.splats()
+    assert sp["alive"][0]
+    np.testing.assert_allclose(sp["mean3"][0], mu_c, atol=1e-13)
+    np.testing.assert_allclose(sp["color"][0], want, atol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Off-screen Jacobian clamp (Sec. 3.1 eq. covsplatting)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("corner", ["lower_right", "upper_left", "right_only"])
+def test_jacobian_clamped_to_widened_image(oracle_lib, corner):
+    # A Gaussian whose mean projects beyond the image widened by m on each side: its 2D
+    # covariance uses the Jacobian of the pinhole map at the point of the same depth that
+    # projects onto the widened border (pixel (1 + m) W or -m W horizontally, (1 + m) H or
+    # -m H vertically).  The Jacobian is taken here by central differences of the projection.
+    W, H, f, m, blur = 64, 40, 50.0, 0.15, 0.3
+    E = look_at64((0.4, 0.3, 3.0), (0.0, 0.0, 0.0))
+    Rw, tau = E[:, :3], E[:, 3]
+    z = 2.0
+    ratios = {"lower_right": (1.2, 0.8), "upper_left": (-1.1, -0.75), "right_only": (1.3, 0.1)}
+    rx, ry = ratios[corner]
+    xc = np.array([rx * z, ry * z, z])          # camera-space mean
+    mu = Rw.T @ (xc - tau)                       # world-space mean
+    s3 = np.array([0.3, 0.15, 0.2])
+    sc = one_gaussian(list(mu) + [0.5], list(s3) + [1.0])
+    vw = view(W, H, f, E, 0.5)
+    st = dict(CF, blur=blur, jacobian_margin=m)
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        sp = fr.splats()
+    cx, cy = W / 2, H / 2
+
+    def proj(p):
+        return np.array([f * p[0] / p[2] + cx, f * p[1] / p[2] + cy])
+
+    u, v = proj(xc)
+    u_c = min(max(u, -m * W), (1 + m) * W)
+    v_c = min(max(v, -m * H), (1 + m) * H)
+    assert (u_c != u) and (corner == "right_only" or v_c != v)
+    pc = np.array([(u_c - cx) * z / f, (v_c - cy) * z / f, z])  # clamped point, same depth
+    h = 1e-6
+    J = np.stack([(proj(pc + h * e) - proj(pc - h * e)) / (2 * h) for e in np.eye(3)], 1)
+    S2 = J @ Rw @ np.diag(s3 ** 2) @ Rw.T @ J.T + blur * np.eye(2)
+    np.testing.assert_allclose(sp["cov2d"][0], [S2[0, 0], S2[0, 1], S2[1, 1]], rtol=1e-8)
+    np.testing.assert_allclose(sp["mean2d"][0], [u, v], rtol=1e-13)
+
+
+def test_jacobian_clamp_frozen_derivative(oracle_lib):
+    # A large Gaussian whose mean lies right of the widened image but whose splat reaches into
+    # it: central differences of the forward agree with the backward, in which the clamped
+    # ratio x/z is a constant.
+    W, H, f = 40, 32, 40.0
+    E = look_at64((0.0, 0.0, 3.0), (0.0, 0.0, 0.0))
+    vw = view(W, H, f, E, 0.5, bg=(0.2, 0.2, 0.2))
+    z = 3.0
+    xc = np.array([0.7 * z, 0.05 * z, z])       # x/z = 0.7 > ((1 + m) W - cx) / f = 0.65
+    mu = E[:, :3].T @ (xc - E[:, 3])
+    sc = one_gaussian(list(mu) + [0.5], [0.45, 0.3, 0.35, 1.0], ql=(0.9, 0.2, 0.1, -0.1),
+                      qr=(1.0, 0.05, -0.1, 0.02), opacity=0.8, sh=dc_for([0.8, 0.5, 0.3]))
+    st = dict(oracle.SMOOTH_SETTINGS)
+    rng = np.random.default_rng(43)
+    g = rng.normal(size=(3, H, W))
+
+    def loss(arr):
+        with oracle.Frame(arr, 0, 0, vw, st, exact_f64=True) as fr:
+            return float((fr.render()["rgb"] * g).sum())
+
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        sp = fr.splats()
+        out = fr.render()
+        grads = fr.backward(g)
+    assert sp["mean2d"][0][0] > 1.15 * W       # the mean is beyond the clamp
+    assert out["n_contrib"].sum() > 50          # and the splat still covers pixels
+    for name in ("mean4", "scale4", "rot_l"):
+        for j in range(sc[name].size):
+            h = 1e-6
+            p = {k: v.copy() for k, v in sc.items()}
+            m = {k: v.copy() for k, v in sc.items()}
+            p[name].reshape(-1)[j] += h
+            m[name].reshape(-1)[j] -= h
+            fd = (loss(p) - loss(m)) / (2 * h)
+            an = grads[name].reshape(-1)[j]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (name, j, fd, an)
+
+
+# ------------------------------------------------------------------------------------------
+# Culls: near plane and temporal marginal (Sec. 8.1 implementation details)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("inside", [True, False])
+def test_near_plane_cull(oracle_lib, inside):
+    # A small Gaussian on the optical axis at camera depth near_z (1 +- 5e-3): in front of the
+    # near plane it is rendered, behind it the image is the background.
+    near, eye_z = 0.2, 3.0
+    depth = near * (1.005 if inside else 0.995)
+    sc = one_gaussian([0, 0, eye_z - depth, 0.5], [0.002, 0.002, 0.002, 1.0], opacity=0.9,
+                      sh=dc_for([1.0, 1.0, 1.0]))
+    vw = view(21, 21, 30.0, look_at64((0, 0, eye_z), (0, 0, 0)), 0.5)
+    st = dict(oracle.DEFAULT_SETTINGS, near_z=near)
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        sp = fr.splats()
+        out = fr.render()
+    np.testing.assert_allclose(sp["depth"][0], depth, rtol=1e-12)
+    assert bool(sp["alive"][0]) == inside
+    assert not sp["optional"][0]
+    centre = out["rgb"][:, 10, 10]
+    if inside:
+        assert centre.min() > 0.5
+    else:
+        assert np.all(out["rgb"] == 0.0) and np.all(out["T"] == 1.0)
+
+
+@pytest.mark.parametrize("above", [True, False])
+def test_marginal_cull(oracle_lib, above):
+    # p(t) = exp(-(t - mu_t)^2 / (2 s_t^2)) for identity rotors; with the paper's threshold
+    # 0.05 a Gaussian at p(t) = 0.05 (1 +- 1e-2) is kept or dropped, although its alpha (up to
+    # 0.05) passes alpha_min = 1/255 either way.
+    thr, s_t = 0.05, 0.1
+    target = thr * (1.01 if above else 0.99)
+    dt = s_t * math.sqrt(-2.0 * math.log(target))
+    sc = one_gaussian([0, 0, 0, 0.5 - dt], [0.05, 0.05, 0.05, s_t], opacity=1.0,
+                      sh=dc_for([1.0, 1.0, 1.0]))
+    vw = view(21, 21, 30.0, look_at64((0, 0, 3.0), (0, 0, 0)), 0.5)
+    st = dict(oracle.DEFAULT_SETTINGS, marginal_min=thr)
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        sp = fr.splats()
+        out = fr.render()
+    np.testing.assert_allclose(sp["p_t"][0], target, rtol=1e-12)
+    assert bool(sp["alive"][0]) == above
+    if above:
+        assert out["rgb"][:, 10, 10].min() > 0.04
+    else:
+        assert np.all(out["rgb"] == 0.0)
+
+
+# ------------------------------------------------------------------------------------------
+# Colour clamp: c = max(color_min, color_offset + 4DSH sum)
+# ------------------------------------------------------------------------------------------
+def test_color_clamp_image_and_zero_sh_gradient(oracle_lib):
+    # Degree 0: the red sum is negative, so red is clamped to 0 and its coefficient gets no
+    # gradient; green and blue get sum_p alpha_p Y00 g_p (single Gaussian, T = 1).
+    sigma, z, f = 0.15, 3.0, 60.0
+    W = H = 25
+    base = np.array([-0.3, 0.6, 0.8])           # 0.5 + Y00 k per channel
+    bg = np.array([0.25, 0.15, 0.05])
+    sc = one_gaussian([0, 0, 0, 0.5], [sigma] * 3 + [0.5], opacity=0.7, sh=dc_for(base))
+    vw = view(W, H, f, look_at64((0, 0, z), (0, 0, 0)), 0.5, bg=bg)
+    st = dict(CF, color_min=0.0)
+    ys, xs = np.mgrid[0:H, 0:W]
+    r2 = (xs + 0.5 - W / 2) ** 2 + (ys + 0.5 - H / 2) ** 2
+    a = 0.7 * np.exp(-0.5 * r2 / (f * sigma / z) ** 2)
+    col = np.maximum(0.0, base)
+    rng = np.random.default_rng(44)
+    g = rng.normal(size=(3, H, W))
+    with oracle.Frame(sc, 0, 0, vw, st, exact_f64=True) as fr:
+        sp = fr.splats()
+        out = fr.render()
+        grads = fr.backward(g)
+    np.testing.assert_allclose(sp["color"][0], col, atol=1e-14)
+    for ch in range(3):
+        np.testing.assert_allclose(out["rgb"][ch], a * col[ch] + (1 - a) * bg[ch], atol=1e-12)
+    assert grads["sh"][0, 0, 0, 0] == 0.0
+    want = [(a * g[ch]).sum() * Y00 for ch in (1, 2)]
+    np.testing.assert_allclose(grads["sh"][0, 0, 0, 1:], want, rtol=1e-12)

@@ -10,6 +10,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+        os.path.join(ROOT, "tests", "test_oracle_branches.py"),
         os.path.join(ROOT, "tests", "test_oracle_gradients.py"),
         os.path.join(ROOT, "tests", "test_oracle_channels.py"),
         os.path.join(ROOT, "tests", "test_oracle_training.py"),
@@ -75,6 +76,29 @@ MUTATIONS = [
      "v = std::ldexp((double)(m + 1024), e - 24);"),
     ("mask threshold inclusive", "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold)) {",
      "if (f.g.mask && !(f.g.mask[i] > f.g.mask_threshold + 0.2)) {"),
+    ("alpha_max clamp removed", "const double alpha = std::min(st.alpha_max, raw);",
+     "const double alpha = raw;"),
+    ("backward ignores the alpha clamp", "    if (!ct.clamped) {", "    if (true) {"),
+    ("alpha_min skip removed", "bool skip = alpha < st.alpha_min;", "bool skip = false;"),
+    ("view direction from the unsliced mean", "for (int j = 0; j < 3; ++j) d[j] = sp.mean3[j] - Cc[j];",
+     "for (int j = 0; j < 3; ++j) d[j] = mean4[j] - Cc[j];"),
+    ("view direction reversed", "for (int j = 0; j < 3; ++j) d[j] = sp.mean3[j] - Cc[j];",
+     "for (int j = 0; j < 3; ++j) d[j] = Cc[j] - sp.mean3[j];"),
+    ("camera centre taken as -tau",
+     "Cc[j] = -(E[0 * 4 + j] * E[3] + E[1 * 4 + j] * E[7] + E[2 * 4 + j] * E[11]);",
+     "Cc[j] = -E[4 * j + 3];"),
+    ("Jacobian x clamp removed", "const S tx = clamp_val(S(x[0] / x[2]), xlo, xhi);",
+     "const S tx = S(x[0] / x[2]);"),
+    ("Jacobian y clamp removed", "const S ty = clamp_val(S(x[1] / x[2]), ylo, yhi);",
+     "const S ty = S(x[1] / x[2]);"),
+    ("Jacobian y clamp bound from the width", "yhi = ((1.0 + m) * vw.height - vw.cy) / vw.fy;",
+     "yhi = ((1.0 + m) * vw.width - vw.cy) / vw.fy;"),
+    ("Jacobian lower x bound sign", "const double xlo = (-m * vw.width - vw.cx) / vw.fx",
+     "const double xlo = (-m * vw.width + vw.cx) / vw.fx"),
+    ("near-plane cull removed", "  if (!(z > st.near_z)) cull = true;\n", "\n"),
+    ("marginal cull removed", "  if (!(pt >= st.marginal_min)) cull = true;\n", "\n"),
+    ("color clamp removed", "if (val(acc) < st.color_min) {", "if (false) {"),
+    ("backward ignores the color clamp", "if (!sp.color_clamped[ch]) gsh[", "if (true) gsh["),
 ]
 
 
