@@ -43,7 +43,8 @@ typedef enum {
   G4D_OK = 0,
   G4D_EINVAL = -1,    /* an argument failed a host-side check; nothing was enqueued */
   G4D_ENOMEM = -2,    /* a device allocation failed */
-  G4D_ECAPACITY = -3, /* the device found more (Gaussian, tile) pairs than the fixed capacity */
+  G4D_ECAPACITY = -3, /* more (Gaussian, tile) pairs than the fixed capacity of a captured graph,
+                         or more than 2^31 - 1 in one call */
   G4D_EHIP = -4,      /* a HIP runtime call failed */
   G4D_ESTATE = -5     /* backward without a matching forward in this context */
 } g4d_status;
@@ -60,7 +61,8 @@ typedef enum {
  *           eq. mask_prune), already activated: the forward uses M_hat = 1{M > mask_threshold},
  *           scales and opacity multiplied by M_hat, so a Gaussian with M <= mask_threshold is
  *           removed; the backward's dL/dM is straight-through (dM_hat/dM = 1).
- * sh_degree in 0..3, t_degree in 0..2, N >= 0. */
+ * sh_degree in 0..3, t_degree in 0..2, N >= 0.  A Gaussian with a non-finite value in any of
+ * its arrays is culled in every view and gets zero gradient. */
 typedef struct {
   int32_t n, sh_degree, t_degree;
   const float *mean4, *scale4, *rot_l, *rot_r, *opacity, *sh;
@@ -95,7 +97,7 @@ typedef struct {
 
 /* (host) Render settings.  The paper leaves these unstated except the marginal filter
  * (p(t) threshold, Sec. 8.1 implementation details); g4d_default_settings fills in:
- *   near_z 0.2        cull when the camera-space depth of the sliced mean is <= near_z
+ *   near_z 0.2        cull when the camera-space depth of the sliced mean is <= near_z (> 0)
  *   marginal_min 1/255 cull when p(t) < marginal_min (the paper quotes 0.05)
  *   cutoff_sigma 3    a splat covers pixels with Mahalanobis distance <= cutoff_sigma
  *   blur 0.3          EWA low-pass: added to both diagonal entries of the 2D covariance (px^2)
@@ -132,6 +134,9 @@ typedef struct {
   int64_t n_tiles;      /* screen tiles over all views */
   int64_t n_pixels;     /* pixels over all views */
   int64_t pair_capacity;
+  int64_t n_clamped_batches; /* LDS batches of the last backward that ran the raster's entry loop
+                                with the alpha_max clamp (an entry's opacity p(t) reaches it);
+                                counted only while g4d_eval_counters is enabled, else -1 */
 } g4d_stats;
 
 /* Fill *s with the defaults listed above.  Returns G4D_EINVAL if s is NULL. */
@@ -295,19 +300,34 @@ g4d_status g4d_render_compact_forward(g4d_ctx *ctx, const g4d_compact *c, const 
  * change between calls): no host synchronization, allocation or per-kernel launch happens in
  * a replay.  The first call (and any call whose key changed) runs one eager step on a private
  * context to size the buffers, then captures with a pair capacity 25% above the pair count
- * it found; if a later replay finds more pairs, g4d_sync_status reports G4D_ECAPACITY and the
- * outputs of that replay are undefined. */
+ * it found; if a later replay finds more pairs, g4d_sync_status reports G4D_ECAPACITY, the
+ * outputs of that replay are undefined, and the graph is dropped so that the next call with
+ * G4D_STEP_GRAPH sizes and captures it again. */
 g4d_status g4d_render_step(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
                            int32_t n_views, const g4d_settings *s, const float *dL_drgb,
                            float *out_rgb, float *out_T, const g4d_grads *grads, int32_t flags,
                            void *stream);
 
 /* Wait for the context's work on `stream` and report errors found on the device
- * (G4D_ECAPACITY when the pair capacity was exceeded; outputs are then undefined). */
+ * (G4D_ECAPACITY when the pair capacity of a captured graph was exceeded; outputs are then
+ * undefined).  An error is reported once: the flag is cleared. */
 g4d_status g4d_sync_status(g4d_ctx *ctx, void *stream);
 
 /* Counters of the last forward; synchronizes `stream`. */
 g4d_status g4d_get_stats(g4d_ctx *ctx, g4d_stats *out, void *stream);
+
+/* Binning of the last forward on this context, for checks and tools (the depth-ordered,
+ * tile-sorted list that the tile-based rasterizer of Sec. 3.2 walks): copies into caller device
+ * buffers, each of which may be NULL,
+ *   tile_ids [n_pairs] uint32: global tile id of every (tile, splat) pair, sorted ascending
+ *            (tiles of all views numbered consecutively, view by view, row-major in a view);
+ *   slots    [n_pairs] uint32: the (view, Gaussian) slot view * N + g of each pair; within a tile
+ *            the slots are in ascending camera depth, ties by ascending slot;
+ *   ranges   [n_tiles][2] uint32: [first, end) of each tile's pairs (0, 0 for an empty tile).
+ * n_pairs and n_tiles are those of g4d_get_stats.  G4D_ESTATE if the context holds no forward
+ * whose binning is kept (a later g4d_preprocess or a compact forward discards it). */
+g4d_status g4d_get_pairs(g4d_ctx *ctx, uint32_t *tile_ids, uint32_t *slots, uint32_t *ranges,
+                         void *stream);
 
 /* Per-pixel work counters of eq:4dblending: bits 0-15 hold the number of (Gaussian, pixel)
  * pairs whose Mahalanobis distance passes the cutoff and that the pixel visits before its

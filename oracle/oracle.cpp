@@ -66,6 +66,9 @@
 //   The extra channels have a zero background.  Their backward differentiates the features,
 //   the gate and the depth; flow is forward only (its upstream gradient is ignored).
 //
+// Failure rule (a reading; the paper has none): a Gaussian with a non-finite parameter is
+// dropped in every view and gets no gradient.
+//
 // Readings where the paper is silent (defaults chosen by the caller through orc_settings):
 // unnormalized Gaussians; opacity clamp alpha_max and skip threshold alpha_min; transmittance
 // stop T_min; per-pixel Mahalanobis cutoff; EWA low-pass "blur"; Jacobian clamp margin;
@@ -549,6 +552,18 @@ void build_frame(Frame& f) {
     }
     double m4[4], s4[4], ql[4], qr[4], o;
     load_params(f.g, i, m4, s4, ql, qr, o);
+    // Failure rule (a reading): a Gaussian with a non-finite parameter is dropped in every view,
+    // so it gets no gradient either.
+    bool finite = std::isfinite(o);
+    for (int k = 0; k < 4; ++k)
+      finite = finite && std::isfinite(m4[k]) && std::isfinite(s4[k]) && std::isfinite(ql[k]) &&
+               std::isfinite(qr[k]);
+    for (int k = 0; k < sh_stride(f.g); ++k)
+      finite = finite && std::isfinite(f.g.sh[(size_t)i * sh_stride(f.g) + k]);
+    if (!finite) {
+      f.splats[i].alive = f.splats[i].optional = false;
+      continue;
+    }
     SplatT<double> sp = preprocess<double>(m4, s4, ql, qr, o, f.g.sh + (size_t)i * sh_stride(f.g),
                                            f.g.sh_degree, f.g.t_degree, f.vw, f.st);
     Splat& s = f.splats[i];

@@ -21,7 +21,8 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_get_stats", "g4d_eval_counters", "g4d_autotune", "g4d_profile",
             "g4d_stage_name", "g4d_render_step", "g4d_render_channels_forward",
             "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward",
-            "g4d_decode_compact", "g4d_render_compact_forward", "g4d_profile_mask"]
+            "g4d_decode_compact", "g4d_render_compact_forward", "g4d_profile_mask",
+            "g4d_get_pairs"]
 G4D_STEP_GRAPH = 1
 G4D_NUM_STAGES = 11
 G4D_MAX_CHANNELS = 36
@@ -75,7 +76,8 @@ class g4d_compact(C.Structure):
 
 class g4d_stats(C.Structure):
     _fields_ = [("n_slots", C.c_int64), ("n_visible", C.c_int64), ("n_pairs", C.c_int64),
-                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("pair_capacity", C.c_int64)]
+                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("pair_capacity", C.c_int64),
+                ("n_clamped_batches", C.c_int64)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -104,6 +106,7 @@ def lib() -> C.CDLL:
                                       C.POINTER(g4d_settings), vp, C.POINTER(g4d_grads), vp]
     L.g4d_sync_status.argtypes = [vp, vp]
     L.g4d_get_stats.argtypes = [vp, C.POINTER(g4d_stats), vp]
+    L.g4d_get_pairs.argtypes = [vp, vp, vp, vp, vp]
     L.g4d_eval_counters.argtypes = [vp, C.c_int, vp, vp]
     L.g4d_render_step.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
                                   C.POINTER(g4d_settings), vp, vp, vp, C.POINTER(g4d_grads), i32,

@@ -55,6 +55,9 @@ void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap
 void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
                  int64_t n_tiles, uint2* ranges, hipStream_t st);
 
+// out[0..n) = in[0..n) widened to 32 bits.
+void widen_u16(const uint16_t* in, int64_t n, uint32_t* out, hipStream_t st);
+
 // *out = min(*n, cap) on the device.
 void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st);
 
@@ -109,6 +112,8 @@ struct RasterArgs {
   const float* dL_ch;        // backward: same layout (flow channels ignored)
   float* dfn;                // backward: dL/d(normalized features) [n_gauss][n_feat], atomics
   const float* bg_px;        // optional per-pixel background, the image's layout (the sky)
+  uint32_t* clamp_batches;   // backward, optional: += 1 per staged batch that ran the entry
+                             // loop with the alpha_max clamp (some entry's opacity p_t reaches it)
 };
 
 // Sky (k_sky.hip): per-pixel background from a cube map [6][R][R][3] queried by each pixel's

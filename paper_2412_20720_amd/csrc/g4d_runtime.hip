@@ -70,6 +70,7 @@ struct g4d_ctx {
   int64_t n_tiles = 0, n_pixels = 0;
   g4d_stats stats{};
   bool count_evals = false;
+  bool counted_bwd = false;  // the last backward counted its clamped batches (counters[4])
   // stage profiling (stages whose bit is set in stage_mask)
   bool profiling = false;
   uint32_t stage_mask = 0xFFFFFFFFu;
@@ -207,7 +208,8 @@ g4d_status check_common(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* vi
   }
   // 0 < alpha_min <= alpha_max < 1: the backward rebuilds T by dividing by 1 - alpha and
   // recovers the opacity partial of an entry by dividing by its opacity p_t >= alpha_min.
-  if (!(s->cutoff_sigma > 0.f) || !(s->alpha_min > 0.f) || !(s->alpha_max >= s->alpha_min) ||
+  if (!(s->near_z > 0.f) || !(s->cutoff_sigma > 0.f) || !(s->alpha_min > 0.f) ||
+      !(s->alpha_max >= s->alpha_min) ||
       !(s->alpha_max < 1.f) || !(s->T_min >= 0.f) || !(s->time_period > 0.f) ||
       !(s->blur >= 0.f) || !(s->jacobian_margin >= 0.f) || !finite(s->near_z) ||
       !finite(s->marginal_min) || !finite(s->color_offset) || std::isnan(s->color_min))
@@ -530,9 +532,11 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   const g4d_settings s_run = run_settings(s, ch);
   const DSettings DS = device_settings(&s_run);
   const int n_ext = n_ext_of(ch);
-  if ((r = ensure(ctx, ctx->counters, 4 * sizeof(uint32_t))) != G4D_OK) return r;
-  // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity
+  if ((r = ensure(ctx, ctx->counters, 8 * sizeof(uint32_t))) != G4D_OK) return r;
+  // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity,
+  // [4] clamped batches of the last counted backward
   uint32_t* cnt = P<uint32_t>(ctx->counters);
+  ctx->counted_bwd = false;
   fill_u32(cnt, 4, 0u, st);
   if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
@@ -616,8 +620,9 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       G4D_HIP(hipEventSynchronize(ctx->counts_ready));
       n_vis = ctx->h_counters[0];
       n_pairs = pair_grid = ctx->h_counters[1];
-      if (n_pairs > (int64_t)UINT32_MAX - 1)
-        return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^32-2", (long long)n_pairs);
+      // list positions are 32-bit signed in the raster kernels
+      if (n_pairs > (int64_t)INT32_MAX)
+        return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^31-1", (long long)n_pairs);
       const bool fits = early && n_pairs <= ctx->pair_cap;
       if (n_pairs > 0 && !fits) {
         for (int b = 0; b < 2; ++b) {
@@ -703,6 +708,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   ctx->stats.n_tiles = ctx->n_tiles;
   ctx->stats.n_pixels = ctx->n_pixels;
   ctx->stats.pair_capacity = ctx->pair_cap;
+  ctx->stats.n_clamped_batches = -1;
   SavedKey& k = ctx->key;
   k.n = g->n;
   k.sh_degree = g->sh_degree;
@@ -788,6 +794,11 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
     a.dL = dL_drgb;
     a.grad2d = P<float>(ctx->grad2d);
     a.bg_px = sky ? P<float>(ctx->skybg) : nullptr;
+    if (ctx->count_evals && !ctx->capturing) {
+      fill_u32(P<uint32_t>(ctx->counters) + 4, 1, 0u, st);
+      a.clamp_batches = P<uint32_t>(ctx->counters) + 4;
+      ctx->counted_bwd = true;
+    }
     if (ch) {
       a.n_ext = n_ext_of(ch);
       a.n_feat = D;
@@ -970,6 +981,8 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
     G4D_HIP(hipStreamSynchronize(st));
     const int64_t slots = (int64_t)g->n * n_views;
     const int64_t want = gc->stats.n_pairs + gc->stats.n_pairs / 4 + 4096;
+    if (want > (int64_t)INT32_MAX)
+      return fail(ctx, G4D_ECAPACITY, "graph pair capacity %lld exceeds 2^31-1", (long long)want);
     for (int b = 0; b < 2; ++b) {
       if ((r = ensure(gc, gc->pk[b], sizeof(uint32_t) * want)) != G4D_OK ||
           (r = ensure(gc, gc->pv[b], sizeof(uint32_t) * want)) != G4D_OK)
@@ -1018,9 +1031,24 @@ g4d_status g4d_sync_status(g4d_ctx* ctx, void* stream) {
     if (!c || !c->counters.p) continue;
     uint32_t flag = 0;
     G4D_HIP(hipMemcpy(&flag, P<uint32_t>(c->counters) + 2, sizeof flag, hipMemcpyDeviceToHost));
+    if (!flag) continue;
+    // reported once: the flag is cleared, and a graph that overflowed is dropped, so that the
+    // next G4D_STEP_GRAPH call sizes and captures it again for the larger pair count
+    const uint32_t zero = 0;
+    G4D_HIP(hipMemcpy(P<uint32_t>(c->counters) + 2, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (c == ctx->graph_ctx && flag == 1) {
+      const long long cap = (long long)c->pair_cap;
+      if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+      if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+      ctx->graph_exec = nullptr;
+      ctx->graph = nullptr;
+      ctx->graph_key.clear();
+      return fail(ctx, G4D_ECAPACITY, "graph pair capacity %lld exceeded (the graph is dropped)",
+                  cap);
+    }
     if (flag == 1)
-      return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)ctx->pair_cap);
-    if (flag) return fail(ctx, G4D_EHIP, "pair count mismatch between preprocess and keygen");
+      return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)c->pair_cap);
+    return fail(ctx, G4D_EHIP, "pair count mismatch between preprocess and keygen");
   }
   return G4D_OK;
 }
@@ -1030,6 +1058,36 @@ g4d_status g4d_get_stats(g4d_ctx* ctx, g4d_stats* out, void* stream) {
   G4D_HIP(hipSetDevice(ctx->device));
   G4D_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
   *out = ctx->stats;
+  if (ctx->counted_bwd) {
+    uint32_t nb = 0;
+    G4D_HIP(hipMemcpy(&nb, P<uint32_t>(ctx->counters) + 4, sizeof nb, hipMemcpyDeviceToHost));
+    out->n_clamped_batches = nb;
+  }
+  return G4D_OK;
+}
+
+g4d_status g4d_get_pairs(g4d_ctx* ctx, uint32_t* tile_ids, uint32_t* slots, uint32_t* ranges,
+                         void* stream) {
+  if (!ctx) return G4D_EINVAL;
+  if (!ctx->saved || ctx->stats.n_pairs < 0)
+    return fail(ctx, G4D_ESTATE, "no eager forward whose binning is kept on this context");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  G4D_HIP(hipSetDevice(ctx->device));
+  const int64_t np = ctx->stats.n_pairs;
+  if (np > 0 && tile_ids) {
+    if (bits_for(ctx->n_tiles + 1) <= 16)
+      widen_u16(P<uint16_t>(ctx->pk[ctx->pair_buf]), np, tile_ids, st);
+    else
+      G4D_HIP(hipMemcpyAsync(tile_ids, ctx->pk[ctx->pair_buf].p, sizeof(uint32_t) * np,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  if (np > 0 && slots)
+    G4D_HIP(hipMemcpyAsync(slots, ctx->pv[ctx->pair_buf].p, sizeof(uint32_t) * np,
+                           hipMemcpyDeviceToDevice, st));
+  if (ranges && ctx->n_tiles > 0)
+    G4D_HIP(hipMemcpyAsync(ranges, ctx->ranges.p, sizeof(uint2) * ctx->n_tiles,
+                           hipMemcpyDeviceToDevice, st));
+  G4D_HIP(hipGetLastError());
   return G4D_OK;
 }
 

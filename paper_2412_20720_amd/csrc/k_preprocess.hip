@@ -64,6 +64,16 @@ __global__ __launch_bounds__(256) void k_preprocess(
 #pragma unroll
     for (int k = 0; k < NSH; ++k) shc[k] = shp[k];
   }
+  // A Gaussian with a non-finite parameter is culled in every view (so it also gets a zero
+  // gradient): NaN would otherwise slip through the min/max clamps as a finite value.
+  bool fin = isfinite(mean.x) && isfinite(mean.y) && isfinite(mean.z) && isfinite(mean.w) &&
+             isfinite(sc4.x) && isfinite(sc4.y) && isfinite(sc4.z) && isfinite(sc4.w) &&
+             isfinite(qlr.x) && isfinite(qlr.y) && isfinite(qlr.z) && isfinite(qlr.w) &&
+             isfinite(qrr.x) && isfinite(qrr.y) && isfinite(qrr.z) && isfinite(qrr.w) &&
+             isfinite(op);
+#pragma unroll
+  for (int k = 0; k < NSH; ++k) fin = fin && isfinite(shc[k]);
+  const bool alive = live && fin;
   Geom g;
   geom_forward(qlr, qrr, sc4, g);
   for (int v = 0; v < n_views; ++v) {
@@ -71,7 +81,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const size_t slot = (size_t)v * n + gi;
     ViewFwd f;
     // a splat that cannot reach alpha_min at any pixel of this view is not listed
-    const bool vis = live && view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f;
+    const bool vis = alive && view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f;
     float opt = 0.f, ex = 0.f, ey = 0.f;
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     uint32_t rows = 0;
@@ -204,6 +214,28 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
       color_forward<DS, DT>(shc, S, f);
       view_backward<DS, DT>(g, mean, op, shc, V, S, f, q, gM, gmean, gop, gsh);
     }
+  }
+  if (nvis == 0) {
+    // listed in no view (culled, masked or off screen): every gradient is exactly zero, also
+    // for parameters that are not finite (their forward culled them)
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = z4;
+    if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = z4;
+    if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = z4;
+    if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = z4;
+    if (out.opacity) out.opacity[gi] = 0.f;
+    if (out.mask) out.mask[gi] = 0.f;
+    if (out.densify) {
+      out.densify[3 * (size_t)gi + 0] = 0.f;
+      out.densify[3 * (size_t)gi + 1] = 0.f;
+      out.densify[3 * (size_t)gi + 2] = 0.f;
+    }
+    if (out.sh) {
+      float* o = out.sh + (size_t)gi * NSH;
+#pragma unroll
+      for (int k = 0; k < NSH; ++k) o[k] = 0.f;
+    }
+    return;
   }
   float gs[4], gql[4], gqr[4];
   geom_backward(g, sc, gM, gs, gql, gqr);

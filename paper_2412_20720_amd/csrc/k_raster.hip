@@ -683,6 +683,7 @@ __global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs 
       if (check) entries(std::false_type{}, std::true_type{});
       else entries(std::false_type{}, std::false_type{});
     } else {
+      if (a.clamp_batches && t.lane == 0) atomicAdd(a.clamp_batches, 1u);
       if (check) entries(std::true_type{}, std::true_type{});
       else entries(std::true_type{}, std::false_type{});
     }

@@ -499,6 +499,11 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_widen_u16(const uint16_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
 __global__ void k_clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out) {
   if (threadIdx.x == 0) *out = min(*n, cap);
 }
@@ -628,6 +633,11 @@ void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap
 void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
                  uint2* ranges, hipStream_t st) {
   tile_ranges_t<uint16_t>(pkey, n_pairs, pair_cap, n_tiles, ranges, st);
+}
+
+void widen_u16(const uint16_t* in, int64_t n, uint32_t* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_widen_u16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, n, out);
 }
 
 void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st) {

@@ -21,8 +21,11 @@ def _stream_handle(device: torch.device) -> int:
 
 
 class Renderer:
-    """One g4d context on one GPU.  A backward must follow its own forward before the next
-    forward on the same Renderer (the library reports G4D_ESTATE otherwise)."""
+    """One g4d context on one GPU.  The context keeps the state of its last forward for the
+    matching backward (the library reports G4D_ESTATE for any other).  The autograd functions
+    below accept several renders on one Renderer before their backwards: a backward whose
+    forward is no longer the context's last one runs that forward again first (the forward is
+    deterministic, so its state is the one the outputs came from)."""
 
     def __init__(self, device: int | torch.device = 0):
         dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
@@ -69,6 +72,27 @@ class Renderer:
     @staticmethod
     def pixel_count(views) -> int:
         return sum(int(v["width"]) * int(v["height"]) for v in views)
+
+    @staticmethod
+    def pixel_count_array(views) -> int:
+        """Pixels of a g4d_view array (or of a list of view dicts)."""
+        if isinstance(views, C.Array):
+            return sum(int(v.width) * int(v.height) for v in views)
+        return Renderer.pixel_count(views)
+
+    def pairs(self):
+        """Sorted (tile id, slot) pairs and tile ranges of the last forward, as int64 CPU
+        tensors: (tile_ids [n_pairs], slots [n_pairs], ranges [n_tiles, 2])."""
+        st = self.stats()
+        n, nt = st["n_pairs"], st["n_tiles"]
+        tid = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        slots = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        ranges = torch.empty((max(nt, 1), 2), dtype=torch.int32, device=self.device)
+        B.check(B.lib().g4d_get_pairs(self._ctx, tid.data_ptr(), slots.data_ptr(),
+                                      ranges.data_ptr(), _stream_handle(self.device)), self._ctx)
+        torch.cuda.synchronize(self.device)
+        u32 = lambda t: t.cpu().to(torch.int64) & 0xFFFFFFFF
+        return u32(tid[:n]), u32(slots[:n]), u32(ranges[:nt])
 
     # -- entry points ----------------------------------------------------------------------
     def forward(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, out_rgb: torch.Tensor,
@@ -192,15 +216,31 @@ class Renderer:
 
     def step(self, g: B.g4d_gaussians, views, settings: B.g4d_settings, dL: torch.Tensor,
              out_rgb: torch.Tensor, out_T: Optional[torch.Tensor],
-             grads: Dict[str, torch.Tensor], graph: bool = True) -> None:
-        """Forward + backward in one call; with graph=True a captured hipGraph is replayed."""
+             grads: Dict[str, torch.Tensor], graph: bool = True, check: bool = True) -> bool:
+        """Forward + backward in one call; with graph=True a captured hipGraph is replayed.
+
+        A replay sorts into pair buffers of fixed capacity.  With check=True (the default) the
+        call waits for the replay and reads the device status; if the pairs outgrew the
+        capacity (parameters moved since the capture), the library drops the graph and this
+        call redoes the step eagerly, so the outputs are always valid, and the next graph call
+        captures again with a larger capacity.  With check=False nothing waits: call sync()
+        before using the outputs.  Returns False when the step had to be redone."""
         va = views if isinstance(views, C.Array) else B.make_views(views)
         gr = B.g4d_grads(*[grads[k].data_ptr() for k in PARAM_NAMES])
-        B.check(B.lib().g4d_render_step(self._ctx, C.byref(g), va, len(va), C.byref(settings),
-                                        dL.data_ptr(), out_rgb.data_ptr(),
-                                        None if out_T is None else out_T.data_ptr(), C.byref(gr),
-                                        B.G4D_STEP_GRAPH if graph else 0,
-                                        _stream_handle(self.device)), self._ctx)
+        args = (self._ctx, C.byref(g), va, len(va), C.byref(settings), dL.data_ptr(),
+                out_rgb.data_ptr(), None if out_T is None else out_T.data_ptr(), C.byref(gr))
+        st = _stream_handle(self.device)
+        B.check(B.lib().g4d_render_step(*args, B.G4D_STEP_GRAPH if graph else 0, st), self._ctx)
+        if not (graph and check):
+            return True
+        try:
+            self.sync()
+            return True
+        except B.G4DError as e:
+            if e.status != B.G4D_ECAPACITY:
+                raise
+        B.check(B.lib().g4d_render_step(*args, 0, st), self._ctx)
+        return False
 
     def preprocess(self, g: B.g4d_gaussians, views, settings: B.g4d_settings):
         va = views if isinstance(views, C.Array) else B.make_views(views)
@@ -267,6 +307,20 @@ class Renderer:
         return {B.lib().g4d_stage_name(k).decode(): (ms[k], n[k]) for k in range(B.G4D_NUM_STAGES)}
 
 
+def _after_forward(r: Renderer, forward, backward, views) -> None:
+    """Run `backward`; if the context's saved forward is another one (G4D_ESTATE), run
+    `forward` (into scratch outputs) again first."""
+    try:
+        backward()
+        return
+    except B.G4DError as e:
+        if e.status != B.G4D_ESTATE:
+            raise
+    npix = Renderer.pixel_count_array(views)
+    forward(torch.empty(3 * npix, device=r.device), torch.empty(npix, device=r.device))
+    backward()
+
+
 class _Render4D(torch.autograd.Function):
     @staticmethod
     def forward(ctx, renderer: Renderer, views, settings, sh_degree, t_degree, mask_threshold,
@@ -295,7 +349,9 @@ class _Render4D(torch.autograd.Function):
             grads["mask"] = torch.empty_like(mask)
         if ctx.densify_out is not None:
             grads["densify"] = ctx.densify_out
-        r.backward(g, ctx.views, ctx.settings, d_rgb.contiguous(), grads)
+        _after_forward(r, lambda rgb, T: r.forward(g, ctx.views, ctx.settings, rgb, T),
+                       lambda: r.backward(g, ctx.views, ctx.settings, d_rgb.contiguous(), grads),
+                       ctx.views)
         return ((None,) * 7 + tuple(grads[k] for k in PARAM_NAMES) + (grads.get("mask"),))
 
 
@@ -330,8 +386,19 @@ class _RenderChannels(torch.autograd.Function):
             grads["features"] = torch.empty_like(features)
             if gate is not None:
                 grads["gate"] = torch.empty_like(gate)
-        r.backward_channels(g, ctx.views, ctx.settings, ch, d_rgb.contiguous(),
-                            None if d_ch is None else d_ch.contiguous(), grads)
+        E = ch.n_features + int(ctx.spec[0]) + 2 * int(ctx.spec[1])
+        npix = Renderer.pixel_count_array(ctx.views)
+
+        def refwd(rgb, T):
+            r.forward_channels(g, ctx.views, ctx.settings, ch, rgb, T,
+                               torch.empty(E * npix, device=r.device))
+
+        _after_forward(r, refwd,
+                       lambda: r.backward_channels(g, ctx.views, ctx.settings, ch,
+                                                   d_rgb.contiguous(),
+                                                   None if d_ch is None else d_ch.contiguous(),
+                                                   grads),
+                       ctx.views)
         return ((None,) * 8 + tuple(grads[k] for k in PARAM_NAMES) +
                 (grads.get("features"), grads.get("gate")))
 
@@ -359,7 +426,11 @@ class _RenderSky(torch.autograd.Function):
         g = r.gaussians(*params, *ctx.degrees)
         grads = {k: torch.empty_like(p) for k, p in zip(PARAM_NAMES, params)}
         grads["cube"] = torch.empty_like(cube)
-        r.backward_sky(g, ctx.views, ctx.settings, Renderer.sky(cube), d_rgb.contiguous(), grads)
+        sky = Renderer.sky(cube)
+        _after_forward(r, lambda rgb, T: r.forward_sky(g, ctx.views, ctx.settings, sky, rgb, T),
+                       lambda: r.backward_sky(g, ctx.views, ctx.settings, sky, d_rgb.contiguous(),
+                                              grads),
+                       ctx.views)
         return (None,) * 5 + tuple(grads[k] for k in PARAM_NAMES) + (grads["cube"],)
 
 

@@ -31,7 +31,7 @@ from typing import Dict, List
 import numpy as np
 
 __all__ = ["Scene", "WORKLOADS", "make_workload", "make_dl_dimage", "look_at", "pinhole",
-           "ring_views", "random_scene", "subset"]
+           "ring_views", "random_scene", "subset", "stress_variant"]
 
 # Constant of the degree-0 real spherical harmonic, 1 / (2 sqrt(pi)); used only to store an
 # RGB draw as the DC coefficient that reproduces it.
@@ -302,3 +302,22 @@ def subset(scene: Scene, idx) -> Scene:
                  opacity=scene.opacity[idx].copy(), sh=scene.sh[idx].copy(),
                  sh_degree=scene.sh_degree, t_degree=scene.t_degree,
                  time_period=scene.time_period, views=list(scene.views), name=scene.name)
+
+
+def stress_variant(scene: Scene, seed: int = 17, opacity=(0.95, 1.0),
+                   rotor_scale=(0.3, 3.0)) -> Scene:
+    """The scene with opacities redrawn ~U(opacity) (None keeps them) and every rotor row
+    multiplied by its own factor ~U(rotor_scale) (None keeps them unit).  High opacities make
+    o p(t) reach the alpha_max clamp; non-unit rotors exercise the normalization inside the
+    render.  Draw order: opacities, then the left and right rotor factors."""
+    rng = np.random.default_rng(seed)
+    out = subset(scene, np.arange(scene.n))
+    out.name = scene.name + "_stress"
+    if opacity is not None:
+        out.opacity = rng.uniform(opacity[0], opacity[1], scene.n).astype(np.float32)
+    if rotor_scale is not None:
+        fl = rng.uniform(rotor_scale[0], rotor_scale[1], (scene.n, 1))
+        fr = rng.uniform(rotor_scale[0], rotor_scale[1], (scene.n, 1))
+        out.rot_l = (scene.rot_l * fl).astype(np.float32)
+        out.rot_r = (scene.rot_r * fr).astype(np.float32)
+    return out

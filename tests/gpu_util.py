@@ -82,3 +82,43 @@ def oracle_frame(scene, view, **settings):
     st = dict(time_period=scene.time_period)
     st.update(settings)
     return oracle.Frame(scene.arrays(), scene.sh_degree, scene.t_degree, view, st)
+
+
+def fd_check(renderer, sc, view, dl, rng, n_subset=500, tol=1e-3, label=""):
+    """Central differences of the FP64 oracle forward against the GPU gradient on a subset of
+    Gaussians with a nonzero gradient, under the smooth settings (cutoff 5 sigma, alpha_min
+    1e-6, T_min 1e-8, marginal threshold 1e-8).  Per group, along the gradient direction
+    restricted to the subset and two random directions: |FD - <g_gpu, u>| <= tol |g_subset|."""
+    import oracle
+    smooth = dict(cutoff_sigma=5.0, alpha_min=1e-6, T_min=1e-8, marginal_min=1e-8)
+    run = GpuRun(renderer, sc, views=[view], **smooth).forward()
+    g = run.backward([dl])
+    nz = np.nonzero(np.abs(g["mean4"]).sum(1) > 0)[0]
+    subset = rng.choice(nz, size=min(n_subset, len(nz)), replace=False)
+    log(f"{label} FD subset of {len(subset)} Gaussians out of {len(nz)} with a gradient")
+    base = {k: np.asarray(a, np.float64) for k, a in sc.arrays().items()}
+    st = dict(oracle.SMOOTH_SETTINGS, time_period=sc.time_period)
+    vv = {k: (np.asarray(x, np.float64) if isinstance(x, np.ndarray) else x) for k, x in view.items()}
+
+    def L(arr):
+        with oracle.Frame(arr, sc.sh_degree, sc.t_degree, vv, st, exact_f64=True) as fr:
+            return float((fr.render()["rgb"] * dl).sum())
+
+    for name in PARAMS:
+        gs = np.zeros_like(base[name])
+        gs[subset] = g[name][subset]
+        norm = np.linalg.norm(gs)
+        if norm == 0:
+            continue
+        dirs = [gs / norm]
+        for _ in range(2):
+            d = np.zeros_like(base[name])
+            d[subset] = rng.normal(size=d[subset].shape)
+            dirs.append(d / np.linalg.norm(d))
+        for u in dirs:
+            h = 1e-4 * max(1.0, float(np.abs(base[name][subset]).max()))
+            fd = (L(dict(base, **{name: base[name] + h * u})) -
+                  L(dict(base, **{name: base[name] - h * u}))) / (2 * h)
+            an = float((g[name] * u).sum())
+            log(f"  {name}: fd {fd:.6e} gpu {an:.6e} |err|/|g| {abs(fd - an) / norm:.2e}")
+            assert abs(fd - an) <= tol * norm, (name, fd, an, norm)

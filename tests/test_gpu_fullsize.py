@@ -95,3 +95,69 @@ def test_w4_batched_sampled_pixels(renderer):
     run = GpuRun(renderer, sc, **BENCH_LAUNCH).forward()
     log(f"w4 stats {renderer.stats()}")
     check_views(sc, run, [0, 5], n=2000)
+
+
+def two_view_gradients(renderer, sc, views_idx, seed):
+    """Batched backward of all views with the upstream gradient nonzero on `views_idx` only,
+    against the oracle's backward summed over those views."""
+    rng = np.random.default_rng(seed)
+    dls = [np.zeros((3, v["height"], v["width"]), np.float32) for v in sc.views]
+    for v in views_idx:
+        dls[v] = rng.normal(size=dls[v].shape).astype(np.float32)
+    run = GpuRun(renderer, sc, **BENCH_LAUNCH).forward()
+    g = run.backward(dls)
+    ref = None
+    for v in views_idx:
+        log(f"{sc.name} oracle backward view {v}")
+        with oracle_frame(sc, sc.views[v]) as fr:
+            ref = fr.backward(dls[v], ref)
+    return parity.grad_rel_errors(g, ref)
+
+
+def test_w3_batched_gradients_two_views(renderer):
+    sc = scenes.make_workload(3)
+    errs = two_view_gradients(renderer, sc, (0, 17), seed=23)
+    log(f"w3 two-view gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
+
+
+def test_w4_batched_gradients_two_views(renderer):
+    sc = scenes.make_workload(4)
+    errs = two_view_gradients(renderer, sc, (0, 5), seed=24)
+    log(f"w4 two-view gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs
+
+
+def test_w2b_batched_sampled_pixels(renderer):
+    sc = scenes.make_workload("2b")
+    run = GpuRun(renderer, sc, **BENCH_LAUNCH).forward()
+    log(f"w2b stats {renderer.stats()}")
+    check_views(sc, run, [1, 10], n=2000)
+
+
+def test_w2_graph_replay_matches_oracle(renderer, w2):
+    # The benchmark's timed graph path: forward + backward captured once and replayed, at the
+    # benchmark launch (autotuned shape of this workload), checked against the oracle on
+    # sampled pixels of three views and the gradient of two views.
+    import torch
+    rng = np.random.default_rng(25)
+    dls = [np.zeros((3, v["height"], v["width"]), np.float32) for v in w2.views]
+    for v in (2, 3):
+        dls[v] = rng.normal(size=dls[v].shape).astype(np.float32)
+    run = GpuRun(renderer, w2, bwd_px_per_lane=8, **BENCH_LAUNCH)
+    dL = torch.from_numpy(np.concatenate([d.reshape(-1) for d in dls])).to(run.dev)
+    grads = {k: torch.empty_like(run.p[k]) for k in PARAMS}
+    for rep in range(3):
+        log(f"w2 graph replay {rep}")
+        ok = renderer.step(run.g, run.views, run.settings, dL, run.rgb, run.T, grads, graph=True)
+        assert ok
+    torch.cuda.synchronize()
+    check_views(w2, run, [2, 3, 12], n=2000)
+    g = {k: v.cpu().numpy() for k, v in grads.items()}
+    ref = None
+    for v in (2, 3):
+        with oracle_frame(w2, w2.views[v]) as fr:
+            ref = fr.backward(dls[v], ref)
+    errs = parity.grad_rel_errors(g, ref)
+    log(f"w2 graph replay two-view gradient rel err {errs}")
+    assert all(e <= 1e-3 for e in errs.values()), errs

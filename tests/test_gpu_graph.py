@@ -52,3 +52,54 @@ def test_graph_replays_match_eager(renderer):
             ref = eager_g[k].cpu().numpy()
             np.testing.assert_allclose(grads[k].cpu().numpy(), ref, rtol=1e-4,
                                        atol=1e-6 * np.abs(ref).max(), err_msg=f"{k} replay {rep}")
+
+
+def test_graph_capacity_overflow_recovers(renderer):
+    # A captured step sorts into pair buffers of fixed capacity (1.25 x the pairs found when it
+    # was captured, plus 4096).  Growing every splat in place past that capacity: the replay's
+    # device status reports G4D_ECAPACITY, the library drops the graph, Renderer.step redoes the
+    # step eagerly (its outputs equal a fresh eager step), and the next graph call captures
+    # again with a larger capacity and matches eager.
+    import torch
+    from paper_2412_20720_amd import _binding as B
+    sc = scenes.make_workload(0)
+    run = GpuRun(renderer, sc)
+    rng = np.random.default_rng(9)
+    dl = torch.from_numpy(rng.normal(size=3 * 128 * 128).astype(np.float32)).to(run.dev)
+    grads = {k: torch.empty_like(run.p[k]) for k in PARAMS}
+    assert renderer.step(run.g, run.views, run.settings, dl, run.rgb, run.T, grads, graph=True)
+    torch.cuda.synchronize()
+    cap0 = renderer.stats()["pair_capacity"]
+    n0 = GpuRun(renderer, sc).forward()
+    pairs0 = renderer.stats()["n_pairs"]
+    run.p["scale4"][:, :3].mul_(3.0)  # every splat 3x wider: about 9x the pairs
+    # raw replay without the check: the status reports the overflow once
+    renderer.step(run.g, run.views, run.settings, dl, run.rgb, run.T, grads, graph=True,
+                  check=False)
+    with pytest.raises(B.G4DError, match="ECAPACITY"):
+        renderer.sync()
+    renderer.sync()  # reported once
+    eager_rgb = torch.empty_like(run.rgb)
+    eager_T = torch.empty_like(run.T)
+    eager_g = {k: torch.empty_like(run.p[k]) for k in PARAMS}
+    renderer.forward(run.g, run.views, run.settings, eager_rgb, eager_T)
+    renderer.backward(run.g, run.views, run.settings, dl, eager_g)
+    torch.cuda.synchronize()
+    pairs1 = renderer.stats()["n_pairs"]
+    log(f"pairs {pairs0} -> {pairs1}, first capture capacity {cap0}")
+    assert pairs1 > cap0
+    # the next graph call captures again (bigger capacity) and equals the eager step
+    assert renderer.step(run.g, run.views, run.settings, dl, run.rgb, run.T, grads, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(run.rgb, eager_rgb) and torch.equal(run.T, eager_T)
+    for k in PARAMS:
+        ref = eager_g[k].cpu().numpy()
+        np.testing.assert_allclose(grads[k].cpu().numpy(), ref, rtol=1e-4,
+                                   atol=1e-6 * np.abs(ref).max(), err_msg=k)
+    # and a checked replay that overflows is redone eagerly, so its outputs are still valid
+    run.p["scale4"][:, :3].mul_(2.0)
+    assert not renderer.step(run.g, run.views, run.settings, dl, run.rgb, run.T, grads,
+                             graph=True)
+    renderer.forward(run.g, run.views, run.settings, eager_rgb, eager_T)
+    torch.cuda.synchronize()
+    assert torch.equal(run.rgb, eager_rgb)

@@ -315,3 +315,38 @@ def test_color_clamp_image_and_zero_sh_gradient(oracle_lib):
     assert grads["sh"][0, 0, 0, 0] == 0.0
     want = [(a * g[ch]).sum() * Y00 for ch in (1, 2)]
     np.testing.assert_allclose(grads["sh"][0, 0, 0, 1:], want, rtol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Failure rule: non-finite parameters
+# ------------------------------------------------------------------------------------------
+def test_nonfinite_gaussians_are_dropped(oracle_lib):
+    # A Gaussian with NaN or Inf in any parameter is dropped in every view: the image equals
+    # the image without it, and it gets no gradient.
+    from paper_2412_20720_amd import scenes
+    sc = scenes.make_workload(0)
+    arr = {k: np.asarray(v, np.float64).copy() for k, v in sc.arrays().items()}
+    idx = np.array([5, 17, 200, 333, 1000, 1500, 1999])
+    arr["mean4"][5, 0] = np.nan
+    arr["scale4"][17, 3] = np.inf
+    arr["rot_l"][200, 1] = -np.inf
+    arr["rot_r"][333, 2] = np.nan
+    arr["opacity"][1000] = np.nan
+    arr["sh"][1500, 0, 0, 1] = np.inf
+    arr["mean4"][1999, 3] = np.nan
+    keep = np.setdiff1d(np.arange(sc.n), idx)
+    sub = {k: v[keep] for k, v in arr.items()}
+    vw = sc.views[0]
+    rng = np.random.default_rng(45)
+    g = rng.normal(size=(3, 128, 128))
+    with oracle.Frame(arr, 0, 0, vw, {}, exact_f64=True) as fr:
+        out = fr.render()
+        grads = fr.backward(g)
+    with oracle.Frame(sub, 0, 0, vw, {}, exact_f64=True) as fr:
+        ref = fr.render()
+        ref_g = fr.backward(g)
+    assert np.isfinite(out["rgb"]).all()
+    assert np.array_equal(out["rgb"], ref["rgb"])
+    for k in ("mean4", "scale4", "rot_l", "rot_r", "opacity", "sh"):
+        assert np.all(grads[k][idx] == 0.0), k
+        np.testing.assert_allclose(grads[k][keep], ref_g[k], rtol=1e-10, atol=1e-12, err_msg=k)

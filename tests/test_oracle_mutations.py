@@ -99,6 +99,7 @@ MUTATIONS = [
     ("marginal cull removed", "  if (!(pt >= st.marginal_min)) cull = true;\n", "\n"),
     ("color clamp removed", "if (val(acc) < st.color_min) {", "if (false) {"),
     ("backward ignores the color clamp", "if (!sp.color_clamped[ch]) gsh[", "if (true) gsh["),
+    ("non-finite Gaussians kept", "    if (!finite) {\n      f.splats[i].alive", "    if (false) {\n      f.splats[i].alive"),
 ]
 
 
