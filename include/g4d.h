@@ -22,6 +22,7 @@
 #ifndef G4D_H
 #define G4D_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -307,6 +308,30 @@ g4d_status g4d_render_step(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view 
                            int32_t n_views, const g4d_settings *s, const float *dL_drgb,
                            float *out_rgb, float *out_T, const g4d_grads *grads, int32_t flags,
                            void *stream);
+
+/* For callers that cannot allocate device memory (code that must not call hipMalloc, such as
+ * tight serving loops or harnesses that forbid it): g4d_render_step without G4D_STEP_GRAPH,
+ * with the same arguments, outputs and numerics, whose every scratch buffer is a slice of one
+ * fixed device array of G4D_NOALLOC_SCRATCH_BYTES bytes.  Each GPU the library runs on holds
+ * its own copy of that array from the first g4d_create on it until the process ends; the call
+ * allocates no device memory and no pinned host memory (no hipMalloc, hipHostMalloc, hipFree).
+ *   Limit: the records, counts and sort buffers of N * n_views slots, the per-pixel state of
+ *   all views and the (Gaussian, tile) pairs must fit in the array together (about
+ *   124 B per slot + 8 B per pixel + 8 B per tile + 16 B per pair; a 100k-Gaussian view of
+ *   1352x1014 fits).  Sizes known before launching are rejected at once with G4D_ECAPACITY and
+ *   nothing enqueued; a pair count above what remains is found when the call reads it (it
+ *   waits on the host once, as g4d_render_forward does) and returned as G4D_ECAPACITY, the
+ *   outputs then undefined.
+ *   All calls on one GPU share its array and leave their contents in it: the call clears what
+ *   must start at zero itself, and calls that overlap on one GPU (other streams, threads or
+ *   contexts) race and give undefined results.  The call keeps no state for g4d_render_backward
+ *   and does not touch the context's own forward state.  g4d_sync_status(ctx) also reports
+ *   device-detected errors of the last such call on the device. */
+#define G4D_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+g4d_status g4d_render_step_noalloc(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
+                                   int32_t n_views, const g4d_settings *s, const float *dL_drgb,
+                                   float *out_rgb, float *out_T, const g4d_grads *grads,
+                                   void *stream);
 
 /* Wait for the context's work on `stream` and report errors found on the device
  * (G4D_ECAPACITY when the pair capacity of a captured graph was exceeded; outputs are then

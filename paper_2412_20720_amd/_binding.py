@@ -22,8 +22,9 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_stage_name", "g4d_render_step", "g4d_render_channels_forward",
             "g4d_render_channels_backward", "g4d_render_sky_forward", "g4d_render_sky_backward",
             "g4d_decode_compact", "g4d_render_compact_forward", "g4d_profile_mask",
-            "g4d_get_pairs"]
+            "g4d_get_pairs", "g4d_render_step_noalloc"]
 G4D_STEP_GRAPH = 1
+G4D_NOALLOC_SCRATCH_BYTES = 64 << 20
 G4D_NUM_STAGES = 11
 G4D_MAX_CHANNELS = 36
 
@@ -111,6 +112,9 @@ def lib() -> C.CDLL:
     L.g4d_render_step.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
                                   C.POINTER(g4d_settings), vp, vp, vp, C.POINTER(g4d_grads), i32,
                                   vp]
+    L.g4d_render_step_noalloc.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
+                                          C.POINTER(g4d_settings), vp, vp, vp,
+                                          C.POINTER(g4d_grads), vp]
     L.g4d_autotune.argtypes = [vp, C.POINTER(g4d_gaussians), C.POINTER(g4d_view), i32,
                                C.POINTER(g4d_settings), vp, vp, vp, C.POINTER(g4d_grads), i32,
                                C.POINTER(C.c_double), vp]

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,7 +22,33 @@
 
 using namespace g4d;
 
+// Device scratch of g4d_render_step_noalloc: one fixed array on every GPU the library runs on,
+// reserved when the code object is loaded and held until the process ends.  Host code never
+// uses the name itself (on the host it is a stand-in, not a device address): g4d_create looks
+// up each device's address once with hipGetSymbolAddress and the entry point passes slices of
+// that address to the kernels.
+static __device__ __align__(256) unsigned char scratch[G4D_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_looked_up[kMaxScratchDevices] = {};
+void* g_scratch_ptr[kMaxScratchDevices] = {};  // device address of `scratch` per GPU
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+
+// Once per device, with that device current.
+void lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_looked_up[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) (void)hipGetLastError();
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? p : nullptr;
+  g_scratch_looked_up[device] = true;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -86,6 +113,10 @@ struct g4d_ctx {
   // grids are sized from the capacities found by an earlier eager pass
   bool capturing = false;
   g4d_ctx* graph_ctx = nullptr;    // private context whose buffers the captured graph uses
+  // g4d_render_step_noalloc: `na` is a private context whose buffers are slices of the fixed
+  // per-device scratch array (`arena`: its buffers are never allocated, grown or freed)
+  g4d_ctx* na = nullptr;
+  bool arena = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -115,6 +146,9 @@ g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
   if (bytes == 0) bytes = 256;
   if (bytes <= b.cap) return G4D_OK;
   if (ctx->capturing) return fail(ctx, G4D_ECAPACITY, "buffer too small during graph capture");
+  if (ctx->arena)
+    return fail(ctx, G4D_ECAPACITY, "%zu bytes needed where the fixed scratch left %zu", bytes,
+                b.cap);
   const size_t want = std::max(bytes, (size_t)((double)bytes * grow));
   if (b.p) {
     G4D_HIP(hipDeviceSynchronize());
@@ -431,8 +465,8 @@ g4d_status g4d_default_settings(g4d_settings* s) {
   return G4D_OK;
 }
 
-g4d_status g4d_create(g4d_ctx** out, int device) {
-  if (!out) return G4D_EINVAL;
+// A context with its pinned staging buffers and events; device memory comes later.
+static g4d_status new_context(g4d_ctx** out, int device) {
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
@@ -455,6 +489,31 @@ g4d_status g4d_create(g4d_ctx** out, int device) {
   return G4D_OK;
 }
 
+g4d_status g4d_create(g4d_ctx** out, int device) {
+  if (!out) return G4D_EINVAL;
+  *out = nullptr;
+  g4d_ctx* ctx = nullptr;
+  g4d_status r = new_context(&ctx, device);
+  if (r != G4D_OK) return r;
+  // Set-up of g4d_render_step_noalloc (new_context left `device` current): the address of the
+  // device's fixed scratch array, and a private context whose buffers will be slices of it.
+  lookup_scratch(device);
+  g4d_ctx* na = nullptr;
+  if ((r = new_context(&na, device)) != G4D_OK) {
+    g4d_destroy(ctx);
+    return r;
+  }
+  na->arena = true;
+  // host-side storage the call fills, reserved here so that the call allocates nothing
+  na->uploaded_views.reserve(G4D_MAX_VIEWS);
+  na->key.views.reserve(G4D_MAX_VIEWS);
+  na->err.reserve(512);
+  ctx->err.reserve(512);
+  ctx->na = na;
+  *out = ctx;
+  return G4D_OK;
+}
+
 g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (!ctx) return G4D_EINVAL;
   (void)hipSetDevice(ctx->device);
@@ -463,6 +522,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->graph_ctx) g4d_destroy(ctx->graph_ctx);
+  if (ctx->na) g4d_destroy(ctx->na);
   DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->dkey,
                     &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->voff,
                     &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
@@ -470,7 +530,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
                     &ctx->grad2d, &ctx->counters, &ctx->fn, &ctx->fnorm, &ctx->flow,
                     &ctx->dfn, &ctx->skybg};
   for (DevBuf* b : bufs)
-    if (b->p) (void)hipFree(b->p);
+    if (b->p && !ctx->arena) (void)hipFree(b->p);  // an arena's buffers are scratch slices
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
   if (ctx->h_views) (void)hipHostFree(ctx->h_views);
   if (ctx->h_tile_base) (void)hipHostFree(ctx->h_tile_base);
@@ -624,6 +684,10 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       if (n_pairs > (int64_t)INT32_MAX)
         return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^31-1", (long long)n_pairs);
       const bool fits = early && n_pairs <= ctx->pair_cap;
+      if (ctx->arena && n_pairs > ctx->pair_cap)
+        return fail(ctx, G4D_ECAPACITY,
+                    "%lld (Gaussian, tile) pairs exceed the %lld the fixed scratch leaves room for",
+                    (long long)n_pairs, (long long)ctx->pair_cap);
       if (n_pairs > 0 && !fits) {
         for (int b = 0; b < 2; ++b) {
           if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
@@ -963,7 +1027,7 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
   put(grads, sizeof *grads);
   if (!ctx->graph_exec || key != ctx->graph_key) {
     if (!ctx->graph_ctx) {
-      if ((r = g4d_create(&ctx->graph_ctx, ctx->device)) != G4D_OK)
+      if ((r = new_context(&ctx->graph_ctx, ctx->device)) != G4D_OK)
         return fail(ctx, r, "cannot create the graph context");
       G4D_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     }
@@ -1023,11 +1087,113 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
   return G4D_OK;
 }
 
+// Points every buffer a plain forward + backward uses into the device's fixed scratch array
+// (256-byte aligned slices, the counters first so that they stay at offset 0 whatever the
+// sizes); the pair buffers and the sort scratch share what remains, and the pair capacity is
+// the largest that fits.
+static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, int64_t slots,
+                                int n_views, int64_t n_tiles, int64_t n_pixels) {
+  const size_t cap = G4D_NOALLOC_SCRATCH_BYTES;
+  auto round = [](size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; };
+  size_t off = 0;
+  struct Slice { DevBuf* b; size_t off, bytes; };
+  Slice plan[24];  // applied only once everything fits
+  int n_plan = 0;
+  auto take = [&](DevBuf& b, size_t bytes) {
+    plan[n_plan++] = {&b, off, round(bytes)};
+    off += round(bytes);
+  };
+  take(na->counters, 8 * sizeof(uint32_t));
+  take(na->views, sizeof(DView) * n_views);
+  take(na->tile_base, sizeof(int32_t) * (n_views + 1));
+  take(na->rec, sizeof(float) * kRec * slots);
+  take(na->tiles, sizeof(uint32_t) * slots);
+  take(na->dkey, sizeof(uint32_t) * slots);
+  for (int b = 0; b < 2; ++b) {
+    take(na->vk[b], sizeof(uint32_t) * slots);
+    take(na->vv[b], sizeof(uint32_t) * slots);
+  }
+  take(na->voff, sizeof(uint32_t) * (slots + 1));
+  take(na->scan_tmp, scan_scratch_bytes(slots));
+  take(na->ranges, sizeof(uint2) * n_tiles);
+  take(na->px_T, sizeof(float) * n_pixels);
+  take(na->px_last, sizeof(int32_t) * n_pixels);
+  take(na->grad2d, sizeof(float) * kGrad2d * slots);
+  const size_t fixed = off;
+  // pairs p need four 4-byte arrays and the radix scratch of max(p, slots) items
+  auto need = [&](int64_t p) {
+    return 4 * round(sizeof(uint32_t) * (size_t)p) +
+           round(radix_scratch_bytes(std::max<int64_t>(p, slots)));
+  };
+  if (fixed > cap || need(0) > cap - fixed)
+    return fail(ctx, G4D_ECAPACITY,
+                "%lld slots, %lld tiles and %lld pixels need %zu bytes before any pair; the "
+                "fixed scratch holds %zu (G4D_NOALLOC_SCRATCH_BYTES)",
+                (long long)slots, (long long)n_tiles, (long long)n_pixels, fixed + need(0), cap);
+  int64_t lo = 0, hi = (int64_t)((cap - fixed) / 16);
+  while (lo < hi) {  // largest p with need(p) <= cap - fixed
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (need(mid) <= cap - fixed) lo = mid; else hi = mid - 1;
+  }
+  hi = std::min<int64_t>(lo, INT32_MAX);
+  for (int b = 0; b < 2; ++b) {
+    take(na->pk[b], sizeof(uint32_t) * hi);
+    take(na->pv[b], sizeof(uint32_t) * hi);
+  }
+  take(na->sort_tmp, radix_scratch_bytes(std::max<int64_t>(hi, slots)));
+  if (off > cap) return fail(ctx, G4D_EHIP, "scratch plan of %zu bytes exceeds %zu", off, cap);
+  for (int k = 0; k < n_plan; ++k) {
+    plan[k].b->p = base + plan[k].off;
+    plan[k].b->cap = plan[k].bytes;
+  }
+  na->pair_cap = hi;
+  return G4D_OK;
+}
+
+g4d_status g4d_render_step_noalloc(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* views,
+                                   int32_t n_views, const g4d_settings* s, const float* dL_drgb,
+                                   float* out_rgb, float* out_T, const g4d_grads* grads,
+                                   void* stream) {
+  g4d_status r = check_common(ctx, g, views, n_views, s);
+  if (r != G4D_OK) return r;
+  if (!dL_drgb || !out_rgb || !grads) return fail(ctx, G4D_EINVAL, "null buffers");
+  const int dev = ctx->device;
+  unsigned char* base = (dev >= 0 && dev < kMaxScratchDevices)
+                            ? static_cast<unsigned char*>(g_scratch_ptr[dev])
+                            : nullptr;
+  if (!ctx->na || !base)
+    return fail(ctx, G4D_EHIP, "no fixed scratch on device %d: %s", dev,
+                dev < kMaxScratchDevices ? hipGetErrorString(g_scratch_err[dev])
+                                         : "device index beyond the scratch table");
+  // the sizes the forward plans (as upload_views counts them)
+  int64_t n_tiles = 0, n_pixels = 0;
+  for (int v = 0; v < n_views; ++v) {
+    n_tiles += (int64_t)((views[v].width + s->tile_size - 1) / s->tile_size) *
+               ((views[v].height + s->tile_size - 1) / s->tile_size);
+    n_pixels += (int64_t)views[v].width * views[v].height;
+  }
+  g4d_ctx* na = ctx->na;
+  if ((r = carve_scratch(ctx, na, base, (int64_t)g->n * n_views, n_views, n_tiles, n_pixels)) !=
+      G4D_OK)
+    return r;
+  // Another call may have left anything in the array: the view table is uploaded again and
+  // the gradient slots, which the raster adjoint accumulates into, are cleared.
+  na->uploaded_to = nullptr;
+  na->uploaded_views.clear();
+  na->grad2d_zero = false;
+  na->count_evals = false;
+  na->profiling = false;
+  if ((r = g4d_render_forward(na, g, views, n_views, s, out_rgb, out_T, stream)) != G4D_OK ||
+      (r = g4d_render_backward(na, g, views, n_views, s, dL_drgb, grads, stream)) != G4D_OK)
+    return fail(ctx, r, "%s", na->err.c_str());
+  return G4D_OK;
+}
+
 g4d_status g4d_sync_status(g4d_ctx* ctx, void* stream) {
   if (!ctx) return G4D_EINVAL;
   G4D_HIP(hipSetDevice(ctx->device));
   G4D_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  for (g4d_ctx* c : {ctx, ctx->graph_ctx}) {
+  for (g4d_ctx* c : {ctx, ctx->graph_ctx, ctx->na}) {
     if (!c || !c->counters.p) continue;
     uint32_t flag = 0;
     G4D_HIP(hipMemcpy(&flag, P<uint32_t>(c->counters) + 2, sizeof flag, hipMemcpyDeviceToHost));
