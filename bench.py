@@ -33,6 +33,13 @@ PEAK_HBM = 8.0e12           # MI355X HBM3E (B/s)
 FLOPS_PER_EVALUATED = 12
 FWD_FLOPS_PER_COMPOSITED = 9
 BWD_FLOPS_PER_COMPOSITED = 39
+# The per-pair figures of the hot-path scope table, charged to every candidate within the
+# plain cutoff that a pixel visits before its stop (E_alg, counted on the GPU by a forward that
+# bins by the cutoff): about 20 flops + 1 exp forward and 60 flops + 1 exp + 1 rcp backward.
+# They charge the full adjoint to candidates that fail alpha_min (which the kernels skip after
+# the 12-flop test), so they overstate the work the kernels must do; both are reported.
+ALG_FLOPS_FWD = 20
+ALG_FLOPS_BWD = 60
 WORKLOAD_KEYS = {"0": 0, "1": 1, "2": 2, "2b": "2b", "3": 3, "4": 4}
 
 
@@ -136,6 +143,15 @@ def main():
     contrib = int((cnt >> 16).sum())
     log(f"bench: visible {stats['n_visible']}, pairs {stats['n_pairs']}, evaluated pairs {evals}, "
         f"composited pairs {contrib}")
+    # E_alg: every candidate within the plain cutoff visited before the stop (the splats are
+    # binned by the cutoff for this one untimed forward; the image is the same).
+    r.eval_counters(2)
+    r.forward(g, views, settings, rgb, T)
+    cnt = r.eval_counters(False, npix).cpu().numpy().astype(np.int64)
+    e_alg = int((cnt & 0xFFFF).sum())
+    if int((cnt >> 16).sum()) != contrib:
+        raise RuntimeError("composited pairs differ between the reach and cutoff binnings")
+    log(f"bench: candidates within the cutoff up to the stop (E_alg) {e_alg}")
 
     for _ in range(args.warmup):
         step()
@@ -220,24 +236,34 @@ def main():
     sky = sky_step(r, g, views, settings, sc, dL, args, npix)
     compact = compact_forward(r, views, settings, sc, args, npix)
 
-    # Roofline of the dominant kernel (largest time per step), from the live HIP events.
+    # Roofline of the dominant kernel (largest time per step), from the live HIP events: the
+    # scope table's per-pair figure over E_alg, and beside it the itemised count of the
+    # arithmetic each evaluated and composited pair needs.
     dom = max(("raster_fwd", "raster_bwd"), key=lambda k: timed_ms.get(k, 0.0))
+    sec = timed_ms[dom] * 1e-3
+    per_pair = ALG_FLOPS_BWD if dom == "raster_bwd" else ALG_FLOPS_FWD
+    flops_alg = per_pair * e_alg
     per_comp = BWD_FLOPS_PER_COMPOSITED if dom == "raster_bwd" else FWD_FLOPS_PER_COMPOSITED
     flops = FLOPS_PER_EVALUATED * evals + per_comp * contrib
-    achieved = flops / (timed_ms[dom] * 1e-3)
     traffic = profiled_traffic(sc.name, settings) if dom == "raster_bwd" else None
-    roofline = dict(kernel=dom, bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32_VALU / 1e12,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_VALU, traffic=traffic,
-                    units={"evaluated_pairs": evals, "composited_pairs": contrib},
-                    flops_per_unit={"evaluated_pair": FLOPS_PER_EVALUATED,
-                                    "composited_pair_extra": per_comp},
-                    flops_per_launch=flops, ms_per_launch=timed_ms[dom])
+    roofline = dict(kernel=dom, bound="alu", achieved=flops_alg / sec / 1e12,
+                    peak=PEAK_FP32_VALU / 1e12, unit="TFLOP/s",
+                    frac=flops_alg / sec / PEAK_FP32_VALU, traffic=traffic,
+                    units={"e_alg_pairs": e_alg}, flops_per_unit={"pair": per_pair},
+                    flops_per_launch=flops_alg, ms_per_launch=timed_ms[dom],
+                    itemised=dict(achieved=flops / sec / 1e12, frac=flops / sec / PEAK_FP32_VALU,
+                                  units={"evaluated_pairs": evals, "composited_pairs": contrib},
+                                  flops_per_unit={"evaluated_pair": FLOPS_PER_EVALUATED,
+                                                  "composited_pair_extra": per_comp},
+                                  flops_per_launch=flops))
 
-    # Whole-path bound from the algorithmic work alone (forward + backward raster flops at the
-    # FP32 VALU peak).
-    bound_s = (2 * FLOPS_PER_EVALUATED * evals +
+    # Whole-path bound from the raster arithmetic alone at the FP32 VALU peak: the scope
+    # table's 80 flops per E_alg pair (forward + backward), and the itemised count.
+    bound_s = (ALG_FLOPS_FWD + ALG_FLOPS_BWD) * e_alg / PEAK_FP32_VALU
+    bound_i = (2 * FLOPS_PER_EVALUATED * evals +
                (FWD_FLOPS_PER_COMPOSITED + BWD_FLOPS_PER_COMPOSITED) * contrib) / PEAK_FP32_VALU
-    alg_bound = dict(mpix_s=npix / bound_s / 1e6, frac=(npix / dt / 1e6) / (npix / bound_s / 1e6),
+    alg_bound = dict(mpix_s=npix / bound_s / 1e6, frac=bound_s / dt, e_alg_per_px=e_alg / npix,
+                     itemised=dict(mpix_s=npix / bound_i / 1e6, frac=bound_i / dt),
                      evaluated_pairs_per_px=evals / npix, composited_pairs_per_px=contrib / npix)
 
     cpu = None
@@ -263,7 +289,7 @@ def main():
         "compact": compact,
         "cpu_baseline": cpu,
         "work": {"visible_slots": stats["n_visible"], "pairs": stats["n_pairs"],
-                 "evaluated_pairs": evals, "composited_pairs": contrib},
+                 "e_alg_pairs": e_alg, "evaluated_pairs": evals, "composited_pairs": contrib},
         "stages_ms": stage_ms,
     }
     print(json.dumps(out), flush=True)
@@ -427,12 +453,22 @@ def compact_forward(r, views, settings, sc, args, npix):
     return dict(forward_only=True, **out)
 
 
-def cpu_baseline(sc, n_views):
-    """The FP64 oracle, as it stands, on a bounded sample: forward + backward of the first
-    n_views views of the workload, on all host threads."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_times(sc, n_views, backward):
+    """Seconds and pixels of the FP64 oracle over the first n_views views of sc: the render,
+    and with `backward` also its gradient."""
     import oracle
     from paper_2412_20720_amd import scenes
-    dls = scenes.make_dl_dimage(sc)
+    dls = scenes.make_dl_dimage(sc) if backward else None
     t0 = time.perf_counter()
     px = 0
     for k in range(n_views):
@@ -440,13 +476,38 @@ def cpu_baseline(sc, n_views):
         with oracle.Frame(sc.arrays(), sc.sh_degree, sc.t_degree, v,
                           dict(time_period=sc.time_period)) as fr:
             fr.render()
-            fr.backward(dls[k])
+            if backward:
+                fr.backward(dls[k])
         px += v["width"] * v["height"]
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, px
+
+
+def cpu_baseline(sc, n_views):
+    """The FP64 oracle, as it stands, on a bounded sample, on all host threads: forward +
+    backward of the first n_views views of the benchmark workload (the reported value), and
+    forward-only and forward + backward times of the 2k- and 100k-Gaussian workloads and of
+    the benchmark workload's first view."""
+    import oracle
+    from paper_2412_20720_amd import scenes
+    dt, px = oracle_times(sc, n_views, True)
     log(f"bench: oracle {px / 1e6:.2f} Mpix fwd+bwd in {dt:.1f} s on {oracle.num_threads()} threads")
+    legs = {}
+    for name, s_leg, nv in (("w0", scenes.make_workload(0), 1), ("w1", scenes.make_workload(1), 1),
+                            (sc.name, sc, 1)):
+        t_f, p_f = oracle_times(s_leg, nv, False)
+        leg = dict(pixels=p_f, forward_s=t_f, forward_mpix_s=p_f / t_f / 1e6)
+        if name != sc.name:
+            t_b, _ = oracle_times(s_leg, nv, True)
+            leg.update(fwd_bwd_s=t_b, fwd_bwd_mpix_s=p_f / t_b / 1e6)
+        else:
+            leg.update(fwd_bwd_s=dt * p_f / px, fwd_bwd_mpix_s=px / dt / 1e6)
+        legs[name if name != sc.name else f"{sc.name}_view0"] = leg
+        log(f"bench: oracle {name}: forward {p_f / t_f / 1e6:.3f} Mpix/s, "
+            f"forward + backward {leg['fwd_bwd_mpix_s']:.3f} Mpix/s")
     return dict(value=px / dt / 1e6, unit="Mpix/s", cores=oracle.num_threads(), kind="oracle",
+                cpu=cpu_model(),
                 sample=f"forward+backward of the first {n_views} view(s) of {sc.name} "
-                       f"({px} pixels), FP64, OpenMP", seconds=dt)
+                       f"({px} pixels), FP64, OpenMP", seconds=dt, legs=legs)
 
 
 if __name__ == "__main__":

@@ -355,9 +355,12 @@ g4d_status g4d_get_pairs(g4d_ctx *ctx, uint32_t *tile_ids, uint32_t *slots, uint
                          void *stream);
 
 /* Per-pixel work counters of eq:4dblending: bits 0-15 hold the number of (Gaussian, pixel)
- * pairs whose Mahalanobis distance passes the cutoff and that the pixel visits before its
- * transmittance stop, bits 16-31 the number of those that were composited (both saturate at
- * 65535).  enable = 1 makes later forwards count them (one extra store per pixel), 0 stops.
+ * pairs that the pixel evaluates before its transmittance stop, bits 16-31 the number of those
+ * that were composited (both saturate at 65535).  enable = 1 makes later forwards count them
+ * (one extra store per pixel), counting the pairs within each splat's reach (the cutoff, or
+ * the smaller radius beyond which alpha < alpha_min: the pairs the backward evaluates);
+ * enable = 2 counts every pair within the plain cutoff instead, binning the splats by the
+ * cutoff for those forwards (more (Gaussian, tile) pairs, the same image); 0 stops.
  * If `out` (device, [total pixels] uint32, views concatenated) is not NULL, the counters of
  * the last counted forward are copied there (G4D_ESTATE if there is none). */
 g4d_status g4d_eval_counters(g4d_ctx *ctx, int enable, uint32_t *out, void *stream);

@@ -22,12 +22,18 @@ LIB_PATH = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 # Renderer settings (readings of the paper where it is silent; see the oracle header) and the
 # parity margins within which a discrete decision is marked as legitimately ambiguous between
-# FP32 and FP64.
+# FP32 and FP64.  Each margin is set from the FP32 error of its deciding quantity as measured
+# on the GPU against this oracle (tests check that every measured error stays within half its
+# margin): camera depth 1.9e-7 relative to max(1, z), so two depths differ by at most 3.8e-7
+# and margin_depth is 2e-6; d2 6.0e-5 relative, margin_d2 2e-4; alpha, whose relative error is
+# about half the absolute error of d2 (up to 9 margin_d2 / 2 = 9e-4 at the cutoff), margin_alpha
+# 1e-3; the final transmittance 6.2e-6 relative, margin_T 1e-4; culls (p(t) and the near
+# plane) margin_cull 1e-4.
 DEFAULT_SETTINGS: Dict[str, float] = dict(
     near_z=0.2, marginal_min=1.0 / 255.0, cutoff_sigma=3.0, blur=0.3, jacobian_margin=0.15,
     alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, color_offset=0.5, color_min=0.0,
     time_period=1.0,
-    margin_d2=2e-4, margin_alpha=1e-3, margin_T=1e-3, margin_depth=2e-5, margin_cull=1e-4,
+    margin_d2=2e-4, margin_alpha=1e-3, margin_T=1e-4, margin_depth=2e-6, margin_cull=1e-4,
 )
 
 # Smooth settings for finite differences: the jumps left are at most exp(-12.5) per pixel.
@@ -113,7 +119,7 @@ def lib() -> C.CDLL:
         L.orc_frame_render.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_frame_variants.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
-                                         C.c_void_p, C.c_void_p, C.c_void_p]
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_frame_backward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Grads),
                                          C.c_void_p, C.c_void_p]
         L.orc_frame_backward_splat.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -334,17 +340,19 @@ class Frame:
         return out
 
     def variants(self, x: int, y: int, max_marks: int = 4):
-        """All admissible (rgb, T, extra channels) of pixel (x, y), or None if it has too many
-        marked decisions."""
+        """All admissible (rgb, T, extra channels, composited count) of pixel (x, y), or None
+        if it has too many marked decisions."""
         cap = 1 << max_marks
         rgb = np.zeros((cap, 3))
         T = np.zeros(cap)
         ext = np.zeros((cap, self.n_ext))
+        nc = np.zeros(cap, np.int32)
         nv = lib().orc_frame_variants(self._h, int(x), int(y), max_marks, cap, rgb.ctypes.data,
-                                      T.ctypes.data, ext.ctypes.data if self.n_ext else None)
+                                      T.ctypes.data, ext.ctypes.data if self.n_ext else None,
+                                      nc.ctypes.data)
         if nv < 0:
             return None
-        return rgb[:nv], T[:nv], ext[:nv]
+        return rgb[:nv], T[:nv], ext[:nv], nc[:nv]
 
     def backward(self, dL_drgb: np.ndarray, grads: Optional[Dict[str, np.ndarray]] = None,
                  dL_dext: Optional[np.ndarray] = None):

@@ -1081,10 +1081,10 @@ int orc_frame_render(void* h, int n_pix, const int32_t* xy, double* rgb, double*
 }
 
 // All admissible results of one pixel: every combination of its marked decisions taken either
-// way.  Returns the number of variants written (2^marks), or -1 if the pixel has more than
+// way (color, transmittance, extra channels and composited count of each).  Returns the number of variants written (2^marks), or -1 if the pixel has more than
 // max_marks marked decisions (unverifiable), or -2 if the output buffer is too small.
 int orc_frame_variants(void* h, int px, int py, int max_marks, int max_out, double* rgb,
-                       double* T, double* ext) {
+                       double* T, double* ext, int32_t* n_contrib) {
   Frame& f = *static_cast<Frame*>(h);
   std::vector<Cand> cands;
   PixelResult base;
@@ -1100,6 +1100,7 @@ int orc_frame_variants(void* h, int px, int py, int max_marks, int max_out, doub
     composite(f, cands, base.marks, (unsigned)v, false, r, nullptr);
     for (int ch = 0; ch < 3; ++ch) rgb[3 * v + ch] = r.rgb[ch];
     if (T) T[v] = r.T;
+    if (n_contrib) n_contrib[v] = r.n_contrib;
     if (ext)
       for (int c = 0; c < f.E; ++c) ext[(size_t)v * f.E + c] = r.ext[c];
   }

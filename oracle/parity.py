@@ -60,6 +60,37 @@ def check_image(gpu_rgb: np.ndarray, frame, tol: float = 1e-4, xy: Optional[np.n
                 n_unverified=unverified, failures=failures[:20], n_failures=len(failures))
 
 
+def check_counts(gpu_counts: np.ndarray, gpu_rgb: np.ndarray, frame, xy: np.ndarray, ref,
+                 tol: float = 1e-4, max_marks: int = 4) -> Dict:
+    """Composited-pair counts at the pixels xy ([n, 2]) against the oracle's, exactly.  An
+    unmarked pixel must have the oracle's count.  A marked pixel must have the count of one of
+    the oracle's variants (its marked decisions taken either way) whose color also agrees with
+    the GPU's within tol; with more than max_marks marks it is reported as unverified."""
+    gpu_counts = np.asarray(gpu_counts).reshape(-1)
+    g = np.asarray(gpu_rgb, np.float64).reshape(-1, 3)
+    marks = ref["n_marks"]
+    clean = marks == 0
+    exact = clean & (gpu_counts == ref["n_contrib"])
+    failures = [(int(xy[p][0]), int(xy[p][1]), int(gpu_counts[p]), int(ref["n_contrib"][p]),
+                 "unmarked") for p in np.nonzero(clean & ~exact)[0]]
+    by_variant, unverified = 0, 0
+    for p in np.nonzero(~clean)[0]:
+        var = frame.variants(int(xy[p][0]), int(xy[p][1]), max_marks)
+        if var is None:
+            unverified += 1
+            continue
+        ok = (np.abs(var[0] - g[p]) <= tol).all(1) & (var[3] == gpu_counts[p])
+        if ok.any():
+            by_variant += 1
+        else:
+            failures.append((int(xy[p][0]), int(xy[p][1]), int(gpu_counts[p]),
+                             int(ref["n_contrib"][p]), "no variant"))
+    n = len(gpu_counts)
+    return dict(n=n, n_clean=int(clean.sum()), n_exact=int(exact.sum()), n_by_variant=by_variant,
+                n_unverified=unverified, verified_frac=(int(exact.sum()) + by_variant) / max(n, 1),
+                failures=failures[:20], n_failures=len(failures))
+
+
 def grad_rel_errors(gpu: Dict[str, np.ndarray], ref: Dict[str, np.ndarray]) -> Dict[str, float]:
     """Relative L2 error of every group the GPU computed (each must exist in ref)."""
     out = {}

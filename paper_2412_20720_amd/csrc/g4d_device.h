@@ -51,6 +51,7 @@ struct DSettings {
   float near_z, marginal_min, cutoff, cut2, blur, jac_margin;
   float alpha_min, alpha_max, T_min, color_offset, color_min, time_period;
   int32_t tile, tile_shift, lds_batch, px_per_lane, bwd_px_per_lane;
+  int32_t cutoff_bins;  // bin and stage every splat within the plain cutoff (work counting)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -322,8 +323,11 @@ __device__ __forceinline__ void color_forward(const float* sh, const DSettings& 
 // cannot be composited anywhere.  Binning the splat with this radius instead of the cutoff
 // leaves every image and gradient unchanged and drops the (tile, splat) pairs and the per-pixel
 // evaluations that could only fail the alpha_min test.  The preprocess (counting) and the key
-// generation (writing) evaluate it on the same stored opt with the same instructions.
+// generation (writing) evaluate it on the same stored opt with the same instructions.  With
+// S.cutoff_bins (a work-counting forward) the bound is the cutoff itself, so the counting raster
+// visits every candidate within the cutoff, as the plain definition of the render does.
 __device__ __forceinline__ float reach2(float opt, const DSettings& S) {
+  if (S.cutoff_bins) return S.cut2;
   return fminf(S.cut2, fmaf(2.002f, logf(opt / S.alpha_min), 2e-3f));
 }
 

@@ -97,6 +97,8 @@ struct g4d_ctx {
   int64_t n_tiles = 0, n_pixels = 0;
   g4d_stats stats{};
   bool count_evals = false;
+  bool count_cutoff = false;   // counting forwards bin by the plain cutoff (g4d_eval_counters 2)
+  bool fwd_cutoff_bins = false;  // the last forward binned by the plain cutoff
   bool counted_bwd = false;  // the last backward counted its clamped batches (counters[4])
   // stage profiling (stages whose bit is set in stage_mask)
   bool profiling = false;
@@ -308,8 +310,9 @@ g4d_settings run_settings(const g4d_settings* s, const g4d_channels* ch) {
   return r;
 }
 
-DSettings device_settings(const g4d_settings* s) {
+DSettings device_settings(const g4d_settings* s, bool cutoff_bins = false) {
   DSettings d{};
+  d.cutoff_bins = cutoff_bins ? 1 : 0;
   d.near_z = s->near_z;
   d.marginal_min = s->marginal_min;
   d.cutoff = s->cutoff_sigma;
@@ -413,7 +416,8 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
     Stage t(ctx, 0, st);
     GaussPtrs gp = gauss_ptrs(g);
     gp.compact = cp;
-    preprocess_forward(gp, P<DView>(ctx->views), n_views, device_settings(s),
+    preprocess_forward(gp, P<DView>(ctx->views), n_views,
+                       device_settings(s, ctx->count_evals && ctx->count_cutoff),
                        P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
   }
   G4D_HIP(hipGetLastError());
@@ -590,7 +594,8 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   if ((r = upload_views(ctx, views, n_views, s, st)) != G4D_OK) return r;
   const int64_t slots = (int64_t)g->n * n_views;
   const g4d_settings s_run = run_settings(s, ch);
-  const DSettings DS = device_settings(&s_run);
+  ctx->fwd_cutoff_bins = ctx->count_evals && ctx->count_cutoff;
+  const DSettings DS = device_settings(&s_run, ctx->fwd_cutoff_bins);
   const int n_ext = n_ext_of(ch);
   if ((r = ensure(ctx, ctx->counters, 8 * sizeof(uint32_t))) != G4D_OK) return r;
   // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity,
@@ -830,7 +835,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   }
   if (slots == 0) return G4D_OK;
   const g4d_settings s_run = run_settings(s, ch);
-  const DSettings DS = device_settings(&s_run);
+  const DSettings DS = device_settings(&s_run, ctx->fwd_cutoff_bins);
   const size_t grad2d_cap = ctx->grad2d.cap;
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
   {
@@ -1270,6 +1275,7 @@ g4d_status g4d_eval_counters(g4d_ctx* ctx, int enable, uint32_t* out, void* stre
                            hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   }
   ctx->count_evals = enable != 0;
+  ctx->count_cutoff = enable == 2;
   return G4D_OK;
 }
 

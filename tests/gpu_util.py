@@ -122,3 +122,59 @@ def fd_check(renderer, sc, view, dl, rng, n_subset=500, tol=1e-3, label=""):
             an = float((g[name] * u).sum())
             log(f"  {name}: fd {fd:.6e} gpu {an:.6e} |err|/|g| {abs(fd - an) / norm:.2e}")
             assert abs(fd - an) <= tol * norm, (name, fd, an, norm)
+
+
+def check_fp32_errors(renderer, sc, view_index, launch, n_px, seed):
+    """FP32 error of each quantity that decides a marked decision, measured on the GPU's
+    records against the oracle's FP64 splats in one view: the camera depth of every splat
+    visible on both sides (relative to max(1, z), as the depth margin), the Mahalanobis
+    distance d2 and alpha of every (splat, pixel) pair with 0.25 <= d2 <= 9 at n_px sampled
+    pixels, and the final transmittance at the sampled pixels with no marked decision (relative
+    to max(T, T_min)).  Each must be at most half its margin."""
+    import oracle
+    view = sc.views[view_index]
+    run = GpuRun(renderer, sc, views=[view], **launch)
+    rec, tiles = renderer.preprocess(run.g, run.views, run.settings)
+    rec, tiles = rec.cpu().numpy()[0].astype(np.float64), tiles.cpu().numpy()[0]
+    T_gpu = run.forward().transmittance()[0]
+    W, H = view["width"], view["height"]
+    rng = np.random.default_rng(seed)
+    xy = np.stack([rng.integers(0, W, n_px), rng.integers(0, H, n_px)], 1)
+    with oracle_frame(sc, view) as fr:
+        sp = fr.splats()
+        ref = fr.render(xy)
+    m = oracle.DEFAULT_SETTINGS
+    both = np.nonzero((tiles > 0) & (sp["alive"] == 1))[0]
+    r, s = rec[both], sp[both]
+    z_err = float((np.abs(r[:, 11] - s["depth"]) / np.maximum(1.0, np.abs(s["depth"]))).max())
+    d2_err, a_err = 0.0, 0.0
+    for k in range(0, len(xy), 100):
+        px = xy[k:k + 100, 0:1] + 0.5
+        py = xy[k:k + 100, 1:2] + 0.5
+        d2 = {}
+        for name, (u, v, a, b, c) in (("gpu", r[:, :5].T), ("ref", (s["mean2d"][:, 0],
+                                      s["mean2d"][:, 1], *s["conic"].T))):
+            dx, dy = px - u[None], py - v[None]
+            d2[name] = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        near = (d2["ref"] <= 9.0) & (d2["ref"] >= 0.25)
+        if near.any():
+            rel = np.abs(d2["gpu"] - d2["ref"])[near] / d2["ref"][near]
+            d2_err = max(d2_err, float(rel.max()))
+            opt_g = np.broadcast_to(r[:, 5][None], near.shape)[near]
+            opt_r = np.broadcast_to(s["opt"][None], near.shape)[near]
+            ag = opt_g * np.exp(-0.5 * d2["gpu"][near])
+            ar = opt_r * np.exp(-0.5 * d2["ref"][near])
+            a_err = max(a_err, float((np.abs(ag - ar) / ar).max()))
+    clean = ref["n_marks"] == 0
+    Tg = T_gpu[xy[:, 1], xy[:, 0]][clean]
+    Tr = ref["T"][clean]
+    T_err = float((np.abs(Tg - Tr) / np.maximum(Tr, m["T_min"])).max())
+    log(f"{sc.name} view {view_index} FP32 errors: depth {z_err:.2e} (margin "
+        f"{m['margin_depth']:.0e}), d2 {d2_err:.2e} (margin {m['margin_d2']:.0e}), alpha "
+        f"{a_err:.2e} (margin {m['margin_alpha']:.0e}), T {T_err:.2e} (margin "
+        f"{m['margin_T']:.0e}); unmarked pixels {clean.mean():.3f}")
+    assert z_err <= 0.5 * m["margin_depth"]
+    assert d2_err <= 0.5 * m["margin_d2"]
+    assert a_err <= 0.5 * m["margin_alpha"]
+    assert T_err <= 0.5 * m["margin_T"]
+    return dict(depth=z_err, d2=d2_err, alpha=a_err, T=T_err, unmarked=float(clean.mean()))

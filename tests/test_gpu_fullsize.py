@@ -5,7 +5,7 @@ gradient against the oracle's backward, and batched launches against per-view la
 import numpy as np
 import pytest
 
-from gpu_util import PARAMS, GpuRun, log, oracle_frame
+from gpu_util import PARAMS, GpuRun, check_fp32_errors, log, oracle_frame
 from oracle import parity
 from paper_2412_20720_amd import scenes
 
@@ -55,6 +55,37 @@ def test_w2_batched_sampled_pixels(renderer, w2):
     run = GpuRun(renderer, w2, **BENCH_LAUNCH).forward()
     log(f"w2 stats {renderer.stats()}")
     check_views(w2, run, [0, 1, 9])
+
+
+def test_w2_fp32_errors_within_parity_margins(renderer, w2):
+    # the FP32 errors of the deciding quantities at the benchmark size (one 1352x1014 and one
+    # 800x800 view of the 300k-Gaussian workload), each at most half its parity margin
+    check_fp32_errors(renderer, w2, 0, BENCH_LAUNCH, 2000, seed=81)
+    check_fp32_errors(renderer, w2, 1, BENCH_LAUNCH, 2000, seed=82)
+
+
+def test_w2_batched_pair_counts(renderer, w2):
+    # Composited-pair counts of the batched benchmark launch, exactly: an unmarked pixel has the
+    # oracle's count, a marked one the count of the oracle variant whose color it produced.
+    run = GpuRun(renderer, w2, **BENCH_LAUNCH)
+    npix = run.T.numel()
+    renderer.eval_counters(True)
+    run.forward()
+    cnt = renderer.eval_counters(False, npix).cpu().numpy().astype(np.int64)
+    imgs = run.images()
+    offs = np.cumsum([0] + [v["width"] * v["height"] for v in w2.views])
+    for v in (0, 1):
+        W = w2.views[v]["width"]
+        xy = sample_pixels(w2.views[v], 1500, seed=40 + v)
+        contrib = cnt[offs[v] + xy[:, 1] * W + xy[:, 0]] >> 16
+        rgb = imgs[v][:, xy[:, 1], xy[:, 0]].T
+        with oracle_frame(w2, w2.views[v]) as fr:
+            ref = fr.render(xy)
+            rep = parity.check_counts(contrib, rgb, fr, xy, ref, 1e-4)
+        log(f"w2 view {v} counts: {rep['n_exact']} unmarked + {rep['n_by_variant']} marked of "
+            f"{rep['n']}, unverified {rep['n_unverified']}, failures {rep['n_failures']} "
+            f"{rep['failures'][:3]}")
+        assert rep["n_failures"] == 0 and rep["verified_frac"] >= 0.9
 
 
 def test_w2_batched_gradients_two_views(renderer, w2):
