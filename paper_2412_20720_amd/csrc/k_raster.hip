@@ -120,13 +120,12 @@ struct WaveTile {
   uint2 range;
 };
 
-// Map this wave to (tile, block of BW x BH pixels).  TILE is a multiple of BW and BH.
+// Map logical wave gw to (tile, block of BW x BH pixels).  TILE is a multiple of BW and BH.
 template <int TILE, int BW, int BH>
-__device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
+__device__ __forceinline__ bool wave_tile_at(const RasterArgs& a, int gw, WaveTile& t) {
   constexpr int QX = TILE / BW, QPT = QX * (TILE / BH);
   t.lane = threadIdx.x & 63;
   t.w = threadIdx.x >> 6;
-  const int gw = __builtin_amdgcn_readfirstlane(xcd_logical_block(a.blocks_per_xcd) * 4 + t.w);
   t.tile = gw / QPT;
   if (t.tile >= a.n_tiles) return false;
   const int q = gw - t.tile * QPT;
@@ -142,6 +141,14 @@ __device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
   t.qy1 = (float)(t.by + BH) - 0.5f;
   t.range = a.ranges[t.tile];
   return true;
+}
+
+// The grid's own mapping: logical wave (XCD-aware logical block) * 4 + wave in the workgroup.
+template <int TILE, int BW, int BH>
+__device__ __forceinline__ bool wave_tile(const RasterArgs& a, WaveTile& t) {
+  const int gw = __builtin_amdgcn_readfirstlane(xcd_logical_block(a.blocks_per_xcd) * 4 +
+                                                (int)(threadIdx.x >> 6));
+  return wave_tile_at<TILE, BW, BH>(a, gw, t);
 }
 
 // Fetch list entry j (if in range) and keep it if its box reaches the wave's pixel block.
@@ -257,20 +264,17 @@ struct LanePixels {
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 template <int TILE, int BATCH, int PXX, int PXY, bool COUNT, int CX>
-__global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
+__device__ __forceinline__ void raster_fwd_wave(const RasterArgs& a, const WaveTile& t,
+                                                Staged* st, float* xp) {
   constexpr int P = PXX * PXY;
   // with extra channels a lane's pixels form one group (see the header)
   constexpr int kGroup = CX > 0 ? P : (kSlotGroup < P ? kSlotGroup : P);
   constexpr int XC = CX > 0 ? CX : 1;
-  __shared__ Staged stage[4][BATCH];
-  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
   float X[P][XC];
 #pragma unroll
   for (int p = 0; p < P; ++p)
 #pragma unroll
     for (int c = 0; c < XC; ++c) X[p][c] = 0.f;
-  WaveTile t;
-  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
   const DSettings& S = a.S;
   LanePixels<PXX, PXY> L;
@@ -295,8 +299,6 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
     any_live |= L.inside[p];
   }
   bool done = __ballot(any_live) == 0ull;
-  Staged* st = stage[t.w];
-  float* xp = xstage[t.w];
   const int end = (int)t.range.y;
   for (int base = (int)t.range.x; base < end && !done; base += BATCH) {
     bool clamp_free;  // not used here: a second copy of the loop costs the forward occupancy
@@ -412,6 +414,20 @@ __global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
   }
 }
 
+// One wave per (tile, block), mapped from its workgroup (XCD-aware).  A persistent grid whose
+// waves take (tile, block) items from per-XCD atomic work queues was measured on the
+// 300k-Gaussian, 16-view workload and was slower (raster_fwd 0.97 -> 1.53 ms, raster_bwd 1.99 ->
+// 2.18 ms): the hardware dispatcher already balances the short, uneven waves.
+template <int TILE, int BATCH, int PXX, int PXY, bool COUNT, int CX>
+__global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs a) {
+  __shared__ Staged stage[4][BATCH];
+  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
+  const int w = threadIdx.x >> 6;
+  WaveTile t;
+  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
+  raster_fwd_wave<TILE, BATCH, PXX, PXY, COUNT, CX>(a, t, stage[w], xstage[w]);
+}
+
 // Transpose-reduce of nine per-lane values over the wave.  v_permlane32_swap exchanges the
 // upper 32 lanes of one register with the lower 32 lanes of another, so one swap and one add
 // fold two values at once (value a over lanes 0-31, value b over lanes 32-63); a
@@ -472,16 +488,13 @@ __device__ __forceinline__ void wave_reduce_rows(const float* q, float* r) {
 // 5.3 ms), the extra-channel backward for 3 (its 35-channel variant drops from 197 to 168
 // VGPRs with a few spills, 15.05 -> 13.64 ms; 3 blocks of its 48 KB of LDS fit a CU anyway).
 template <int TILE, int BATCH, int PXX, int PXY, int CX>
-__global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs a) {
+__device__ __forceinline__ void raster_bwd_wave(const RasterArgs& a, const WaveTile& t,
+                                                Staged* st, float* xp) {
   constexpr int P = PXX * PXY;
   static_assert(CX % 4 == 0, "extra channels come in groups of four");
   constexpr int kGroup = CX > 0 ? P : (kSlotGroup < P ? kSlotGroup : P);
   constexpr int XC = CX > 0 ? CX : 1;
-  __shared__ Staged stage[4][BATCH];
-  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
   float gx[P][XC];  // upstream gradient of the extra channels per pixel (0: flow, padding)
-  WaveTile t;
-  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
   const DView& V = a.views[t.v];
   const DSettings& S = a.S;
   LanePixels<PXX, PXY> L;
@@ -540,8 +553,6 @@ __global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs 
   if (hi_last < 0) return;
   // entries at or before every pixel's last composited one need no per-pixel position test
   const int lo_last = __builtin_amdgcn_readfirstlane(wave_min(lane_first));
-  Staged* st = stage[t.w];
-  float* xp = xstage[t.w];
   const int lo_list = (int)t.range.x;
   for (int hi = hi_last + 1; hi > lo_list; hi -= BATCH) {
     const int lo = max(lo_list, hi - BATCH);
@@ -689,6 +700,16 @@ __global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs 
     }
     G4D_WAVE_SYNC();
   }
+}
+
+template <int TILE, int BATCH, int PXX, int PXY, int CX>
+__global__ __launch_bounds__(256, CX == 0 ? 4 : 3) void k_raster_bwd(RasterArgs a) {
+  __shared__ Staged stage[4][BATCH];
+  __shared__ float xstage[4][CX > 0 ? BATCH * CX : 1];
+  const int w = threadIdx.x >> 6;
+  WaveTile t;
+  if (!wave_tile<TILE, 8 * PXX, 8 * PXY>(a, t)) return;
+  raster_bwd_wave<TILE, BATCH, PXX, PXY, CX>(a, t, stage[w], xstage[w]);
 }
 
 // Grid of 4-wave workgroups, one wave per (8 PXX) x (8 PXY) block of every tile, padded to a
