@@ -33,7 +33,13 @@ enum RecField {
 };
 // Screen-space gradient slot layout: d/du, d/dv, d/da, d/db, d/dc, d/d(opacity p_t), d/drgb.
 // G_DEPTH: dL/d(camera depth), from the depth channel of the extra-channel render (0 otherwise).
-enum GradField { G_U = 0, G_V = 1, G_A = 2, G_B = 3, G_C = 4, G_OPT = 5, G_R = 6, G_DEPTH = 9 };
+// The color adjoint replaces d/drgb by the color's dL/dmu_c (G_MUC, 3 floats) and writes its
+// dL/d(t - mu_t) to G_DT, which the geometry adjoint then reads; fields 10 and 11 are zero
+// between backwards.
+enum GradField {
+  G_U = 0, G_V = 1, G_A = 2, G_B = 3, G_C = 4, G_OPT = 5, G_R = 6, G_DEPTH = 9,
+  G_MUC = 6, G_DT = 10
+};
 
 struct DView {
   float W[9];        // world-to-camera rotation, row-major
@@ -211,26 +217,52 @@ struct ViewFwd {
 // Slice and splat; returns false when the Gaussian is culled in this view.  With kCull the
 // function stops at the first cull; without it every field is computed (used by the adjoint,
 // which must not depend on re-deciding a cull).
+// View-independent slice constants: 1 / Sigma_44 and sigma = Sigma_{1:3,4} = M_{1:3} m^T.
+__device__ __forceinline__ void slice_consts(const Geom& g, float& inv_s, float sigma[3]) {
+  const float* m = g.M[3];
+  const float s44 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
+  inv_s = 1.f / s44;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float* Mi = g.M[i];
+    sigma[i] = Mi[0] * m[0] + Mi[1] * m[1] + Mi[2] * m[2] + Mi[3] * m[3];
+  }
+}
+
+// Conditional mean at the view's time (dt = t - mu_t, k = dt / Sigma_44) and the unit view
+// direction from the camera centre (1 / |mu_c - C| in idn).  The forward, its recomputation
+// in the adjoint and the color adjoint all call this, so they agree bit for bit.
+__device__ __forceinline__ void slice_mean_dir(const float4 mean, float inv_s, const float* sigma,
+                                               const DView& V, float& dt, float& k,
+                                               float* muc, float* dir, float& idn) {
+  dt = V.t - mean.w;
+  k = dt * inv_s;
+  const float mu[3] = {mean.x, mean.y, mean.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) muc[i] = fmaf(sigma[i], k, mu[i]);
+  float d[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) d[i] = muc[i] - V.C[i];
+  idn = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dir[i] = d[i] * idn;
+}
+
 template <bool kCull = true>
 __device__ __forceinline__ bool view_forward(const Geom& g, const float4 mean, const DView& V,
                                              const DSettings& S, ViewFwd& f) {
   bool alive = true;
   const float* m = g.M[3];
-  const float s44 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
-  f.inv_s = 1.f / s44;
-  f.dt = V.t - mean.w;
-  f.k = f.dt * f.inv_s;
+  slice_consts(g, f.inv_s, f.sigma);
+  slice_mean_dir(mean, f.inv_s, f.sigma, V, f.dt, f.k, f.muc, f.dir, f.idn);
   f.pt = __expf(-0.5f * f.dt * f.k);
   if (!(f.pt >= S.marginal_min)) {
     if (kCull) return false;
     alive = false;
   }
-  const float mu[3] = {mean.x, mean.y, mean.z};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const float* Mi = g.M[i];
-    f.sigma[i] = Mi[0] * m[0] + Mi[1] * m[1] + Mi[2] * m[2] + Mi[3] * m[3];
-    f.muc[i] = fmaf(f.sigma[i], f.k, mu[i]);
     const float c = f.sigma[i] * f.inv_s;
 #pragma unroll
     for (int j = 0; j < 4; ++j) f.A[i][j] = fmaf(-c, m[j], Mi[j]);
@@ -282,13 +314,12 @@ __device__ __forceinline__ bool view_forward(const Geom& g, const float4 mean, c
   f.conic[0] = f.cov[2] * idet;
   f.conic[1] = -f.cov[1] * idet;
   f.conic[2] = f.cov[0] * idet;
-  float d[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) d[i] = f.muc[i] - V.C[i];
-  f.idn = rsqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) f.dir[i] = d[i] * f.idn;
   return alive;
+}
+
+// Fourier factor cos(2 pi n dt / T) of the 4DSH time basis (1 for n = 0).
+__device__ __forceinline__ float fourier_cos(int n, float dt, const DSettings& S) {
+  return (n == 0) ? 1.f : __cosf(6.283185307179586f * (float)n * dt / S.time_period);
 }
 
 // 4DSH color of one view; `sh` holds the (DT+1) x (DS+1)^2 x 3 coefficients of the Gaussian.
@@ -300,7 +331,7 @@ __device__ __forceinline__ void color_forward(const float* sh, const DSettings& 
   float acc[3] = {S.color_offset, S.color_offset, S.color_offset};
 #pragma unroll
   for (int n = 0; n <= DT; ++n) {
-    const float fn = (n == 0) ? 1.f : __cosf(6.283185307179586f * (float)n * f.dt / S.time_period);
+    const float fn = fourier_cos(n, f.dt, S);
     float in[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < NK; ++k)
@@ -438,60 +469,18 @@ __device__ __forceinline__ float coverage_limit(float opt, const DSettings& S) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Adjoint of one view.  Inputs: the screen-space gradient q[0..8] of (u, v, conic a, b, c,
-// opacity p_t, rgb) and the forward state f.  Outputs are accumulated: gM (4x4, w.r.t. M),
-// gmean (4), gopacity, gsh (coefficient gradient, DT+1 x NK x 3).
+// Adjoint of one view, geometry part.  Inputs: the screen-space gradient q (u, v, conic a, b,
+// c, opacity p_t at G_U..G_OPT, camera depth at G_DEPTH), the color's contribution to dL/dmu_c
+// (gmuc_color) and to dL/d(dt) (gdt_color) through the view direction and the Fourier factors,
+// and the forward state f.  Outputs are accumulated: gM (4x4, w.r.t. M), gmean (4), gopacity.
 // ------------------------------------------------------------------------------------------
-template <int DS, int DT>
-__device__ __forceinline__ void view_backward(const Geom& g, const float4 mean, float opacity,
-                                              const float* sh, const DView& V,
-                                              const DSettings& S, const ViewFwd& f,
-                                              const float* q, float gM[4][4], float gmean[4],
-                                              float& gopacity, float* gsh) {
-  constexpr int NK = (DS + 1) * (DS + 1);
-  // ---- color ----
-  float graw[3];
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) graw[ch] = (f.raw[ch] < S.color_min) ? 0.f : q[G_R + ch];
-  float Y[NK];
-  sh_basis<DS>(f.dir[0], f.dir[1], f.dir[2], Y);
-  float w[NK];
-#pragma unroll
-  for (int k = 0; k < NK; ++k) w[k] = 0.f;
-  float gdt = 0.f;
-  const float om = 6.283185307179586f / S.time_period;
-#pragma unroll
-  for (int n = 0; n <= DT; ++n) {
-    float fn = 1.f, dfn = 0.f;
-    if (n > 0) {
-      float sn, cn;
-      __sincosf(om * (float)n * f.dt, &sn, &cn);
-      fn = cn;
-      dfn = -om * (float)n * sn;
-    }
-    float dotn = 0.f;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      float wk = 0.f;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        const float c = sh[(n * NK + k) * 3 + ch];
-        gsh[(n * NK + k) * 3 + ch] = fmaf(graw[ch] * fn, Y[k], gsh[(n * NK + k) * 3 + ch]);
-        wk = fmaf(graw[ch], c, wk);
-      }
-      w[k] = fmaf(fn, wk, w[k]);
-      dotn = fmaf(wk, Y[k], dotn);
-    }
-    gdt = fmaf(dfn, dotn, gdt);
-  }
-  float gdir[3];
-  sh_basis_vjp<DS>(f.dir[0], f.dir[1], f.dir[2], w, gdir[0], gdir[1], gdir[2]);
-  float gmuc[3];
-  {
-    const float pr = gdir[0] * f.dir[0] + gdir[1] * f.dir[1] + gdir[2] * f.dir[2];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) gmuc[i] = (gdir[i] - f.dir[i] * pr) * f.idn;
-  }
+__device__ __forceinline__ void view_backward_geom(const Geom& g, float opacity, const DView& V,
+                                                   const ViewFwd& f, const float* q,
+                                                   const float* gmuc_color, float gdt_color,
+                                                   float gM[4][4], float gmean[4],
+                                                   float& gopacity) {
+  float gmuc[3] = {gmuc_color[0], gmuc_color[1], gmuc_color[2]};
+  const float gdt = gdt_color;
   // ---- opacity * p_t ----
   gopacity = fmaf(q[G_OPT], f.pt, gopacity);
   float gpt = q[G_OPT] * opacity;

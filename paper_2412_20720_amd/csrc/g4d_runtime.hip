@@ -834,7 +834,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   {
     Stage t(ctx, 10, st);
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
-                        P<float>(ctx->grad2d), gp, st);
+                        P<float>(ctx->rec), P<float>(ctx->grad2d), gp, st);
     G4D_HIP(hipGetLastError());
   }
   ctx->grad2d_zero = true;

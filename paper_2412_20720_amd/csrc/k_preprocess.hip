@@ -141,14 +141,26 @@ __global__ __launch_bounds__(256) void k_preprocess(
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Adjoint of the preprocess: one thread per Gaussian loops over the views it is listed in (the
+// gradient slots the raster adjoint filled), recomputes the view's slice and splat, and
+// propagates the slot's gradient through the 4DSH color, the EWA splat, the projection and the
+// slice to M = R S, the mean, the opacity and the coefficients, summing over the views; at the
+// end it goes through the rotors and their normalization and writes every gradient once.  The
+// clamp at color_min is read from the color the forward stored: max(color_min, raw) equals
+// color_min where the clamp was taken (at raw = color_min exactly, the kink, the derivative is
+// taken as 0), and there the color passes no gradient; so the raw color is not rebuilt.
+// Each slot is zeroed once read, so the slots need no clearing before the next backward.
+// ------------------------------------------------------------------------------------------
 template <int DS, int DT>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(
     int n, int n_views, const float4* __restrict__ mean4, const float4* __restrict__ scale4,
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, const uint32_t* __restrict__ tiles,
-    float* __restrict__ grad2d, GradPtrs out) {
-  constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
+    const float* __restrict__ rec, float* __restrict__ grad2d, GradPtrs out) {
+  constexpr int NK = (DS + 1) * (DS + 1);
+  constexpr int NSH = (DT + 1) * NK * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n) return;
   const float4 sc = scale4[gi];
@@ -172,9 +184,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   float gop = 0.f;
   float dens = 0.f;  // sum over listed views of |dL/d(u, v)|
   int nvis = 0;
+  const float om = 6.283185307179586f / S.time_period;
   // Views in chunks of 32: the chunk's listing flags are loaded together, and each view's
-  // gradient slot is loaded one view ahead, so that its latency overlaps the current view's
-  // arithmetic (one wave per SIMD leaves nothing else to hide it).
+  // gradient slot and stored color are loaded one view ahead, so that their latency overlaps
+  // the current view's arithmetic (one wave per SIMD leaves nothing else to hide it).
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int v0 = 0; v0 < n_views; v0 += 32) {
     const int nv = n_views - v0 < 32 ? n_views - v0 : 32;
@@ -182,21 +195,23 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     for (int j = 0; j < nv; ++j)
       listed |= (tiles[(size_t)(v0 + j) * n + gi] != 0u ? 1u : 0u) << j;
     float4 p0 = z, p1 = z, p2 = z;
-    if (listed & 1u) {
-      const float4* gp = reinterpret_cast<const float4*>(grad2d + ((size_t)v0 * n + gi) * kGrad2d);
+    float pc[3] = {0.f, 0.f, 0.f};
+    auto fetch = [&](int v) {
+      const size_t sl = (size_t)v * n + gi;
+      const float4* gp = reinterpret_cast<const float4*>(grad2d + sl * kGrad2d);
       p0 = gp[0];
       p1 = gp[1];
       p2 = gp[2];
-    }
+      const float* col = rec + sl * kRec + R_R;
+      pc[0] = col[0];
+      pc[1] = col[1];
+      pc[2] = col[2];
+    };
+    if (listed & 1u) fetch(v0);
     for (int j = 0; j < nv; ++j) {
       const float4 q0 = p0, q1 = p1, q2 = p2;
-      if (j + 1 < nv && ((listed >> (j + 1)) & 1u)) {
-        const float4* gp =
-            reinterpret_cast<const float4*>(grad2d + ((size_t)(v0 + j + 1) * n + gi) * kGrad2d);
-        p0 = gp[0];
-        p1 = gp[1];
-        p2 = gp[2];
-      }
+      const float col[3] = {pc[0], pc[1], pc[2]};
+      if (j + 1 < nv && ((listed >> (j + 1)) & 1u)) fetch(v0 + j + 1);
       if (!((listed >> j) & 1u)) continue;
       const int v = v0 + j;
       // the raster adjoint accumulates only into listed slots, so zeroing each listed slot once
@@ -207,22 +222,61 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
       gz[2] = z;
       dens += sqrtf(fmaf(q0.x, q0.x, q0.y * q0.y));
       ++nvis;
-      const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y};
       const DView& V = views[v];
       ViewFwd f;
       view_forward<false>(g, mean, V, S, f);
-      color_forward<DS, DT>(shc, S, f);
-      view_backward<DS, DT>(g, mean, op, shc, V, S, f, q, gM, gmean, gop, gsh);
+      // ---- 4DSH color: dL/dk, and the color's share of dL/d(direction) and dL/d(dt) ----
+      const float graw[3] = {(col[0] == S.color_min) ? 0.f : q1.z,
+                             (col[1] == S.color_min) ? 0.f : q1.w,
+                             (col[2] == S.color_min) ? 0.f : q2.x};
+      float Y[NK], w[NK];
+      sh_basis<DS>(f.dir[0], f.dir[1], f.dir[2], Y);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) w[k] = 0.f;
+      float gdt = 0.f;
+#pragma unroll
+      for (int t = 0; t <= DT; ++t) {
+        float ft = 1.f, dft = 0.f;
+        if (t > 0) {
+          float sn, cn;
+          __sincosf(om * (float)t * f.dt, &sn, &cn);
+          ft = cn;
+          dft = -om * (float)t * sn;
+        }
+        float dot = 0.f;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          float wk = 0.f;
+          const float fy = ft * Y[k];
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const int idx = (t * NK + k) * 3 + ch;
+            gsh[idx] = fmaf(graw[ch], fy, gsh[idx]);
+            wk = fmaf(graw[ch], shc[idx], wk);
+          }
+          w[k] = fmaf(ft, wk, w[k]);
+          dot = fmaf(wk, Y[k], dot);
+        }
+        gdt = fmaf(dft, dot, gdt);
+      }
+      float gd[3];
+      sh_basis_vjp<DS>(f.dir[0], f.dir[1], f.dir[2], w, gd[0], gd[1], gd[2]);
+      const float pr = gd[0] * f.dir[0] + gd[1] * f.dir[1] + gd[2] * f.dir[2];
+      float gmuc[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gmuc[a] = (gd[a] - f.dir[a] * pr) * f.idn;
+      // ---- geometry ----
+      const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, 0.f, 0.f, 0.f, q2.y};
+      view_backward_geom(g, op, V, f, q, gmuc, gdt, gM, gmean, gop);
     }
   }
   if (nvis == 0) {
     // listed in no view (culled, masked or off screen): every gradient is exactly zero, also
     // for parameters that are not finite (their forward culled them)
-    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = z4;
-    if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = z4;
-    if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = z4;
-    if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = z4;
+    if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = z;
+    if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = z;
+    if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = z;
+    if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = z;
     if (out.opacity) out.opacity[gi] = 0.f;
     if (out.mask) out.mask[gi] = 0.f;
     if (out.densify) {
@@ -322,14 +376,14 @@ void dispatch_decode_t(int n, int dt, const CompactPtrs& cp, float* mean4, float
 
 template <int DS, int DT>
 void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                const uint32_t* tiles, float* grad2d, const GradPtrs& out, hipStream_t st) {
-  const int blocks = (gp.n + 255) / 256;
-  hipLaunchKernelGGL((k_preprocess_bwd<DS, DT>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
-                     reinterpret_cast<const float4*>(gp.mean4),
+                const uint32_t* tiles, const float* rec, float* grad2d, const GradPtrs& out,
+                hipStream_t st) {
+  hipLaunchKernelGGL((k_preprocess_bwd<DS, DT>), dim3((unsigned)((gp.n + 255) / 256)), dim3(256),
+                     0, st, gp.n, n_views, reinterpret_cast<const float4*>(gp.mean4),
                      reinterpret_cast<const float4*>(gp.scale4),
                      reinterpret_cast<const float4*>(gp.rot_l),
                      reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
-                     tiles, grad2d, out);
+                     tiles, rec, grad2d, out);
 }
 
 template <int DS>
@@ -344,12 +398,12 @@ void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 
 template <int DS>
 void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S,
-                    const uint32_t* tiles, float* grad2d, const GradPtrs& out,
+                    const uint32_t* tiles, const float* rec, float* grad2d, const GradPtrs& out,
                     hipStream_t st) {
   switch (gp.t_degree) {
-    case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, grad2d, out, st); break;
-    case 1: launch_bwd<DS, 1>(gp, views, nv, S, tiles, grad2d, out, st); break;
-    default: launch_bwd<DS, 2>(gp, views, nv, S, tiles, grad2d, out, st); break;
+    case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
+    case 1: launch_bwd<DS, 1>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
+    default: launch_bwd<DS, 2>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
   }
 }
 
@@ -379,14 +433,14 @@ void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs
 }
 
 void preprocess_backward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                         const uint32_t* tiles, float* grad2d, const GradPtrs& out,
-                         hipStream_t st) {
+                         const uint32_t* tiles, const float* rec, float* grad2d,
+                         const GradPtrs& out, hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {
-    case 0: dispatch_bwd_t<0>(gp, views, n_views, S, tiles, grad2d, out, st); break;
-    case 1: dispatch_bwd_t<1>(gp, views, n_views, S, tiles, grad2d, out, st); break;
-    case 2: dispatch_bwd_t<2>(gp, views, n_views, S, tiles, grad2d, out, st); break;
-    default: dispatch_bwd_t<3>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    case 0: dispatch_bwd_t<0>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
+    case 1: dispatch_bwd_t<1>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
+    case 2: dispatch_bwd_t<2>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
+    default: dispatch_bwd_t<3>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
   }
 }
 

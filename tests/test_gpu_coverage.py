@@ -129,3 +129,38 @@ def test_nonfinite_parameters_are_culled_with_zero_gradient(renderer):
     log(f"non-finite parameters: image failures {rep['n_failures']}, gradient rel err {errs}")
     assert rep["n_failures"] == 0
     assert all(e <= 1e-3 for e in errs.values()), errs
+
+
+@pytest.mark.parametrize("wl", [0, 1])
+def test_color_clamp_gradients(renderer, wl):
+    # The 4DSH color is clamped at color_min (read as max(0, 0.5 + sum), Sec. 3.2 with the
+    # rasterizer conventions the paper adopts): a third of the Gaussians get a direct component
+    # of -2.5 / Y00 in one channel, far below any view-dependent term, so that channel is
+    # clamped in every view.  Image and gradients match the oracle, and the clamped channel's
+    # coefficients get exactly zero gradient.
+    sc = scenes.make_workload(wl)
+    if wl == 1:
+        sc = scenes.subset(sc, np.arange(0, sc.n, 5))
+        sc.views = [dict(sc.views[0], width=320, height=240, fx=np.float32(343.1),
+                         fy=np.float32(343.1), cx=np.float32(160.0), cy=np.float32(120.0))]
+    rng = np.random.default_rng(31)
+    idx = rng.choice(sc.n, sc.n // 3, replace=False)
+    ch = rng.integers(0, 3, len(idx))
+    sc.sh = sc.sh.copy()
+    sc.sh[idx, 0, 0, ch] = np.float32(-2.5 / 0.28209479177387814)
+    v = sc.views[0]
+    dl = [np.random.default_rng(32).normal(size=(3, v["height"], v["width"])).astype(np.float32)]
+    run = GpuRun(renderer, sc).forward()
+    img = run.images()[0]
+    g = run.backward(dl)
+    with oracle_frame(sc, v) as fr:
+        rep = parity.check_image(img, fr, 1e-4)
+        ref = fr.backward(dl[0])
+    errs = parity.grad_rel_errors(g, ref)
+    clamped = g["sh"][idx, :, :, ch]
+    log(f"w{wl} color clamp: {len(idx)} clamped channels, image failures {rep['n_failures']}, "
+        f"max |sh grad| of clamped channels {np.abs(clamped).max():.1e}, gradient rel err {errs}")
+    assert rep["n_failures"] == 0
+    assert np.all(clamped == 0.0)
+    assert np.abs(g["sh"]).max() > 0
+    assert all(e <= 1e-3 for e in errs.values()), errs
