@@ -31,11 +31,13 @@ void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_
 // Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
 // n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.  Keys of
 // 32 or 16 bits (the tile ids of a batch with fewer than 2^16 tiles move as 16-bit keys).
+// `wide` takes workgroups of 8,192 items instead of 4,096 (long sorts: longer digit runs in
+// the scatter; short ones keep more workgroups).  The scratch size serves either.
 size_t radix_scratch_bytes(int64_t n_cap);
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, void* scratch, hipStream_t st);
+               int bits, bool wide, void* scratch, hipStream_t st);
 int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, void* scratch, hipStream_t st);
+               int bits, bool wide, void* scratch, hipStream_t st);
 
 // One (tile id, slot) pair per covered tile, records visited in depth order.  Tile ids are
 // below n_tiles; n_tiles itself marks filler pairs (never drawn).

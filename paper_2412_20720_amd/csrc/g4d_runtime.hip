@@ -589,7 +589,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     int vb;
     {
       Stage t(ctx, 2, st);
-      vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
+      vb = radix_sort(vk, vv, cnt + 0, slots, 32, false, ctx->sort_tmp.p, st);
     }
     ctx->vis_buf = vb;
     {
@@ -657,12 +657,14 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
       {
         Stage t(ctx, 5, st);
+        // workgroups of 8,192 pairs once there are enough of them to fill the chip
+        const bool wide = pair_grid >= ((int64_t)1 << 22);
         if (key16) {
           uint16_t* pk[2] = {P<uint16_t>(ctx->pk[0]), P<uint16_t>(ctx->pk[1])};
-          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, ctx->sort_tmp.p, st);
+          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, wide, ctx->sort_tmp.p, st);
         } else {
           uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
-          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, ctx->sort_tmp.p, st);
+          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, wide, ctx->sort_tmp.p, st);
         }
       }
       G4D_HIP(hipGetLastError());

@@ -230,25 +230,34 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 // stable scatter.  Each wave owns a contiguous 1024-item run of its block; ranks inside a
 // wave come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const K* __restrict__ key,
-                                                         const uint32_t* n_dev, int shift,
-                                                         uint32_t mask, uint32_t* hist,
-                                                         int nblocks) {
-  __shared__ uint32_t wh[4][kRadix];
+// NT threads per workgroup, 16 items per thread: 256 (4096 items), or 512 for long sorts, whose
+// scatter then writes runs of one digit about twice as long (8192 items over 256 digits) with
+// two workgroups still resident per CU.  Tile sort of the 300k-Gaussian, 16-view workload
+// (26.1M pairs, 16-bit keys): 0.399 ms at 256 threads, 0.375 at 512, 0.399 at 1024 (16,384
+// items, full-line runs, but one workgroup per CU serializes its load, rank and write phases).
+template <typename K, int NT>
+__global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ key,
+                                                   const uint32_t* n_dev, int shift,
+                                                   uint32_t mask, uint32_t* hist, int nblocks) {
+  constexpr int NW = NT / 64, ITEMS = NT * kRadixPerThread;
+  __shared__ uint32_t wh[NW][kRadix];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = threadIdx.x; d < 4 * kRadix; d += kThreads) (&wh[0][0])[d] = 0;
+  for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wh[0][0])[d] = 0;
   __syncthreads();
   const int64_t n = *n_dev;
-  const int64_t base = (int64_t)blockIdx.x * kRadixItems + w * (kRadixItems / 4);
+  const int64_t base = (int64_t)blockIdx.x * ITEMS + w * (ITEMS / NW);
 #pragma unroll 4
   for (int r = 0; r < kRadixPerThread; ++r) {
     const int64_t i = base + r * 64 + lane;
     if (i < n) atomicAdd(&wh[w][((uint32_t)key[i] >> shift) & mask], 1u);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kThreads)
-    hist[(int64_t)d * nblocks + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+  for (int d = threadIdx.x; d < kRadix; d += NT) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += wh[k][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = t;
+  }
 }
 
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
@@ -262,24 +271,26 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
   return peers;
 }
 
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+template <typename K, int NT>
+__global__ __launch_bounds__(NT) void k_radix_scatter(
     const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* n_dev, int shift, uint32_t mask,
     const uint32_t* __restrict__ hist, int nblocks) {
-  __shared__ uint32_t wcount[4][kRadix];
+  constexpr int NW = NT / 64, ITEMS = NT * kRadixPerThread;
+  static_assert(NT >= kRadix, "one thread per digit");
+  __shared__ uint32_t wcount[NW][kRadix];
   __shared__ uint32_t bstart[kRadix];
   __shared__ uint32_t goff[kRadix];
-  __shared__ K sk[kRadixItems];
-  __shared__ uint32_t sv[kRadixItems];
+  __shared__ K sk[ITEMS];
+  __shared__ uint32_t sv[ITEMS];
   __shared__ uint32_t lds4[4];
   const int64_t n = *n_dev;
-  const int64_t bbase = (int64_t)blockIdx.x * kRadixItems;
+  const int64_t bbase = (int64_t)blockIdx.x * ITEMS;
   if (bbase >= n) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = threadIdx.x; d < 4 * kRadix; d += kThreads) (&wcount[0][0])[d] = 0;
+  for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcount[0][0])[d] = 0;
   __syncthreads();
-  const int64_t base = bbase + w * (kRadixItems / 4);
+  const int64_t base = bbase + w * (ITEMS / NW);
   const uint64_t lt = lanemask_lt();
   uint32_t k[kRadixPerThread], v[kRadixPerThread], rank[kRadixPerThread];
 #pragma unroll
@@ -297,17 +308,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // Per-digit totals, exclusive prefix over waves (in place) and over digits (bstart).
-  {
-    const int d = threadIdx.x;  // kThreads == kRadix
-    uint32_t c0 = wcount[0][d], c1 = wcount[1][d], c2 = wcount[2][d], c3 = wcount[3][d];
-    wcount[0][d] = 0;
-    wcount[1][d] = c0;
-    wcount[2][d] = c0 + c1;
-    wcount[3][d] = c0 + c1 + c2;
-    uint32_t tot;
-    bstart[d] = block_excl_scan(c0 + c1 + c2 + c3, tot, lds4);
+  // Per-digit totals, exclusive prefix over waves (in place) and over digits (bstart): the
+  // first 256 threads hold one digit each.
+  uint32_t tot = 0;
+  if (threadIdx.x < kRadix) {
+    const int d = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const uint32_t c = wcount[q][d];
+      wcount[q][d] = tot;
+      tot += c;
+    }
     goff[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+  }
+  const uint32_t inc = wave_incl_scan(tot);  // waves past the digits scan zeros
+  if (lane == 63 && w < 4) lds4[w] = inc;
+  __syncthreads();
+  if (threadIdx.x < kRadix) {
+    uint32_t pre = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pre += (q < w) ? lds4[q] : 0u;
+    bstart[threadIdx.x] = pre + inc - tot;
   }
   __syncthreads();
 #pragma unroll
@@ -321,8 +342,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
   }
   __syncthreads();
-  const int cnt = (int)((n - bbase) < kRadixItems ? (n - bbase) : kRadixItems);
-  for (int p = threadIdx.x; p < cnt; p += kThreads) {
+  const int cnt = (int)((n - bbase) < ITEMS ? (n - bbase) : ITEMS);
+  for (int p = threadIdx.x; p < cnt; p += NT) {
     const uint32_t kk = (uint32_t)sk[p];
     const uint32_t d = (kk >> shift) & mask;
     const uint32_t dst = goff[d] + ((uint32_t)p - bstart[d]);
@@ -547,16 +568,18 @@ void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_
                total, scratch, st);
 }
 
+// The table of the smaller workgroups is the larger one: it serves either.
 size_t radix_scratch_bytes(int64_t n_cap) {
   const int64_t blocks = (n_cap + kRadixItems - 1) / kRadixItems;
   const int64_t table = blocks * kRadix;
   return sizeof(uint32_t) * (size_t)(table + 16) + scan_scratch_bytes(table);
 }
 
-template <typename K>
-int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  const int64_t blocks = (n_cap + kRadixItems - 1) / kRadixItems;
+template <typename K, int NT>
+int radix_sort_nt(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+                  void* scratch, hipStream_t st) {
+  constexpr int64_t ITEMS = (int64_t)NT * kRadixPerThread;
+  const int64_t blocks = (n_cap + ITEMS - 1) / ITEMS;
   if (blocks == 0 || bits <= 0) return 0;
   uint32_t* hist = static_cast<uint32_t*>(scratch);
   void* scan_tmp = hist + blocks * kRadix + 16;
@@ -564,26 +587,33 @@ int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_c
   for (int shift = 0; shift < bits; shift += kRadixBits) {
     const int nb = (bits - shift) < kRadixBits ? (bits - shift) : kRadixBits;
     const uint32_t mask = (1u << nb) - 1u;
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur], n_dev,
-                       shift, mask, hist, (int)blocks);
+    hipLaunchKernelGGL((k_radix_hist<K, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, key[cur],
+                       n_dev, shift, mask, hist, (int)blocks);
     scan_generic(InPlain{hist}, InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr,
                  scan_tmp, st);
-    hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, key[cur],
-                       val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
+    hipLaunchKernelGGL((k_radix_scatter<K, NT>), dim3((unsigned)blocks), dim3(NT), 0, st,
+                       key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
                        (int)blocks);
     cur ^= 1;
   }
   return cur;
 }
 
+template <typename K>
+int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+                 bool wide, void* scratch, hipStream_t st) {
+  if (wide) return radix_sort_nt<K, 2 * kThreads>(key, val, n_dev, n_cap, bits, scratch, st);
+  return radix_sort_nt<K, kThreads>(key, val, n_dev, n_cap, bits, scratch, st);
+}
+
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  return radix_sort_t<uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
+               bool wide, void* scratch, hipStream_t st) {
+  return radix_sort_t<uint32_t>(key, val, n_dev, n_cap, bits, wide, scratch, st);
 }
 
 int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, scratch, st);
+               bool wide, void* scratch, hipStream_t st) {
+  return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, wide, scratch, st);
 }
 
 template <typename K>
