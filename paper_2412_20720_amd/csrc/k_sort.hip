@@ -233,8 +233,14 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 // NT threads per workgroup, 16 items per thread: 256 (4096 items), or 512 for long sorts, whose
 // scatter then writes runs of one digit about twice as long (8192 items over 256 digits) with
 // two workgroups still resident per CU.  Tile sort of the 300k-Gaussian, 16-view workload
-// (26.1M pairs, 16-bit keys): 0.399 ms at 256 threads, 0.375 at 512, 0.399 at 1024 (16,384
-// items, full-line runs, but one workgroup per CU serializes its load, rank and write phases).
+// (26.1M pairs, 16-bit keys): 0.399 ms at 256 threads, 0.368-0.375 at 512, 0.477 at 384
+// (three workgroups per CU, shorter runs), 0.442 at 768 and 0.399 at 1024 (one workgroup per
+// CU, which serializes its load, rank and write phases).
+#ifndef G4D_WIDE_THREADS
+#define G4D_WIDE_THREADS 512
+#endif
+constexpr int kWideThreads = G4D_WIDE_THREADS;
+
 template <typename K, int NT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ key,
                                                    const uint32_t* n_dev, int shift,
@@ -602,7 +608,7 @@ int radix_sort_nt(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_
 template <typename K>
 int radix_sort_t(K* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
                  bool wide, void* scratch, hipStream_t st) {
-  if (wide) return radix_sort_nt<K, 2 * kThreads>(key, val, n_dev, n_cap, bits, scratch, st);
+  if (wide) return radix_sort_nt<K, kWideThreads>(key, val, n_dev, n_cap, bits, scratch, st);
   return radix_sort_nt<K, kThreads>(key, val, n_dev, n_cap, bits, scratch, st);
 }
 
