@@ -300,8 +300,8 @@ g4d_status g4d_render_compact_forward(g4d_ctx *ctx, const g4d_compact *c, const 
  * with the same inputs, views, settings and buffer addresses (parameter and dL values may
  * change between calls): no host synchronization, allocation or per-kernel launch happens in
  * a replay.  The first call (and any call whose key changed) runs one eager step on a private
- * context to size the buffers, then captures with a pair capacity 25% above the pair count
- * it found; if a later replay finds more pairs, g4d_sync_status reports G4D_ECAPACITY, the
+ * context to size the buffers, then captures with pair and row-run capacities 25% above the
+ * counts it found; if a later replay finds more, g4d_sync_status reports G4D_ECAPACITY, the
  * outputs of that replay are undefined, and the graph is dropped so that the next call with
  * G4D_STEP_GRAPH sizes and captures it again. */
 g4d_status g4d_render_step(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *views,
@@ -317,11 +317,12 @@ g4d_status g4d_render_step(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view 
  * allocates no device memory and no pinned host memory (no hipMalloc, hipHostMalloc, hipFree).
  *   Limit: the records, counts and sort buffers of N * n_views slots, the per-pixel state of
  *   all views and the (Gaussian, tile) pairs must fit in the array together (about
- *   124 B per slot + 8 B per pixel + 8 B per tile + 16 B per pair; a 100k-Gaussian view of
- *   1352x1014 fits).  Sizes known before launching are rejected at once with G4D_ECAPACITY and
- *   nothing enqueued; a pair count above what remains is found when the call reads it (it
- *   waits on the host once, as g4d_render_forward does) and returned as G4D_ECAPACITY, the
- *   outputs then undefined.
+ *   124 B per slot + 8 B per pixel + 8 B per tile + 40 B per tile row + 16 B per pair, the
+ *   pair list and the binning's row runs, of which there may be up to half as many as pairs;
+ *   a 100k-Gaussian view of 1352x1014 fits).  Sizes known before launching are rejected at
+ *   once with G4D_ECAPACITY and nothing enqueued; a pair or run count above what remains is
+ *   found when the call reads it (it waits on the host once, as g4d_render_forward does) and
+ *   returned as G4D_ECAPACITY, the outputs then undefined.
  *   All calls on one GPU share its array and leave their contents in it: the call clears what
  *   must start at zero itself, and calls that overlap on one GPU (other streams, threads or
  *   contexts) race and give undefined results.  The call keeps no state for g4d_render_backward
@@ -334,7 +335,7 @@ g4d_status g4d_render_step_noalloc(g4d_ctx *ctx, const g4d_gaussians *g, const g
                                    void *stream);
 
 /* Wait for the context's work on `stream` and report errors found on the device
- * (G4D_ECAPACITY when the pair capacity of a captured graph was exceeded; outputs are then
+ * (G4D_ECAPACITY when a pair or row-run capacity was exceeded; outputs are then
  * undefined).  An error is reported once: the flag is cleared. */
 g4d_status g4d_sync_status(g4d_ctx *ctx, void *stream);
 
@@ -381,8 +382,8 @@ g4d_status g4d_autotune(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *vi
 /* Pipeline stages timed by g4d_profile (index: name). */
 #define G4D_NUM_STAGES 11
 /* Stage timing with HIP events recorded on the call's stream around each kernel group:
- *   0 preprocess, 1 compact, 2 depth_sort, 3 pair_offsets, 4 keygen, 5 tile_sort,
- *   6 tile_ranges, 7 raster_fwd, 8 clear_grad, 9 raster_bwd, 10 preprocess_bwd.
+ *   0 preprocess, 1 compact, 2 depth_sort, 3 row_offsets, 4 row_gen, 5 row_sort,
+ *   6 expand, 7 raster_fwd, 8 clear_grad, 9 raster_bwd, 10 preprocess_bwd.
  * enable = 1 starts recording for later calls, 0 stops.  If ms / launches are not NULL
  * (host arrays of G4D_NUM_STAGES), the context's device is synchronized, every recorded
  * interval is added in and the totals since the last reset are returned; reset = 1 then

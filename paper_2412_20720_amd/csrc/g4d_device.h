@@ -50,7 +50,7 @@ struct DView {
   float xlo, xhi, ylo, yhi;  // Jacobian clamp of x/z and y/z (filled on the device)
   int32_t width, height, tiles_x, tiles_y;
   int32_t tile_base, pix_base;
-  int32_t pad0, pad1;
+  int32_t pad0, row_base;    // pad0: unused on the device; row_base: first global tile row
 };
 
 struct DSettings {

@@ -23,10 +23,13 @@ void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slot
                      uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
                      hipStream_t st);
 
-// offsets[i] = sum_{k<i} tiles[val[k]] for i < *n_dev (exclusive); total to *total (device).
-void pair_offsets(const uint32_t* tiles, const uint32_t* val, const uint32_t* n_dev,
-                  int64_t n_cap, uint32_t* offsets, uint32_t* total, void* scratch,
-                  hipStream_t st);
+// *total = sum of tiles[0, n): the (Gaussian, tile) pairs the preprocess counted.
+void pair_total(const uint32_t* tiles, int64_t n, uint32_t* total, void* scratch, hipStream_t st);
+
+// roff[i] = sum_{k<i} nrows[vval[k]] for i < *n_vis (exclusive), nrows being the rows of each
+// slot's tile box; total to *total (device).
+void row_offsets(const uint32_t* nrows, const uint32_t* vval, const uint32_t* n_vis,
+                 int64_t n_cap, uint32_t* roff, uint32_t* total, void* scratch, hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
 // n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.  Keys of
@@ -38,27 +41,47 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_
                int bits, bool wide, void* scratch, hipStream_t st);
 int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
                int bits, bool wide, void* scratch, hipStream_t st);
+// The same with 8-byte values (workgroups of 4,096 items).
+int radix_sort(uint32_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+               void* scratch, hipStream_t st);
+int radix_sort(uint16_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
+               void* scratch, hipStream_t st);
 
-// One (tile id, slot) pair per covered tile, records visited in depth order.  Tile ids are
-// below n_tiles; n_tiles itself marks filler pairs (never drawn).
-void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
-            int n_tiles, const DView* views, DSettings S, uint32_t* pkey, uint32_t* pval,
-            uint32_t* overflow, hipStream_t st);
-void keygen(const float* rec, const uint32_t* vval, const uint32_t* voff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_pairs, int64_t pair_cap, int n_slots_per_view,
-            int n_tiles, const DView* views, DSettings S, uint16_t* pkey, uint32_t* pval,
-            uint32_t* overflow, hipStream_t st);
+// One run per box row of every visible slot, visible slots in depth order: rkey = global tile
+// row (view row_base + row), rval = (slot, span) with span = (first column << 16) | last
+// column, or ~0u for a row the ellipse misses.  Runs past row_cap set *flag = 1; rows that
+// disagree with the offsets set *flag = 2.
+void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
+            const DView* views, DSettings S, uint32_t* rkey, uint2* rval, uint32_t* flag,
+            hipStream_t st);
+void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
+            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
+            const DView* views, DSettings S, uint16_t* rkey, uint2* rval, uint32_t* flag,
+            hipStream_t st);
 
-// ranges[tile] = [first, last+1) of the tile's pairs in the sorted key array (keys >= n_tiles
-// are skipped).
-void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
-                 int64_t n_tiles, uint2* ranges, hipStream_t st);
-void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap,
-                 int64_t n_tiles, uint2* ranges, hipStream_t st);
+// Expansion of the row-sorted runs into the tile lists: rrange = each tile row's runs in the
+// sorted order (runs = their (slot, span)), pval = every tile's slots in depth order,
+// ranges = [first, end) per tile ((0, 0) if empty).  chunk_cap >= runs / 64 + n_rows and
+// hist_cap >= max tiles_x * ceil(runs / 64) + n_tiles bound the chunk grid and the count
+// table; rinfo holds 2 n_rows entries, crow 8 chunk_cap (a chunk list per XCD); counts (10
+// words) receive the chunks of each XCD, the table entries and the pairs written.  A pair count
+// other than *n_pairs sets *flag = 2 (unless set).
+void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,
+            const uint2* runs, int64_t chunk_cap,
+            int64_t hist_cap, int64_t pair_cap, const uint32_t* n_pairs, uint4* rinfo,
+            uint32_t* crow, uint32_t* hist, uint32_t* counts, uint32_t* pval, uint2* ranges,
+            uint32_t* flag, void* scratch, hipStream_t st);
 
-// out[0..n) = in[0..n) widened to 32 bits.
-void widen_u16(const uint16_t* in, int64_t n, uint32_t* out, hipStream_t st);
+// ids[i] = the tile whose range holds pair i, for i < n.
+void tile_ids_of(const uint2* ranges, int64_t n_tiles, int64_t n, uint32_t* ids, hipStream_t st);
+
+// ranges[k] = [first, last+1) of key k's items in a sorted key array (keys >= n_keys are
+// skipped; absent keys get (0, 0)).
+void tile_ranges(const uint32_t* key, const uint32_t* n_dev, int64_t cap, int64_t n_keys,
+                 uint2* ranges, hipStream_t st);
+void tile_ranges(const uint16_t* key, const uint32_t* n_dev, int64_t cap, int64_t n_keys,
+                 uint2* ranges, hipStream_t st);
 
 // *out = min(*n, cap) on the device.
 void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st);
@@ -79,7 +102,8 @@ struct GradPtrs {
 };
 
 void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
-                        float* rec, uint32_t* tiles, uint32_t* dkey, hipStream_t st);
+                        float* rec, uint32_t* tiles, uint32_t* nrows, uint32_t* dkey,
+                        hipStream_t st);
 void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
                            float* mean4, float* scale4, float* rot_l, float* rot_r,
                            float* opacity, float* sh, hipStream_t st);

@@ -73,11 +73,12 @@ struct SavedKey {
 struct g4d_ctx {
   int device = 0;
   std::string err;
-  DevBuf views, tile_base, rec, tiles, dkey, vk[2], vv[2], voff, pk[2], pv[2], scan_tmp,
-      sort_tmp, ranges, px_T, px_last, px_evals, grad2d, counters;
+  DevBuf views, tile_base, rec, tiles, nrows, dkey, vk[2], vv[2], roff, rk[2], rv[2], rrange,
+      rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last, px_evals, grad2d,
+      counters;
   DevBuf fn, fnorm, flow, dfn;     // extra channels
   DevBuf skybg;                    // per-pixel sky background
-  uint32_t* h_counters = nullptr;  // pinned: visible, pairs, overflow
+  uint32_t* h_counters = nullptr;  // pinned: visible, pairs, flag, runs
   DView* h_views = nullptr;        // pinned staging
   int32_t* h_tile_base = nullptr;  // pinned staging
   hipEvent_t staging_done = nullptr;
@@ -86,7 +87,8 @@ struct g4d_ctx {
   // the view table now on the device (skips the upload when a call repeats it)
   std::vector<DView> uploaded_views;
   void* uploaded_to = nullptr;
-  int64_t pair_cap = 0;
+  // capacities of the pair list, the run arrays and the expansion's count table
+  int64_t pair_cap = 0, row_cap = 0, hist_cap = 0;
   // the whole grad2d allocation holds zeros: the last backward ran to its preprocess adjoint,
   // which zeroes every slot the raster adjoint accumulated into (false after a reallocation or
   // an interrupted backward; the next backward then clears the whole allocation)
@@ -94,8 +96,10 @@ struct g4d_ctx {
   // state left by the last forward
   bool saved = false;
   SavedKey key;
-  int vis_buf = 0, pair_buf = 0;
+  int vis_buf = 0;
   int64_t n_tiles = 0, n_pixels = 0;
+  int64_t n_rows = 0, max_tiles_x = 0;  // tile rows of the batch, widest view in tiles
+  int64_t last_runs = 0;                 // row runs of the last eager forward
   g4d_stats stats{};
   bool count_evals = false;
   bool count_cutoff = false;   // counting forwards bin by the plain cutoff (g4d_eval_counters 2)
@@ -169,8 +173,8 @@ g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
 }
 
 const char* const kStageNames[G4D_NUM_STAGES] = {
-    "preprocess", "compact", "depth_sort", "pair_offsets", "keygen", "tile_sort",
-    "tile_ranges", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
+    "preprocess", "compact", "depth_sort", "row_offsets", "row_gen", "row_sort",
+    "expand", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
 
 hipEvent_t take_event(g4d_ctx* c) {
   if (!c->ev_free.empty()) {
@@ -290,6 +294,41 @@ GaussPtrs gauss_ptrs(const g4d_gaussians* g) {
                    g->rot_r,   g->opacity,   g->sh,       g->mask,  g->mask_threshold};
 }
 
+// Run arrays for `runs` row runs, the pair list for `pairs` pairs, and the expansion's count
+// table, sort and scan scratch that the run capacity implies (each capacity becomes what was
+// allocated; `grow` adds headroom to what has to grow).
+g4d_status size_binning(g4d_ctx* ctx, int64_t slots, int64_t runs, int64_t pairs, double grow) {
+  g4d_status r;
+  if (runs > ctx->row_cap) {
+    // keys (sized for 32 bits) and (slot, span) values, double-buffered for the row sort
+    size_t cap = SIZE_MAX;
+    for (int b = 0; b < 2; ++b) {
+      if ((r = ensure(ctx, ctx->rk[b], sizeof(uint32_t) * (size_t)runs, grow)) != G4D_OK ||
+          (r = ensure(ctx, ctx->rv[b], sizeof(uint2) * (size_t)runs, grow)) != G4D_OK)
+        return r;
+      cap = std::min({cap, ctx->rk[b].cap / sizeof(uint32_t), ctx->rv[b].cap / sizeof(uint2)});
+    }
+    ctx->row_cap = std::min<int64_t>((int64_t)cap, INT32_MAX);
+  }
+  if (pairs > ctx->pair_cap) {
+    if ((r = ensure(ctx, ctx->pval, sizeof(uint32_t) * (size_t)pairs, grow)) != G4D_OK) return r;
+    ctx->pair_cap = std::min<int64_t>((int64_t)(ctx->pval.cap / sizeof(uint32_t)), INT32_MAX);
+  }
+  // a row of len runs has ceil(len / 64) chunks, each with one entry per column
+  const int64_t chunk_need = (ctx->row_cap + 63) / 64 + ctx->n_rows;
+  if ((r = ensure(ctx, ctx->crow, 8 * sizeof(uint32_t) * (size_t)chunk_need, grow)) != G4D_OK)
+    return r;
+  const int64_t hist_need = ctx->max_tiles_x * ((ctx->row_cap + 63) / 64) + ctx->n_tiles;
+  if (hist_need > ctx->hist_cap) {
+    if ((r = ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)hist_need, grow)) != G4D_OK) return r;
+    ctx->hist_cap = (int64_t)(ctx->hist.cap / sizeof(uint32_t));
+  }
+  if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(ctx->row_cap, slots)), grow)) !=
+      G4D_OK)
+    return r;
+  return ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(std::max(ctx->hist_cap, slots)), grow);
+}
+
 // Plan tile grids and offsets, upload the view table and derive per-view constants.
 g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const g4d_settings* s,
                         hipStream_t st) {
@@ -298,7 +337,7 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
     ctx->staging_pending = false;
   }
   const int T = s->tile_size;
-  int64_t tile_base = 0, pix_base = 0;
+  int64_t tile_base = 0, pix_base = 0, row_base = 0, max_tx = 0;
   for (int v = 0; v < n_views; ++v) {
     const g4d_view& in = views[v];
     DView& d = ctx->h_views[v];
@@ -319,9 +358,12 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
     d.tiles_y = (in.height + T - 1) / T;
     d.tile_base = (int32_t)tile_base;
     d.pix_base = (int32_t)pix_base;
+    d.row_base = (int32_t)row_base;
     std::memcpy(&d.pad0, &s->jacobian_margin, sizeof(float));  // part of the upload key
     ctx->h_tile_base[v] = (int32_t)tile_base;
     tile_base += (int64_t)d.tiles_x * d.tiles_y;
+    row_base += d.tiles_y;
+    max_tx = std::max<int64_t>(max_tx, d.tiles_x);
     pix_base += (int64_t)in.width * in.height;
     if (pix_base > INT32_MAX || tile_base > INT32_MAX)
       return fail(ctx, G4D_EINVAL, "total pixels of the batch exceed 2^31-1");
@@ -329,6 +371,8 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
   ctx->h_tile_base[n_views] = (int32_t)tile_base;
   ctx->n_tiles = tile_base;
   ctx->n_pixels = pix_base;
+  ctx->n_rows = row_base;
+  ctx->max_tiles_x = max_tx;
   if (ctx->capturing) return G4D_OK;  // the view table was uploaded before the capture
   g4d_status r;
   if ((r = ensure(ctx, ctx->views, sizeof(DView) * n_views)) != G4D_OK) return r;
@@ -357,6 +401,7 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
   if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
   if (zero_records) G4D_HIP(hipMemsetAsync(ctx->rec.p, 0, sizeof(float) * kRec * slots, st));
   if ((r = ensure(ctx, ctx->tiles, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->nrows, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   {
     Stage t(ctx, 0, st);
@@ -364,7 +409,8 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
     gp.compact = cp;
     preprocess_forward(gp, P<DView>(ctx->views), n_views,
                        device_settings(s, ctx->count_evals && ctx->count_cutoff),
-                       P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), st);
+                       P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->nrows),
+                       P<uint32_t>(ctx->dkey), st);
   }
   G4D_HIP(hipGetLastError());
   return G4D_OK;
@@ -473,9 +519,11 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->graph_ctx) g4d_destroy(ctx->graph_ctx);
   if (ctx->na) g4d_destroy(ctx->na);
-  DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->dkey,
-                    &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->voff,
-                    &ctx->pk[0], &ctx->pk[1], &ctx->pv[0], &ctx->pv[1], &ctx->scan_tmp,
+  DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->nrows, &ctx->dkey,
+                    &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->roff,
+                    &ctx->rk[0], &ctx->rk[1], &ctx->rv[0], &ctx->rv[1], &ctx->rrange,
+                    &ctx->rinfo, &ctx->crow, &ctx->hist, &ctx->pval,
+                    &ctx->scan_tmp,
                     &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
                     &ctx->grad2d, &ctx->counters, &ctx->fn, &ctx->fnorm, &ctx->flow,
                     &ctx->dfn, &ctx->skybg};
@@ -543,21 +591,23 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   ctx->fwd_cutoff_bins = ctx->count_evals && ctx->count_cutoff;
   const DSettings DS = device_settings(&s_run, ctx->fwd_cutoff_bins);
   const int n_ext = n_ext_of(ch);
-  if ((r = ensure(ctx, ctx->counters, 8 * sizeof(uint32_t))) != G4D_OK) return r;
-  // [0] visible, [1] pairs, [2] overflow / mismatch flag, [3] pairs clamped to the capacity,
-  // [4] clamped batches of the last counted backward
+  if ((r = ensure(ctx, ctx->counters, 16 * sizeof(uint32_t))) != G4D_OK) return r;
+  // [0] visible, [1] pairs the preprocess counted, [2] overflow / mismatch flag, [3] runs,
+  // [4] clamped batches of the last counted backward, [5] runs clamped to the capacity,
+  // [6..15] the expansion's chunks per XCD, table entries and pairs written
   uint32_t* cnt = P<uint32_t>(ctx->counters);
   ctx->counted_bwd = false;
   fill_u32(cnt, 4, 0u, st);
   if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->ranges, sizeof(uint2) * ctx->n_tiles, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->rrange, sizeof(uint2) * ctx->n_rows, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->rinfo, 2 * sizeof(uint4) * ctx->n_rows, 1.1)) != G4D_OK) return r;
   if (ctx->count_evals &&
       (r = ensure(ctx, ctx->px_evals, sizeof(uint32_t) * ctx->n_pixels, 1.1)) != G4D_OK)
     return r;
 
-  int64_t n_vis = 0, n_pairs = 0;
-  int pb = 0;
+  int64_t n_vis = 0, n_pairs = 0, run_grid = 0;
   if (slots > 0) {
     if ((r = run_preprocess(ctx, g, n_views, &s_run, st, false, cp)) != G4D_OK) return r;
     if (ch && ch->n_features > 0) {
@@ -576,7 +626,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       if ((r = ensure(ctx, ctx->vk[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
       if ((r = ensure(ctx, ctx->vv[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
     }
-    if ((r = ensure(ctx, ctx->voff, sizeof(uint32_t) * (slots + 1), 1.1)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->roff, sizeof(uint32_t) * (slots + 1), 1.1)) != G4D_OK) return r;
     if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
     if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
     {
@@ -594,93 +644,93 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     ctx->vis_buf = vb;
     {
       Stage t(ctx, 3, st);
-      pair_offsets(P<uint32_t>(ctx->tiles), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->voff),
-                   cnt + 1, ctx->scan_tmp.p, st);
+      pair_total(P<uint32_t>(ctx->tiles), slots, cnt + 1, ctx->scan_tmp.p, st);
+      row_offsets(P<uint32_t>(ctx->nrows), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->roff),
+                  cnt + 3, ctx->scan_tmp.p, st);
     }
     G4D_HIP(hipGetLastError());
-    int64_t pair_grid;
-    // n_tiles + 1 keys: the dummy tile id n_tiles must sort too.  With at most 2^16 of them
-    // the keys move as 16-bit words (the pair buffers are sized for 32).
-    const int key_bits = bits_for(ctx->n_tiles + 1);
+    // Run keys are global tile rows; with at most 2^16 of them they move as 16-bit words (the
+    // run buffers are sized for 32).
+    const int key_bits = bits_for(ctx->n_rows);
     const bool key16 = key_bits <= 16;
-    auto run_keygen = [&](int64_t vis_grid) {
+    auto run_rowgen = [&](int64_t vis_grid) {
       Stage t(ctx, 4, st);
       if (key16)
-        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
-               ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
-               P<uint16_t>(ctx->pk[0]), P<uint32_t>(ctx->pv[0]), cnt + 2, st);
+        rowgen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->roff), cnt + 0, vis_grid, cnt + 3,
+               ctx->row_cap, g->n, P<DView>(ctx->views), DS, P<uint16_t>(ctx->rk[0]),
+               P<uint2>(ctx->rv[0]), cnt + 2, st);
       else
-        keygen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->voff), cnt + 0, vis_grid, cnt + 1,
-               ctx->pair_cap, g->n, (int)ctx->n_tiles, P<DView>(ctx->views), DS,
-               P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pv[0]), cnt + 2, st);
-      clamp_count(cnt + 1, (uint32_t)ctx->pair_cap, cnt + 3, st);
+        rowgen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->roff), cnt + 0, vis_grid, cnt + 3,
+               ctx->row_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->rk[0]),
+               P<uint2>(ctx->rv[0]), cnt + 2, st);
+      clamp_count(cnt + 3, (uint32_t)ctx->row_cap, cnt + 5, st);
     };
     if (ctx->capturing) {
       // counts stay on the device; grids cover the capacities
-      n_pairs = pair_grid = ctx->pair_cap;
-      if (n_pairs > 0) run_keygen(slots);
+      n_pairs = ctx->pair_cap;
+      run_grid = ctx->row_cap;
+      if (run_grid > 0) run_rowgen(slots);
     } else {
-      // The counts go to the host; with pair buffers from an earlier call the key generation
+      // The counts go to the host; with run buffers from an earlier call the run generation
       // is queued behind the copy at once (grid over every slot, writes clamped to the
       // capacity), so that the GPU does not idle while the host reads the counts.  Should the
-      // pairs exceed that capacity, the buffers grow and the key generation runs again.
-      const bool early = ctx->pair_cap > 0;
-      G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      // runs exceed that capacity, the buffers grow and the run generation runs again.
+      const bool early = ctx->row_cap > 0;
+      G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       G4D_HIP(hipEventRecord(ctx->counts_ready, st));
-      if (early) run_keygen(slots);
+      if (early) run_rowgen(slots);
       G4D_HIP(hipEventSynchronize(ctx->counts_ready));
       n_vis = ctx->h_counters[0];
-      n_pairs = pair_grid = ctx->h_counters[1];
+      n_pairs = ctx->h_counters[1];
+      const int64_t n_runs = ctx->h_counters[3];
       // list positions are 32-bit signed in the raster kernels
       if (n_pairs > (int64_t)INT32_MAX)
         return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^31-1", (long long)n_pairs);
-      const bool fits = early && n_pairs <= ctx->pair_cap;
-      if (ctx->arena && n_pairs > ctx->pair_cap)
+      if (ctx->arena && (n_pairs > ctx->pair_cap || n_runs > ctx->row_cap))
         return fail(ctx, G4D_ECAPACITY,
-                    "%lld (Gaussian, tile) pairs exceed the %lld the fixed scratch leaves room for",
-                    (long long)n_pairs, (long long)ctx->pair_cap);
-      if (n_pairs > 0 && !fits) {
-        for (int b = 0; b < 2; ++b) {
-          if ((r = ensure(ctx, ctx->pk[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
-          if ((r = ensure(ctx, ctx->pv[b], sizeof(uint32_t) * n_pairs, 1.2)) != G4D_OK) return r;
-        }
-        ctx->pair_cap = (int64_t)(std::min(ctx->pk[0].cap, ctx->pv[0].cap) / sizeof(uint32_t));
+                    "%lld (Gaussian, tile) pairs in %lld row runs exceed the %lld pairs and %lld "
+                    "runs the fixed scratch leaves room for",
+                    (long long)n_pairs, (long long)n_runs, (long long)ctx->pair_cap,
+                    (long long)ctx->row_cap);
+      const bool fits = early && n_runs <= ctx->row_cap;
+      if ((r = size_binning(ctx, slots, n_runs, n_pairs, 1.2)) != G4D_OK) return r;
+      if (n_runs > 0 && !fits) {
         if (early) fill_u32(cnt + 2, 1, 0u, st);  // the early pass flagged the overflow
-        run_keygen(n_vis);
+        run_rowgen(n_vis);
       }
-      if (n_pairs > 0 &&
-          (r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(n_pairs, slots)), 1.2)) !=
-              G4D_OK)
-        return r;
+      run_grid = n_runs;
+      ctx->last_runs = n_runs;
     }
-    if (n_pairs > 0) {
-      uint32_t* pv[2] = {P<uint32_t>(ctx->pv[0]), P<uint32_t>(ctx->pv[1])};
+    if (run_grid > 0) {
+      int rb;
       {
         Stage t(ctx, 5, st);
-        // workgroups of 8,192 pairs once there are enough of them to fill the chip
-        const bool wide = pair_grid >= ((int64_t)1 << 22);
+        uint2* rv[2] = {P<uint2>(ctx->rv[0]), P<uint2>(ctx->rv[1])};
         if (key16) {
-          uint16_t* pk[2] = {P<uint16_t>(ctx->pk[0]), P<uint16_t>(ctx->pk[1])};
-          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, wide, ctx->sort_tmp.p, st);
+          uint16_t* rk[2] = {P<uint16_t>(ctx->rk[0]), P<uint16_t>(ctx->rk[1])};
+          rb = radix_sort(rk, rv, cnt + 5, run_grid, key_bits, ctx->sort_tmp.p, st);
+          tile_ranges(rk[rb], cnt + 5, run_grid, ctx->n_rows, P<uint2>(ctx->rrange), st);
         } else {
-          uint32_t* pk[2] = {P<uint32_t>(ctx->pk[0]), P<uint32_t>(ctx->pk[1])};
-          pb = radix_sort(pk, pv, cnt + 3, pair_grid, key_bits, wide, ctx->sort_tmp.p, st);
+          uint32_t* rk[2] = {P<uint32_t>(ctx->rk[0]), P<uint32_t>(ctx->rk[1])};
+          rb = radix_sort(rk, rv, cnt + 5, run_grid, key_bits, ctx->sort_tmp.p, st);
+          tile_ranges(rk[rb], cnt + 5, run_grid, ctx->n_rows, P<uint2>(ctx->rrange), st);
         }
+      }
+      {
+        Stage t(ctx, 6, st);
+        expand(P<uint2>(ctx->rrange), (int)ctx->n_rows, P<DView>(ctx->views), n_views,
+               ctx->n_tiles, P<uint2>(ctx->rv[rb]), (run_grid + 63) / 64 + ctx->n_rows,
+               ctx->hist_cap,
+               ctx->pair_cap, cnt + 1, P<uint4>(ctx->rinfo), P<uint32_t>(ctx->crow),
+               P<uint32_t>(ctx->hist), cnt + 6,
+               P<uint32_t>(ctx->pval), P<uint2>(ctx->ranges), cnt + 2, ctx->scan_tmp.p, st);
       }
       G4D_HIP(hipGetLastError());
     }
   }
-  ctx->pair_buf = pb;
-  {
+  if (run_grid <= 0) {
     Stage t(ctx, 6, st);
-    if (n_pairs > 0 && bits_for(ctx->n_tiles + 1) <= 16)
-      tile_ranges(P<uint16_t>(ctx->pk[pb]), cnt + 3, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
-                  st);
-    else if (n_pairs > 0)
-      tile_ranges(P<uint32_t>(ctx->pk[pb]), cnt + 3, n_pairs, ctx->n_tiles, P<uint2>(ctx->ranges),
-                  st);
-    else
-      fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
+    fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
   }
   if (sky) {
     if ((r = ensure(ctx, ctx->skybg, sizeof(float) * 3 * ctx->n_pixels, 1.1)) != G4D_OK) return r;
@@ -690,7 +740,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   RasterArgs a{};
   a.bg_px = sky ? P<float>(ctx->skybg) : nullptr;
   a.rec = P<float>(ctx->rec);
-  a.pval = n_pairs > 0 ? P<uint32_t>(ctx->pv[pb]) : nullptr;
+  a.pval = n_pairs > 0 ? P<uint32_t>(ctx->pval) : nullptr;
   a.ranges = P<uint2>(ctx->ranges);
   a.views = P<DView>(ctx->views);
   a.tile_base = P<int32_t>(ctx->tile_base);
@@ -799,7 +849,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   if (ctx->stats.n_pairs > 0 || ctx->capturing) {
     RasterArgs a{};
     a.rec = P<float>(ctx->rec);
-    a.pval = P<uint32_t>(ctx->pv[ctx->pair_buf]);
+    a.pval = P<uint32_t>(ctx->pval);
     a.ranges = P<uint2>(ctx->ranges);
     a.views = P<DView>(ctx->views);
     a.tile_base = P<int32_t>(ctx->tile_base);
@@ -982,23 +1032,18 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
     ctx->graph_exec = nullptr;
     ctx->graph = nullptr;
     ctx->graph_key.clear();
-    // One eager pass sizes every buffer and finds the pair count; the capture then gets a
-    // pair capacity with 25% headroom (exceeding it is reported by g4d_sync_status).
+    // One eager pass sizes every buffer and finds the pair and run counts; the capture then
+    // gets capacities with 25% headroom (exceeding them is reported by g4d_sync_status).
     if ((r = g4d_render_forward(gc, g, views, n_views, s, out_rgb, out_T, stream)) != G4D_OK ||
         (r = g4d_render_backward(gc, g, views, n_views, s, dL_drgb, grads, stream)) != G4D_OK)
       return fail(ctx, r, "graph sizing pass: %s", gc->err.c_str());
     G4D_HIP(hipStreamSynchronize(st));
     const int64_t slots = (int64_t)g->n * n_views;
-    const int64_t want = gc->stats.n_pairs + gc->stats.n_pairs / 4 + 4096;
-    if (want > (int64_t)INT32_MAX)
-      return fail(ctx, G4D_ECAPACITY, "graph pair capacity %lld exceeds 2^31-1", (long long)want);
-    for (int b = 0; b < 2; ++b) {
-      if ((r = ensure(gc, gc->pk[b], sizeof(uint32_t) * want)) != G4D_OK ||
-          (r = ensure(gc, gc->pv[b], sizeof(uint32_t) * want)) != G4D_OK)
-        return fail(ctx, r, "%s", gc->err.c_str());
-    }
-    gc->pair_cap = (int64_t)(std::min(gc->pk[0].cap, gc->pv[0].cap) / sizeof(uint32_t));
-    if ((r = ensure(gc, gc->sort_tmp, radix_scratch_bytes(std::max(gc->pair_cap, slots)))) != G4D_OK)
+    const int64_t want_p = gc->stats.n_pairs + gc->stats.n_pairs / 4 + 4096;
+    const int64_t want_r = gc->last_runs + gc->last_runs / 4 + 4096;
+    if (want_p > (int64_t)INT32_MAX || want_r > (int64_t)INT32_MAX)
+      return fail(ctx, G4D_ECAPACITY, "graph pair capacity %lld exceeds 2^31-1", (long long)want_p);
+    if ((r = size_binning(gc, slots, want_r, want_p, 1.0)) != G4D_OK)
       return fail(ctx, r, "%s", gc->err.c_str());
     G4D_HIP(hipDeviceSynchronize());
     gc->capturing = true;
@@ -1034,64 +1079,82 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
 
 // Points every buffer a plain forward + backward uses into the device's fixed scratch array
 // (256-byte aligned slices, the counters first so that they stay at offset 0 whatever the
-// sizes); the pair buffers and the sort scratch share what remains, and the pair capacity is
-// the largest that fits.
+// sizes); the pair list, the row runs (half as many as pairs), their count table and the sort
+// and scan scratch share what remains, and the pair capacity is the largest that fits.
 static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, int64_t slots,
-                                int n_views, int64_t n_tiles, int64_t n_pixels) {
+                                int n_views, int64_t n_tiles, int64_t n_pixels, int64_t n_rows,
+                                int64_t max_tx) {
   const size_t cap = G4D_NOALLOC_SCRATCH_BYTES;
   auto round = [](size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; };
   size_t off = 0;
   struct Slice { DevBuf* b; size_t off, bytes; };
-  Slice plan[24];  // applied only once everything fits
+  Slice plan[32];  // applied only once everything fits
   int n_plan = 0;
   auto take = [&](DevBuf& b, size_t bytes) {
     plan[n_plan++] = {&b, off, round(bytes)};
     off += round(bytes);
   };
-  take(na->counters, 8 * sizeof(uint32_t));
+  take(na->counters, 16 * sizeof(uint32_t));
   take(na->views, sizeof(DView) * n_views);
   take(na->tile_base, sizeof(int32_t) * (n_views + 1));
   take(na->rec, sizeof(float) * kRec * slots);
   take(na->tiles, sizeof(uint32_t) * slots);
+  take(na->nrows, sizeof(uint32_t) * slots);
   take(na->dkey, sizeof(uint32_t) * slots);
   for (int b = 0; b < 2; ++b) {
     take(na->vk[b], sizeof(uint32_t) * slots);
     take(na->vv[b], sizeof(uint32_t) * slots);
   }
-  take(na->voff, sizeof(uint32_t) * (slots + 1));
-  take(na->scan_tmp, scan_scratch_bytes(slots));
+  take(na->roff, sizeof(uint32_t) * (slots + 1));
   take(na->ranges, sizeof(uint2) * n_tiles);
+  take(na->rrange, sizeof(uint2) * n_rows);
+  take(na->rinfo, 2 * sizeof(uint4) * n_rows);
   take(na->px_T, sizeof(float) * n_pixels);
   take(na->px_last, sizeof(int32_t) * n_pixels);
   take(na->grad2d, sizeof(float) * kGrad2d * slots);
   const size_t fixed = off;
-  // pairs p need four 4-byte arrays and the radix scratch of max(p, slots) items
+  // p pairs: the pair list, p / 2 runs (two 4-byte keys and two 8-byte values each), their
+  // chunk maps and count table,
+  // and the sort scratch of max(runs, slots) and scan scratch of max(table, slots) items
+  auto hist_of = [&](int64_t runs) { return max_tx * ((runs + 63) / 64) + n_tiles; };
+  auto chunks_of = [&](int64_t runs) { return (runs + 63) / 64 + n_rows; };
   auto need = [&](int64_t p) {
-    return 4 * round(sizeof(uint32_t) * (size_t)p) +
-           round(radix_scratch_bytes(std::max<int64_t>(p, slots)));
+    const int64_t runs = p / 2;
+    return round(sizeof(uint32_t) * (size_t)p) + 2 * round(sizeof(uint32_t) * (size_t)runs) +
+           2 * round(sizeof(uint2) * (size_t)runs) +
+           round(8 * sizeof(uint32_t) * (size_t)chunks_of(runs)) +
+           round(sizeof(uint32_t) * (size_t)hist_of(runs)) +
+           round(radix_scratch_bytes(std::max<int64_t>(runs, slots))) +
+           round(scan_scratch_bytes(std::max<int64_t>(hist_of(runs), slots)));
   };
   if (fixed > cap || need(0) > cap - fixed)
     return fail(ctx, G4D_ECAPACITY,
                 "%lld slots, %lld tiles and %lld pixels need %zu bytes before any pair; the "
                 "fixed scratch holds %zu (G4D_NOALLOC_SCRATCH_BYTES)",
                 (long long)slots, (long long)n_tiles, (long long)n_pixels, fixed + need(0), cap);
-  int64_t lo = 0, hi = (int64_t)((cap - fixed) / 16);
+  int64_t lo = 0, hi = (int64_t)((cap - fixed) / 4);
   while (lo < hi) {  // largest p with need(p) <= cap - fixed
     const int64_t mid = lo + (hi - lo + 1) / 2;
     if (need(mid) <= cap - fixed) lo = mid; else hi = mid - 1;
   }
-  hi = std::min<int64_t>(lo, INT32_MAX);
+  const int64_t pairs = std::min<int64_t>(lo, INT32_MAX), runs = pairs / 2;
+  take(na->pval, sizeof(uint32_t) * pairs);
   for (int b = 0; b < 2; ++b) {
-    take(na->pk[b], sizeof(uint32_t) * hi);
-    take(na->pv[b], sizeof(uint32_t) * hi);
+    take(na->rk[b], sizeof(uint32_t) * runs);
+    take(na->rv[b], sizeof(uint2) * runs);
   }
-  take(na->sort_tmp, radix_scratch_bytes(std::max<int64_t>(hi, slots)));
+  take(na->crow, 8 * sizeof(uint32_t) * chunks_of(runs));
+  take(na->hist, sizeof(uint32_t) * hist_of(runs));
+  take(na->sort_tmp, radix_scratch_bytes(std::max<int64_t>(runs, slots)));
+  take(na->scan_tmp, scan_scratch_bytes(std::max<int64_t>(hist_of(runs), slots)));
   if (off > cap) return fail(ctx, G4D_EHIP, "scratch plan of %zu bytes exceeds %zu", off, cap);
   for (int k = 0; k < n_plan; ++k) {
     plan[k].b->p = base + plan[k].off;
     plan[k].b->cap = plan[k].bytes;
   }
-  na->pair_cap = hi;
+  na->pair_cap = pairs;
+  na->row_cap = runs;
+  na->hist_cap = hist_of(runs);
   return G4D_OK;
 }
 
@@ -1111,15 +1174,18 @@ g4d_status g4d_render_step_noalloc(g4d_ctx* ctx, const g4d_gaussians* g, const g
                 dev < kMaxScratchDevices ? hipGetErrorString(g_scratch_err[dev])
                                          : "device index beyond the scratch table");
   // the sizes the forward plans (as upload_views counts them)
-  int64_t n_tiles = 0, n_pixels = 0;
+  int64_t n_tiles = 0, n_pixels = 0, n_rows = 0, max_tx = 0;
   for (int v = 0; v < n_views; ++v) {
-    n_tiles += (int64_t)((views[v].width + s->tile_size - 1) / s->tile_size) *
-               ((views[v].height + s->tile_size - 1) / s->tile_size);
+    const int64_t tx = (views[v].width + s->tile_size - 1) / s->tile_size;
+    const int64_t ty = (views[v].height + s->tile_size - 1) / s->tile_size;
+    n_tiles += tx * ty;
+    n_rows += ty;
+    max_tx = std::max(max_tx, tx);
     n_pixels += (int64_t)views[v].width * views[v].height;
   }
   g4d_ctx* na = ctx->na;
-  if ((r = carve_scratch(ctx, na, base, (int64_t)g->n * n_views, n_views, n_tiles, n_pixels)) !=
-      G4D_OK)
+  if ((r = carve_scratch(ctx, na, base, (int64_t)g->n * n_views, n_views, n_tiles, n_pixels,
+                         n_rows, max_tx)) != G4D_OK)
     return r;
   // Another call may have left anything in the array: the view table is uploaded again and
   // the gradient slots, which the raster adjoint accumulates into, are cleared.
@@ -1154,12 +1220,14 @@ g4d_status g4d_sync_status(g4d_ctx* ctx, void* stream) {
       ctx->graph_exec = nullptr;
       ctx->graph = nullptr;
       ctx->graph_key.clear();
-      return fail(ctx, G4D_ECAPACITY, "graph pair capacity %lld exceeded (the graph is dropped)",
-                  cap);
+      return fail(ctx, G4D_ECAPACITY,
+                  "graph capacity of %lld pairs or %lld row runs exceeded (the graph is dropped)",
+                  cap, (long long)c->row_cap);
     }
     if (flag == 1)
-      return fail(ctx, G4D_ECAPACITY, "pair capacity %lld exceeded", (long long)c->pair_cap);
-    return fail(ctx, G4D_EHIP, "pair count mismatch between preprocess and keygen");
+      return fail(ctx, G4D_ECAPACITY, "capacity of %lld pairs or %lld row runs exceeded",
+                  (long long)c->pair_cap, (long long)c->row_cap);
+    return fail(ctx, G4D_EHIP, "pair count mismatch between the preprocess and the binning");
   }
   return G4D_OK;
 }
@@ -1185,16 +1253,10 @@ g4d_status g4d_get_pairs(g4d_ctx* ctx, uint32_t* tile_ids, uint32_t* slots, uint
   hipStream_t st = static_cast<hipStream_t>(stream);
   G4D_HIP(hipSetDevice(ctx->device));
   const int64_t np = ctx->stats.n_pairs;
-  if (np > 0 && tile_ids) {
-    if (bits_for(ctx->n_tiles + 1) <= 16)
-      widen_u16(P<uint16_t>(ctx->pk[ctx->pair_buf]), np, tile_ids, st);
-    else
-      G4D_HIP(hipMemcpyAsync(tile_ids, ctx->pk[ctx->pair_buf].p, sizeof(uint32_t) * np,
-                             hipMemcpyDeviceToDevice, st));
-  }
+  if (np > 0 && tile_ids) tile_ids_of(P<uint2>(ctx->ranges), ctx->n_tiles, np, tile_ids, st);
   if (np > 0 && slots)
-    G4D_HIP(hipMemcpyAsync(slots, ctx->pv[ctx->pair_buf].p, sizeof(uint32_t) * np,
-                           hipMemcpyDeviceToDevice, st));
+    G4D_HIP(hipMemcpyAsync(slots, ctx->pval.p, sizeof(uint32_t) * np, hipMemcpyDeviceToDevice,
+                           st));
   if (ranges && ctx->n_tiles > 0)
     G4D_HIP(hipMemcpyAsync(ranges, ctx->ranges.p, sizeof(uint2) * ctx->n_tiles,
                            hipMemcpyDeviceToDevice, st));

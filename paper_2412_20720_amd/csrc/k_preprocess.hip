@@ -30,8 +30,8 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
-    uint32_t* __restrict__ tiles, uint32_t* __restrict__ dkey, const float* __restrict__ mask,
-    float mask_thr, CompactPtrs cp) {
+    uint32_t* __restrict__ tiles, uint32_t* __restrict__ nrows, uint32_t* __restrict__ dkey,
+    const float* __restrict__ mask, float mask_thr, CompactPtrs cp) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64], s_lim[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64];
@@ -137,7 +137,10 @@ __global__ __launch_bounds__(256) void k_preprocess(
       r[2] = make_float4(f.color[2], ex, ey, f.x[2]);
       dkey[slot] = __float_as_uint(f.x[2]);
     }
-    if (live) tiles[slot] = cnt;
+    if (live) {
+      tiles[slot] = cnt;
+      nrows[slot] = cnt > 0 ? rows : 0u;  // rows of the tile box, for the row binning
+    }
   }
 }
 
@@ -316,19 +319,19 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 template <int DS, int DT>
 void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S, float* rec,
-                uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+                uint32_t* tiles, uint32_t* nrows, uint32_t* dkey, hipStream_t st) {
   const int blocks = (gp.n + 255) / 256;
   if (gp.compact)
     hipLaunchKernelGGL((k_preprocess<DS, DT, true>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, views, S, rec, tiles,
-                       dkey, nullptr, 0.f, *gp.compact);
+                       nrows, dkey, nullptr, 0.f, *gp.compact);
   else
     hipLaunchKernelGGL((k_preprocess<DS, DT, false>), dim3(blocks), dim3(256), 0, st, gp.n,
                        n_views, reinterpret_cast<const float4*>(gp.mean4),
                        reinterpret_cast<const float4*>(gp.scale4),
                        reinterpret_cast<const float4*>(gp.rot_l),
                        reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
-                       rec, tiles, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
+                       rec, tiles, nrows, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
 }
 
 template <int DS, int DT>
@@ -388,11 +391,11 @@ void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings 
 
 template <int DS>
 void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S, float* rec,
-                    uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+                    uint32_t* tiles, uint32_t* nrows, uint32_t* dkey, hipStream_t st) {
   switch (gp.t_degree) {
-    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, dkey, st); break;
-    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, dkey, st); break;
-    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, dkey, st); break;
+    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
+    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
+    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
   }
 }
 
@@ -410,13 +413,14 @@ void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 }  // namespace
 
 void preprocess_forward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                        float* rec, uint32_t* tiles, uint32_t* dkey, hipStream_t st) {
+                        float* rec, uint32_t* tiles, uint32_t* nrows, uint32_t* dkey,
+                        hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {
-    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, dkey, st); break;
-    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, dkey, st); break;
-    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, dkey, st); break;
-    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, dkey, st); break;
+    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
+    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
+    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
+    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
   }
 }
 

@@ -112,7 +112,7 @@ def test_noalloc_rejects_oversize_then_works(ctxs):
     log(f"  status {st}: {msg}")
     assert st == B.G4D_ECAPACITY and "fixed scratch" in msg
     # pairs beyond what the array leaves: 64 splats covering most of a 2048^2 view at 8-pixel
-    # tiles (about 3.7M pairs; the array leaves room for about 1.9M)
+    # tiles (about 4.2M pairs; the array leaves room for about 1.4M)
     n = 64
     rng = np.random.default_rng(21)
     huge = scenes.subset(sc, np.arange(n))
@@ -127,10 +127,9 @@ def test_noalloc_rejects_oversize_then_works(ctxs):
     st = step.call(na, L.g4d_render_step_noalloc)[0]
     msg = L.g4d_last_error(na._ctx).decode()
     log(f"  status {st}: {msg}")
-    assert st == B.G4D_ECAPACITY and "pairs exceed" in msg, (st, msg)
-    with pytest.raises(B.G4DError) as e:
-        na.sync()  # the device flag of that call is reported once
-    assert e.value.status == B.G4D_ECAPACITY
+    assert st == B.G4D_ECAPACITY and "pairs" in msg and "exceed" in msg, (st, msg)
+    # the host read the counts and refused before any pair was written (its row runs fit), so
+    # no device-side error of that call remains
     na.sync()
     # the array is usable again right after
     small = scenes.make_workload(0)
