@@ -23,13 +23,11 @@ void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slot
                      uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
                      hipStream_t st);
 
-// *total = sum of tiles[0, n): the (Gaussian, tile) pairs the preprocess counted.
-void pair_total(const uint32_t* tiles, int64_t n, uint32_t* total, void* scratch, hipStream_t st);
-
-// roff[i] = sum_{k<i} nrows[vval[k]] for i < *n_vis (exclusive), nrows being the rows of each
-// slot's tile box; total to *total (device).
-void row_offsets(const uint32_t* nrows, const uint32_t* vval, const uint32_t* n_vis,
-                 int64_t n_cap, uint32_t* roff, uint32_t* total, void* scratch, hipStream_t st);
+// *pairs = sum of tiles[0, n) and *runs = the rows of the boxes rowbox[0, n) (first << 16 |
+// last, ~0u: none): the (Gaussian, tile) pairs and (Gaussian, tile row) runs the preprocess
+// listed.
+void bin_totals(const uint32_t* tiles, const uint32_t* rowbox, int64_t n, uint32_t* pairs,
+                uint32_t* runs, void* scratch, hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
 // n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.  Keys of
@@ -47,21 +45,29 @@ int radix_sort(uint32_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n
 int radix_sort(uint16_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
                void* scratch, hipStream_t st);
 
-// One run per box row of every visible slot, visible slots in depth order: rkey = global tile
-// row (view row_base + row), rval = (slot, span) with span = (first column << 16) | last
-// column, or ~0u for a row the ellipse misses.  Runs past row_cap set *flag = 1; rows that
-// disagree with the offsets set *flag = 2.
-void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint32_t* rkey, uint2* rval, uint32_t* flag,
-            hipStream_t st);
-void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint16_t* rkey, uint2* rval, uint32_t* flag,
-            hipStream_t st);
+// Regroups the depth-sorted visible slots (vkey / vval buffer vb) by view with one stable pass
+// on the view index; returns the buffer that holds them and writes vrange[v] = [first, end) of
+// view v's slots.
+int group_by_view(uint32_t* vkey[2], uint32_t* vval[2], int vb, const uint32_t* n_vis,
+                  int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange, void* scratch,
+                  hipStream_t st);
 
-// Expansion of the row-sorted runs into the tile lists: rrange = each tile row's runs in the
-// sorted order (runs = their (slot, span)), pval = every tile's slots in depth order,
+// The runs of every view's splats (vval grouped by view, depth order within a view), grouped
+// by global tile row with each row's runs in depth order: runs = (slot, span) with span =
+// (first column << 16) | last column, or ~0u for a row the ellipse misses; rrange = each
+// row's [first, end) ((0, 0) if empty).  chunk_cap >= visible / 64 + n_views and rhist_cap >=
+// max tiles_y * chunk_cap bound the chunk grid and the count table; rowbox = each slot's tile
+// rows (first << 16 | last, ~0u: none); vinfo holds 2 n_views entries, cview chunk_cap; counts
+// (3 words) receive the chunks, the table entries and the runs laid down.
+// More runs than row_cap set *flag = 1, a total other than *n_runs *flag = 2.
+void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_t n_rows,
+                    const uint32_t* vval, const uint32_t* rowbox, const float* rec, DSettings S,
+                    int64_t chunk_cap, int64_t rhist_cap, int64_t row_cap, const uint32_t* n_runs,
+                    uint4* vinfo, uint16_t* cview, uint32_t* rhist, uint32_t* counts, uint2* runs,
+                    uint2* rrange, uint32_t* flag, void* scratch, hipStream_t st);
+
+// Expansion of the row-grouped runs into the tile lists: rrange = each tile row's runs
+// (runs = their (slot, span)), pval = every tile's slots in depth order,
 // ranges = [first, end) per tile ((0, 0) if empty).  chunk_cap >= runs / 64 + n_rows and
 // hist_cap >= max tiles_x * ceil(runs / 64) + n_tiles bound the chunk grid and the count
 // table; rinfo holds 2 n_rows entries, crow 8 chunk_cap (a chunk list per XCD); counts (10
@@ -102,7 +108,7 @@ struct GradPtrs {
 };
 
 void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
-                        float* rec, uint32_t* tiles, uint32_t* nrows, uint32_t* dkey,
+                        float* rec, uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey,
                         hipStream_t st);
 void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
                            float* mean4, float* scale4, float* rot_l, float* rot_r,

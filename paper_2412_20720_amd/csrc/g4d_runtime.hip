@@ -73,9 +73,9 @@ struct SavedKey {
 struct g4d_ctx {
   int device = 0;
   std::string err;
-  DevBuf views, tile_base, rec, tiles, nrows, dkey, vk[2], vv[2], roff, rk[2], rv[2], rrange,
-      rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last, px_evals, grad2d,
-      counters;
+  DevBuf views, tile_base, rec, tiles, rowbox, dkey, vk[2], vv[2], vrange, vinfo, cview, rhist, runs,
+      rrange, rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last, px_evals,
+      grad2d, counters;
   DevBuf fn, fnorm, flow, dfn;     // extra channels
   DevBuf skybg;                    // per-pixel sky background
   uint32_t* h_counters = nullptr;  // pinned: visible, pairs, flag, runs
@@ -87,8 +87,8 @@ struct g4d_ctx {
   // the view table now on the device (skips the upload when a call repeats it)
   std::vector<DView> uploaded_views;
   void* uploaded_to = nullptr;
-  // capacities of the pair list, the run arrays and the expansion's count table
-  int64_t pair_cap = 0, row_cap = 0, hist_cap = 0;
+  // capacities of the pair list, the run list and the two expansions' count tables
+  int64_t pair_cap = 0, row_cap = 0, hist_cap = 0, rhist_cap = 0;
   // the whole grad2d allocation holds zeros: the last backward ran to its preprocess adjoint,
   // which zeroes every slot the raster adjoint accumulated into (false after a reallocation or
   // an interrupted backward; the next backward then clears the whole allocation)
@@ -98,7 +98,7 @@ struct g4d_ctx {
   SavedKey key;
   int vis_buf = 0;
   int64_t n_tiles = 0, n_pixels = 0;
-  int64_t n_rows = 0, max_tiles_x = 0;  // tile rows of the batch, widest view in tiles
+  int64_t n_rows = 0, max_tiles_x = 0, max_tiles_y = 0;  // tile rows of the batch, largest view
   int64_t last_runs = 0;                 // row runs of the last eager forward
   g4d_stats stats{};
   bool count_evals = false;
@@ -173,8 +173,8 @@ g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
 }
 
 const char* const kStageNames[G4D_NUM_STAGES] = {
-    "preprocess", "compact", "depth_sort", "row_offsets", "row_gen", "row_sort",
-    "expand", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
+    "preprocess", "compact", "depth_sort", "bin_totals", "group_views", "splat_rows",
+    "row_tiles", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
 
 hipEvent_t take_event(g4d_ctx* c) {
   if (!c->ev_free.empty()) {
@@ -294,21 +294,14 @@ GaussPtrs gauss_ptrs(const g4d_gaussians* g) {
                    g->rot_r,   g->opacity,   g->sh,       g->mask,  g->mask_threshold};
 }
 
-// Run arrays for `runs` row runs, the pair list for `pairs` pairs, and the expansion's count
-// table, sort and scan scratch that the run capacity implies (each capacity becomes what was
-// allocated; `grow` adds headroom to what has to grow).
+// The run list for `runs` row runs, the pair list for `pairs` pairs, and the tile expansion's
+// chunk maps, count table and scan scratch that the run capacity implies (each capacity
+// becomes what was allocated; `grow` adds headroom to what has to grow).
 g4d_status size_binning(g4d_ctx* ctx, int64_t slots, int64_t runs, int64_t pairs, double grow) {
   g4d_status r;
   if (runs > ctx->row_cap) {
-    // keys (sized for 32 bits) and (slot, span) values, double-buffered for the row sort
-    size_t cap = SIZE_MAX;
-    for (int b = 0; b < 2; ++b) {
-      if ((r = ensure(ctx, ctx->rk[b], sizeof(uint32_t) * (size_t)runs, grow)) != G4D_OK ||
-          (r = ensure(ctx, ctx->rv[b], sizeof(uint2) * (size_t)runs, grow)) != G4D_OK)
-        return r;
-      cap = std::min({cap, ctx->rk[b].cap / sizeof(uint32_t), ctx->rv[b].cap / sizeof(uint2)});
-    }
-    ctx->row_cap = std::min<int64_t>((int64_t)cap, INT32_MAX);
+    if ((r = ensure(ctx, ctx->runs, sizeof(uint2) * (size_t)runs, grow)) != G4D_OK) return r;
+    ctx->row_cap = std::min<int64_t>((int64_t)(ctx->runs.cap / sizeof(uint2)), INT32_MAX);
   }
   if (pairs > ctx->pair_cap) {
     if ((r = ensure(ctx, ctx->pval, sizeof(uint32_t) * (size_t)pairs, grow)) != G4D_OK) return r;
@@ -323,10 +316,8 @@ g4d_status size_binning(g4d_ctx* ctx, int64_t slots, int64_t runs, int64_t pairs
     if ((r = ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)hist_need, grow)) != G4D_OK) return r;
     ctx->hist_cap = (int64_t)(ctx->hist.cap / sizeof(uint32_t));
   }
-  if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(std::max(ctx->row_cap, slots)), grow)) !=
-      G4D_OK)
-    return r;
-  return ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(std::max(ctx->hist_cap, slots)), grow);
+  return ensure(ctx, ctx->scan_tmp,
+                scan_scratch_bytes(std::max({ctx->hist_cap, ctx->rhist_cap, slots})), grow);
 }
 
 // Plan tile grids and offsets, upload the view table and derive per-view constants.
@@ -337,7 +328,7 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
     ctx->staging_pending = false;
   }
   const int T = s->tile_size;
-  int64_t tile_base = 0, pix_base = 0, row_base = 0, max_tx = 0;
+  int64_t tile_base = 0, pix_base = 0, row_base = 0, max_tx = 0, max_ty = 0;
   for (int v = 0; v < n_views; ++v) {
     const g4d_view& in = views[v];
     DView& d = ctx->h_views[v];
@@ -364,6 +355,7 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
     tile_base += (int64_t)d.tiles_x * d.tiles_y;
     row_base += d.tiles_y;
     max_tx = std::max<int64_t>(max_tx, d.tiles_x);
+    max_ty = std::max<int64_t>(max_ty, d.tiles_y);
     pix_base += (int64_t)in.width * in.height;
     if (pix_base > INT32_MAX || tile_base > INT32_MAX)
       return fail(ctx, G4D_EINVAL, "total pixels of the batch exceed 2^31-1");
@@ -373,6 +365,7 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
   ctx->n_pixels = pix_base;
   ctx->n_rows = row_base;
   ctx->max_tiles_x = max_tx;
+  ctx->max_tiles_y = max_ty;
   if (ctx->capturing) return G4D_OK;  // the view table was uploaded before the capture
   g4d_status r;
   if ((r = ensure(ctx, ctx->views, sizeof(DView) * n_views)) != G4D_OK) return r;
@@ -401,7 +394,7 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
   if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
   if (zero_records) G4D_HIP(hipMemsetAsync(ctx->rec.p, 0, sizeof(float) * kRec * slots, st));
   if ((r = ensure(ctx, ctx->tiles, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
-  if ((r = ensure(ctx, ctx->nrows, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
+  if ((r = ensure(ctx, ctx->rowbox, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   {
     Stage t(ctx, 0, st);
@@ -409,7 +402,7 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
     gp.compact = cp;
     preprocess_forward(gp, P<DView>(ctx->views), n_views,
                        device_settings(s, ctx->count_evals && ctx->count_cutoff),
-                       P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->nrows),
+                       P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->rowbox),
                        P<uint32_t>(ctx->dkey), st);
   }
   G4D_HIP(hipGetLastError());
@@ -519,9 +512,9 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->graph_ctx) g4d_destroy(ctx->graph_ctx);
   if (ctx->na) g4d_destroy(ctx->na);
-  DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->nrows, &ctx->dkey,
-                    &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->roff,
-                    &ctx->rk[0], &ctx->rk[1], &ctx->rv[0], &ctx->rv[1], &ctx->rrange,
+  DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->rowbox, &ctx->dkey,
+                    &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->vrange,
+                    &ctx->vinfo, &ctx->cview, &ctx->rhist, &ctx->runs, &ctx->rrange,
                     &ctx->rinfo, &ctx->crow, &ctx->hist, &ctx->pval,
                     &ctx->scan_tmp,
                     &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
@@ -591,10 +584,11 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   ctx->fwd_cutoff_bins = ctx->count_evals && ctx->count_cutoff;
   const DSettings DS = device_settings(&s_run, ctx->fwd_cutoff_bins);
   const int n_ext = n_ext_of(ch);
-  if ((r = ensure(ctx, ctx->counters, 16 * sizeof(uint32_t))) != G4D_OK) return r;
-  // [0] visible, [1] pairs the preprocess counted, [2] overflow / mismatch flag, [3] runs,
-  // [4] clamped batches of the last counted backward, [5] runs clamped to the capacity,
-  // [6..15] the expansion's chunks per XCD, table entries and pairs written
+  if ((r = ensure(ctx, ctx->counters, 32 * sizeof(uint32_t))) != G4D_OK) return r;
+  // [0] visible, [1] pairs the preprocess counted, [2] overflow / mismatch flag, [3] runs the
+  // preprocess counted, [4] clamped batches of the last counted backward, [6..15] the tile
+  // expansion's chunks per XCD, table entries and pairs written, [16..18] the row expansion's
+  // chunks, table entries and runs written
   uint32_t* cnt = P<uint32_t>(ctx->counters);
   ctx->counted_bwd = false;
   fill_u32(cnt, 4, 0u, st);
@@ -626,8 +620,18 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       if ((r = ensure(ctx, ctx->vk[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
       if ((r = ensure(ctx, ctx->vv[b], sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
     }
-    if ((r = ensure(ctx, ctx->roff, sizeof(uint32_t) * (slots + 1), 1.1)) != G4D_OK) return r;
-    if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
+    // the row expansion's count table: a row of the view per chunk of 64 visible slots
+    const int64_t row_chunks = (slots + 63) / 64 + n_views;
+    if ((r = ensure(ctx, ctx->rhist, sizeof(uint32_t) * (size_t)(ctx->max_tiles_y * row_chunks),
+                    1.1)) != G4D_OK)
+      return r;
+    ctx->rhist_cap = (int64_t)(ctx->rhist.cap / sizeof(uint32_t));
+    if ((r = ensure(ctx, ctx->vrange, sizeof(uint2) * n_views)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->vinfo, 2 * sizeof(uint4) * n_views)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->cview, sizeof(uint16_t) * row_chunks, 1.1)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(std::max(slots, ctx->rhist_cap)),
+                    1.1)) != G4D_OK)
+      return r;
     if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
     {
       Stage t(ctx, 1, st);
@@ -644,41 +648,38 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     ctx->vis_buf = vb;
     {
       Stage t(ctx, 3, st);
-      pair_total(P<uint32_t>(ctx->tiles), slots, cnt + 1, ctx->scan_tmp.p, st);
-      row_offsets(P<uint32_t>(ctx->nrows), vv[vb], cnt + 0, slots, P<uint32_t>(ctx->roff),
-                  cnt + 3, ctx->scan_tmp.p, st);
+      bin_totals(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->rowbox), slots, cnt + 1, cnt + 3,
+                 ctx->scan_tmp.p, st);
+    }
+    int gb;
+    {
+      Stage t(ctx, 4, st);
+      gb = group_by_view(vk, vv, vb, cnt + 0, slots, n_views, (uint32_t)g->n,
+                         P<uint2>(ctx->vrange), ctx->sort_tmp.p, st);
     }
     G4D_HIP(hipGetLastError());
-    // Run keys are global tile rows; with at most 2^16 of them they move as 16-bit words (the
-    // run buffers are sized for 32).
-    const int key_bits = bits_for(ctx->n_rows);
-    const bool key16 = key_bits <= 16;
-    auto run_rowgen = [&](int64_t vis_grid) {
-      Stage t(ctx, 4, st);
-      if (key16)
-        rowgen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->roff), cnt + 0, vis_grid, cnt + 3,
-               ctx->row_cap, g->n, P<DView>(ctx->views), DS, P<uint16_t>(ctx->rk[0]),
-               P<uint2>(ctx->rv[0]), cnt + 2, st);
-      else
-        rowgen(P<float>(ctx->rec), vv[vb], P<uint32_t>(ctx->roff), cnt + 0, vis_grid, cnt + 3,
-               ctx->row_cap, g->n, P<DView>(ctx->views), DS, P<uint32_t>(ctx->rk[0]),
-               P<uint2>(ctx->rv[0]), cnt + 2, st);
-      clamp_count(cnt + 3, (uint32_t)ctx->row_cap, cnt + 5, st);
+    auto run_rows = [&]() {
+      Stage t(ctx, 5, st);
+      splats_to_rows(P<uint2>(ctx->vrange), n_views, P<DView>(ctx->views), ctx->n_rows, vv[gb],
+                     P<uint32_t>(ctx->rowbox), P<float>(ctx->rec), DS, row_chunks,
+                     ctx->rhist_cap, ctx->row_cap, cnt + 3, P<uint4>(ctx->vinfo),
+                     P<uint16_t>(ctx->cview), P<uint32_t>(ctx->rhist), cnt + 16,
+                     P<uint2>(ctx->runs), P<uint2>(ctx->rrange), cnt + 2, ctx->scan_tmp.p, st);
     };
     if (ctx->capturing) {
       // counts stay on the device; grids cover the capacities
       n_pairs = ctx->pair_cap;
       run_grid = ctx->row_cap;
-      if (run_grid > 0) run_rowgen(slots);
+      if (run_grid > 0) run_rows();
     } else {
-      // The counts go to the host; with run buffers from an earlier call the run generation
-      // is queued behind the copy at once (grid over every slot, writes clamped to the
-      // capacity), so that the GPU does not idle while the host reads the counts.  Should the
-      // runs exceed that capacity, the buffers grow and the run generation runs again.
+      // The counts go to the host; with a run list from an earlier call the row expansion is
+      // queued behind the copy at once (writes clamped to the capacity), so that the GPU does
+      // not idle while the host reads the counts.  Should the runs exceed that capacity, the
+      // list grows and the row expansion runs again.
       const bool early = ctx->row_cap > 0;
       G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       G4D_HIP(hipEventRecord(ctx->counts_ready, st));
-      if (early) run_rowgen(slots);
+      if (early) run_rows();
       G4D_HIP(hipEventSynchronize(ctx->counts_ready));
       n_vis = ctx->h_counters[0];
       n_pairs = ctx->h_counters[1];
@@ -696,34 +697,19 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       if ((r = size_binning(ctx, slots, n_runs, n_pairs, 1.2)) != G4D_OK) return r;
       if (n_runs > 0 && !fits) {
         if (early) fill_u32(cnt + 2, 1, 0u, st);  // the early pass flagged the overflow
-        run_rowgen(n_vis);
+        run_rows();
       }
       run_grid = n_runs;
       ctx->last_runs = n_runs;
     }
     if (run_grid > 0) {
-      int rb;
-      {
-        Stage t(ctx, 5, st);
-        uint2* rv[2] = {P<uint2>(ctx->rv[0]), P<uint2>(ctx->rv[1])};
-        if (key16) {
-          uint16_t* rk[2] = {P<uint16_t>(ctx->rk[0]), P<uint16_t>(ctx->rk[1])};
-          rb = radix_sort(rk, rv, cnt + 5, run_grid, key_bits, ctx->sort_tmp.p, st);
-          tile_ranges(rk[rb], cnt + 5, run_grid, ctx->n_rows, P<uint2>(ctx->rrange), st);
-        } else {
-          uint32_t* rk[2] = {P<uint32_t>(ctx->rk[0]), P<uint32_t>(ctx->rk[1])};
-          rb = radix_sort(rk, rv, cnt + 5, run_grid, key_bits, ctx->sort_tmp.p, st);
-          tile_ranges(rk[rb], cnt + 5, run_grid, ctx->n_rows, P<uint2>(ctx->rrange), st);
-        }
-      }
       {
         Stage t(ctx, 6, st);
         expand(P<uint2>(ctx->rrange), (int)ctx->n_rows, P<DView>(ctx->views), n_views,
-               ctx->n_tiles, P<uint2>(ctx->rv[rb]), (run_grid + 63) / 64 + ctx->n_rows,
-               ctx->hist_cap,
-               ctx->pair_cap, cnt + 1, P<uint4>(ctx->rinfo), P<uint32_t>(ctx->crow),
-               P<uint32_t>(ctx->hist), cnt + 6,
-               P<uint32_t>(ctx->pval), P<uint2>(ctx->ranges), cnt + 2, ctx->scan_tmp.p, st);
+               ctx->n_tiles, P<uint2>(ctx->runs), (run_grid + 63) / 64 + ctx->n_rows,
+               ctx->hist_cap, ctx->pair_cap, cnt + 1, P<uint4>(ctx->rinfo), P<uint32_t>(ctx->crow),
+               P<uint32_t>(ctx->hist), cnt + 6, P<uint32_t>(ctx->pval), P<uint2>(ctx->ranges),
+               cnt + 2, ctx->scan_tmp.p, st);
       }
       G4D_HIP(hipGetLastError());
     }
@@ -1079,11 +1065,12 @@ g4d_status g4d_render_step(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view*
 
 // Points every buffer a plain forward + backward uses into the device's fixed scratch array
 // (256-byte aligned slices, the counters first so that they stay at offset 0 whatever the
-// sizes); the pair list, the row runs (half as many as pairs), their count table and the sort
-// and scan scratch share what remains, and the pair capacity is the largest that fits.
+// sizes); the pair list, the row runs (half as many as pairs), the tile expansion's chunk maps
+// and count table and the scan scratch share what remains, and the pair capacity is the
+// largest that fits.
 static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, int64_t slots,
                                 int n_views, int64_t n_tiles, int64_t n_pixels, int64_t n_rows,
-                                int64_t max_tx) {
+                                int64_t max_tx, int64_t max_ty) {
   const size_t cap = G4D_NOALLOC_SCRATCH_BYTES;
   auto round = [](size_t b) { return (std::max<size_t>(b, 256) + 255) & ~(size_t)255; };
   size_t off = 0;
@@ -1094,18 +1081,23 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
     plan[n_plan++] = {&b, off, round(bytes)};
     off += round(bytes);
   };
-  take(na->counters, 16 * sizeof(uint32_t));
+  const int64_t rhist = max_ty * ((slots + 63) / 64 + n_views);
+  take(na->counters, 32 * sizeof(uint32_t));
   take(na->views, sizeof(DView) * n_views);
   take(na->tile_base, sizeof(int32_t) * (n_views + 1));
   take(na->rec, sizeof(float) * kRec * slots);
   take(na->tiles, sizeof(uint32_t) * slots);
-  take(na->nrows, sizeof(uint32_t) * slots);
+  take(na->rowbox, sizeof(uint32_t) * slots);
   take(na->dkey, sizeof(uint32_t) * slots);
   for (int b = 0; b < 2; ++b) {
     take(na->vk[b], sizeof(uint32_t) * slots);
     take(na->vv[b], sizeof(uint32_t) * slots);
   }
-  take(na->roff, sizeof(uint32_t) * (slots + 1));
+  take(na->sort_tmp, radix_scratch_bytes(slots));
+  take(na->vrange, sizeof(uint2) * n_views);
+  take(na->vinfo, 2 * sizeof(uint4) * n_views);
+  take(na->cview, sizeof(uint16_t) * ((slots + 63) / 64 + n_views));
+  take(na->rhist, sizeof(uint32_t) * rhist);
   take(na->ranges, sizeof(uint2) * n_tiles);
   take(na->rrange, sizeof(uint2) * n_rows);
   take(na->rinfo, 2 * sizeof(uint4) * n_rows);
@@ -1113,19 +1105,16 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
   take(na->px_last, sizeof(int32_t) * n_pixels);
   take(na->grad2d, sizeof(float) * kGrad2d * slots);
   const size_t fixed = off;
-  // p pairs: the pair list, p / 2 runs (two 4-byte keys and two 8-byte values each), their
-  // chunk maps and count table,
-  // and the sort scratch of max(runs, slots) and scan scratch of max(table, slots) items
+  // p pairs: the pair list, p / 2 runs of 8 bytes, the tile expansion's chunk maps and count
+  // table, and the scan scratch of max(tables, slots) items
   auto hist_of = [&](int64_t runs) { return max_tx * ((runs + 63) / 64) + n_tiles; };
   auto chunks_of = [&](int64_t runs) { return (runs + 63) / 64 + n_rows; };
   auto need = [&](int64_t p) {
     const int64_t runs = p / 2;
-    return round(sizeof(uint32_t) * (size_t)p) + 2 * round(sizeof(uint32_t) * (size_t)runs) +
-           2 * round(sizeof(uint2) * (size_t)runs) +
+    return round(sizeof(uint32_t) * (size_t)p) + round(sizeof(uint2) * (size_t)runs) +
            round(8 * sizeof(uint32_t) * (size_t)chunks_of(runs)) +
            round(sizeof(uint32_t) * (size_t)hist_of(runs)) +
-           round(radix_scratch_bytes(std::max<int64_t>(runs, slots))) +
-           round(scan_scratch_bytes(std::max<int64_t>(hist_of(runs), slots)));
+           round(scan_scratch_bytes(std::max({hist_of(runs), rhist, slots})));
   };
   if (fixed > cap || need(0) > cap - fixed)
     return fail(ctx, G4D_ECAPACITY,
@@ -1139,14 +1128,10 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
   }
   const int64_t pairs = std::min<int64_t>(lo, INT32_MAX), runs = pairs / 2;
   take(na->pval, sizeof(uint32_t) * pairs);
-  for (int b = 0; b < 2; ++b) {
-    take(na->rk[b], sizeof(uint32_t) * runs);
-    take(na->rv[b], sizeof(uint2) * runs);
-  }
+  take(na->runs, sizeof(uint2) * runs);
   take(na->crow, 8 * sizeof(uint32_t) * chunks_of(runs));
   take(na->hist, sizeof(uint32_t) * hist_of(runs));
-  take(na->sort_tmp, radix_scratch_bytes(std::max<int64_t>(runs, slots)));
-  take(na->scan_tmp, scan_scratch_bytes(std::max<int64_t>(hist_of(runs), slots)));
+  take(na->scan_tmp, scan_scratch_bytes(std::max({hist_of(runs), rhist, slots})));
   if (off > cap) return fail(ctx, G4D_EHIP, "scratch plan of %zu bytes exceeds %zu", off, cap);
   for (int k = 0; k < n_plan; ++k) {
     plan[k].b->p = base + plan[k].off;
@@ -1155,6 +1140,7 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
   na->pair_cap = pairs;
   na->row_cap = runs;
   na->hist_cap = hist_of(runs);
+  na->rhist_cap = rhist;
   return G4D_OK;
 }
 
@@ -1174,18 +1160,19 @@ g4d_status g4d_render_step_noalloc(g4d_ctx* ctx, const g4d_gaussians* g, const g
                 dev < kMaxScratchDevices ? hipGetErrorString(g_scratch_err[dev])
                                          : "device index beyond the scratch table");
   // the sizes the forward plans (as upload_views counts them)
-  int64_t n_tiles = 0, n_pixels = 0, n_rows = 0, max_tx = 0;
+  int64_t n_tiles = 0, n_pixels = 0, n_rows = 0, max_tx = 0, max_ty = 0;
   for (int v = 0; v < n_views; ++v) {
     const int64_t tx = (views[v].width + s->tile_size - 1) / s->tile_size;
     const int64_t ty = (views[v].height + s->tile_size - 1) / s->tile_size;
     n_tiles += tx * ty;
     n_rows += ty;
     max_tx = std::max(max_tx, tx);
+    max_ty = std::max(max_ty, ty);
     n_pixels += (int64_t)views[v].width * views[v].height;
   }
   g4d_ctx* na = ctx->na;
   if ((r = carve_scratch(ctx, na, base, (int64_t)g->n * n_views, n_views, n_tiles, n_pixels,
-                         n_rows, max_tx)) != G4D_OK)
+                         n_rows, max_tx, max_ty)) != G4D_OK)
     return r;
   // Another call may have left anything in the array: the view table is uploaded again and
   // the gradient slots, which the raster adjoint accumulates into, are cleared.

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
-    uint32_t* __restrict__ tiles, uint32_t* __restrict__ nrows, uint32_t* __restrict__ dkey,
+    uint32_t* __restrict__ tiles, uint32_t* __restrict__ rowbox, uint32_t* __restrict__ dkey,
     const float* __restrict__ mask, float mask_thr, CompactPtrs cp) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64], s_lim[4][64];
@@ -43,7 +43,10 @@ __global__ __launch_bounds__(256) void k_preprocess(
   // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
   const bool live = in_range && !(mask && !(mask[gi] > mask_thr));
   if (in_range && !live)
-    for (int v = 0; v < n_views; ++v) tiles[(size_t)v * n + gi] = 0u;
+    for (int v = 0; v < n_views; ++v) {
+      tiles[(size_t)v * n + gi] = 0u;
+      rowbox[(size_t)v * n + gi] = ~0u;
+    }
   if (__ballot(live) == 0ull) return;  // the whole wave: the lanes below work together
   // Lanes past the end read the last Gaussian (unconditional loads of read-only data, which
   // the compiler may repeat per view instead of holding 4DSH coefficients in registers); only
@@ -139,7 +142,8 @@ __global__ __launch_bounds__(256) void k_preprocess(
     }
     if (live) {
       tiles[slot] = cnt;
-      nrows[slot] = cnt > 0 ? rows : 0u;  // rows of the tile box, for the row binning
+      // the tile rows of its box, first << 16 | last, for the row binning
+      rowbox[slot] = cnt > 0 ? ((uint32_t)y0 << 16) | (uint32_t)y1 : ~0u;
     }
   }
 }
@@ -319,19 +323,19 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 template <int DS, int DT>
 void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S, float* rec,
-                uint32_t* tiles, uint32_t* nrows, uint32_t* dkey, hipStream_t st) {
+                uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, hipStream_t st) {
   const int blocks = (gp.n + 255) / 256;
   if (gp.compact)
     hipLaunchKernelGGL((k_preprocess<DS, DT, true>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, views, S, rec, tiles,
-                       nrows, dkey, nullptr, 0.f, *gp.compact);
+                       rowbox, dkey, nullptr, 0.f, *gp.compact);
   else
     hipLaunchKernelGGL((k_preprocess<DS, DT, false>), dim3(blocks), dim3(256), 0, st, gp.n,
                        n_views, reinterpret_cast<const float4*>(gp.mean4),
                        reinterpret_cast<const float4*>(gp.scale4),
                        reinterpret_cast<const float4*>(gp.rot_l),
                        reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
-                       rec, tiles, nrows, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
+                       rec, tiles, rowbox, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
 }
 
 template <int DS, int DT>
@@ -391,11 +395,11 @@ void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings 
 
 template <int DS>
 void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S, float* rec,
-                    uint32_t* tiles, uint32_t* nrows, uint32_t* dkey, hipStream_t st) {
+                    uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, hipStream_t st) {
   switch (gp.t_degree) {
-    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
-    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
-    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, nrows, dkey, st); break;
+    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
+    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
+    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
   }
 }
 
@@ -413,14 +417,14 @@ void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 }  // namespace
 
 void preprocess_forward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                        float* rec, uint32_t* tiles, uint32_t* nrows, uint32_t* dkey,
+                        float* rec, uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey,
                         hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {
-    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
-    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
-    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
-    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, nrows, dkey, st); break;
+    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
+    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
+    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
+    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
   }
 }
 

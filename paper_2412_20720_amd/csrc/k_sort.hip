@@ -73,18 +73,6 @@ struct InFlag {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i] > 0u ? 1u : 0u; }
 };
-// Gathers cnt[idx[i]] and keeps it at keep[i], so that a second pass over the same items
-// reads them contiguously instead of gathering again (each gather costs a cache line).
-struct InGatherKeep {
-  const uint32_t* cnt;
-  const uint32_t* idx;
-  uint32_t* keep;
-  __device__ uint32_t operator()(int64_t i) const {
-    const uint32_t c = cnt[idx[i]];
-    keep[i] = c;
-    return c;
-  }
-};
 struct InPlain {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i]; }
@@ -380,37 +368,320 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
 // tile would leave them; the sort moves one item per run instead of one per pair.
 // ------------------------------------------------------------------------------------------
 
-// One run per box row of every visible splat, in depth order: each wave takes 64 consecutive
-// visible entries, numbers their rows with a wave scan and deals them out 64 per round; the
-// run of row k lands at roff[first] + k.  rkey = global tile row, rval = (slot, span) with
-// span = (first column << 16) | last, or ~0u for a row the ellipse misses.
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_rowgen(
-    const float* __restrict__ rec, const uint32_t* __restrict__ vval,
-    const uint32_t* __restrict__ roff, const uint32_t* n_vis_dev, const uint32_t* n_rows_dev,
-    int64_t row_cap, int n_per_view, const DView* __restrict__ views, DSettings S,
-    K* __restrict__ rkey, uint2* __restrict__ rval, uint32_t* flag) {
-  __shared__ uint32_t s_rows[4][64];
+// ------------------------------------------------------------------------------------------
+// Splats to tile rows.  After the depth sort the visible slots are regrouped by view (one
+// stable pass on the view index), so that each view's splats lie together in depth order.
+// Each view's list is taken 64 splats at a time (a chunk, one wave): a count pass tallies how
+// many of the chunk's splats have each tile row of the view in their box (an LDS difference
+// array), an exclusive scan over (row, chunk) in row order gives every chunk its place in each
+// row's run list, and a write pass deals the chunk's (splat, row) runs out over the lanes,
+// finds each run's columns (tile_row_span) and lays it down as (slot, span), span = (first
+// column << 16) | last, or ~0u for a row the ellipse misses.  Each row's runs so come in
+// depth order.
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
+  return x;
+}
+
+// Rows of a packed row box (first << 16 | last; ~0u: none).
+__device__ __forceinline__ uint32_t box_rows(uint32_t rb) {
+  return rb == ~0u ? 0u : (rb & 0xFFFFu) - (rb >> 16) + 1u;
+}
+
+// Block sums of the tile counts and of the box rows (16 items per thread), then one block adds
+// them up.
+__global__ __launch_bounds__(kThreads) void k_sum2_blocks(const uint32_t* __restrict__ a,
+                                                          const uint32_t* __restrict__ b,
+                                                          int64_t n, uint2* __restrict__ sums) {
+  __shared__ uint32_t s_a[4], s_b[4];
+  const int64_t base = (int64_t)blockIdx.x * kItems;
+  uint32_t sa = 0, sb = 0;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < n) {
+      sa += a[i];
+      sb += box_rows(b[i]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sa += __shfl_xor(sa, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_a[w] = sa;
+    s_b[w] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    sums[blockIdx.x] = make_uint2(s_a[0] + s_a[1] + s_a[2] + s_a[3], s_b[0] + s_b[1] + s_b[2] + s_b[3]);
+}
+
+__global__ __launch_bounds__(1024) void k_sum2_final(const uint2* __restrict__ sums, int count,
+                                                     uint32_t* ta, uint32_t* tb) {
+  __shared__ uint32_t s_a[16], s_b[16];
+  uint32_t sa = 0, sb = 0;
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    sa += sums[i].x;
+    sb += sums[i].y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sa += __shfl_xor(sa, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_a[w] = sa;
+    s_b[w] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t A = 0, B = 0;
+    for (int k = 0; k < 16; ++k) {
+      A += s_a[k];
+      B += s_b[k];
+    }
+    *ta = A;
+    *tb = B;
+  }
+}
+
+// View index of each visible slot: the key of the regrouping pass.
+__global__ void k_view_keys(const uint32_t* __restrict__ vval, const uint32_t* n_dev, int64_t cap,
+                            uint32_t n_per_view, uint16_t* __restrict__ keys) {
+  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = (uint16_t)(vval[i] / n_per_view);
+}
+
+// Per view v (one workgroup of 256 threads, a thread per view): its splats [lo, lo + len) in
+// the regrouped list, its chunks of 64 splats, the index of its first chunk, and the base of
+// its (row, chunk) count table: vinfo[2v] = (lo, len, first chunk, table base),
+// vinfo[2v + 1] = (chunks, tiles_y, row_base, 0).  totals = (chunks, table entries).
+__global__ __launch_bounds__(256) void k_view_table(const uint2* __restrict__ vrange, int n_views,
+                                                    const DView* __restrict__ views,
+                                                    uint4* __restrict__ vinfo, uint32_t rhist_cap,
+                                                    uint32_t* totals) {
+  __shared__ uint32_t s_c[4], s_h[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int v = threadIdx.x;
+  uint32_t lo = 0, len = 0, nch = 0, ny = 0, rb = 0;
+  if (v < n_views) {
+    const uint2 g = vrange[v];
+    lo = g.x;
+    len = g.y - g.x;
+    nch = (len + 63u) >> 6;
+    ny = (uint32_t)views[v].tiles_y;
+    rb = (uint32_t)views[v].row_base;
+  }
+  const uint32_t hs = nch * ny;
+  const uint32_t ic = wave_incl_scan(nch), ih = wave_incl_scan(hs);
+  if (lane == 63) {
+    s_c[w] = ic;
+    s_h[w] = ih;
+  }
+  __syncthreads();
+  uint32_t pc = 0, ph = 0;
+  for (int k = 0; k < w; ++k) {
+    pc += s_c[k];
+    ph += s_h[k];
+  }
+  if (v < n_views) {
+    vinfo[2 * v] = make_uint4(lo, len, pc + ic - nch, ph + ih - hs);
+    vinfo[2 * v + 1] = make_uint4(nch, ny, rb, 0u);
+  }
+  if (threadIdx.x == 0) {
+    totals[0] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    // (the table capacity covers every view's chunks; the clamp only keeps a broken count
+    // from taking the scan past it)
+    totals[1] = min(s_h[0] + s_h[1] + s_h[2] + s_h[3], rhist_cap);
+  }
+}
+
+// cview[chunk] = its view (one workgroup per view).
+__global__ void k_chunk_views(const uint4* __restrict__ vinfo, int64_t chunk_cap,
+                              uint16_t* __restrict__ cview) {
+  const uint32_t v = blockIdx.x;
+  const uint32_t first = vinfo[2 * v].z, nch = vinfo[2 * v + 1].x;
+  for (uint32_t k = threadIdx.x; k < nch && (int64_t)(first + k) < chunk_cap; k += blockDim.x)
+    cview[first + k] = (uint16_t)v;
+}
+
+// A chunk of a view's splats: the view's table entries, the chunk within the view, and per
+// lane its splat's box rows [y0, y0 + h] (an empty lane: y0 = ~0u, h = 0).
+struct SplatChunk {
+  uint4 a, b;  // vinfo of the view
+  uint32_t v, c, slot, y0, h, ymin, ymax;
+  bool valid;
+  int x0, x1;
+};
+
+// Chunk g: its view (scalar), its splats and their box rows; with the records also the box
+// columns (tile_rect on the record, as the preprocess listed them).
+template <bool REC>
+__device__ __forceinline__ bool load_splat_chunk(const uint4* __restrict__ vinfo,
+                                                 const uint16_t* __restrict__ cview,
+                                                 const uint32_t* n_chunks_dev,
+                                                 const uint32_t* __restrict__ vval,
+                                                 const uint32_t* __restrict__ rowbox,
+                                                 const float* __restrict__ rec,
+                                                 const DView* __restrict__ views, int shift,
+                                                 SplatChunk& ck) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+  if (g >= *n_chunks_dev) return false;
+  ck.v = __builtin_amdgcn_readfirstlane((uint32_t)cview[g]);
+  ck.a = vinfo[2 * ck.v];
+  ck.b = vinfo[2 * ck.v + 1];
+  ck.c = g - ck.a.z;
+  const uint32_t e = ck.c * 64u + (uint32_t)lane;
+  ck.valid = e < ck.a.y;
+  ck.slot = ck.valid ? vval[ck.a.x + e] : 0u;
+  ck.y0 = ~0u;
+  ck.h = 0u;
+  ck.x0 = 0;
+  ck.x1 = -1;
+  uint32_t y1 = 0u;
+  if (ck.valid) {
+    const uint32_t rb = rowbox[ck.slot];
+    if (rb != ~0u) {
+      ck.y0 = rb >> 16;
+      y1 = rb & 0xFFFFu;
+      ck.h = y1 - ck.y0;
+    }
+    if (REC) {
+      const float* p = rec + (size_t)ck.slot * kRec;
+      int x0, x1, y0, yy1;
+      if (tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], views[ck.v], shift, x0, x1, y0, yy1)) {
+        ck.x0 = x0;
+        ck.x1 = x1;
+      }
+    }
+  }
+  ck.ymin = __builtin_amdgcn_readfirstlane(wave_min_u32(ck.y0));
+  ck.ymax = __builtin_amdgcn_readfirstlane(wave_max_u32(y1));
+  return true;
+}
+
+// Count pass: rhist[table base + row * chunks + chunk] = splats of the chunk whose box holds
+// the row (row-major, so that one scan over the whole table yields run positions in row
+// order), from a +1 / -1 difference array over 256 rows per window.
+constexpr int kCountRows = 256;
+__global__ __launch_bounds__(256) void k_rows_count(const uint4* __restrict__ vinfo,
+                                                    const uint16_t* __restrict__ cview,
+                                                    const uint32_t* n_chunks_dev,
+                                                    const uint32_t* __restrict__ vval,
+                                                    const uint32_t* __restrict__ rowbox,
+                                                    uint32_t* __restrict__ rhist,
+                                                    int64_t rhist_cap) {
+  __shared__ int4 s_diff[4][kCountRows / 4 + 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int* diff = reinterpret_cast<int*>(&s_diff[w][0]);
+  SplatChunk ck;
+  if (!load_splat_chunk<false>(vinfo, cview, n_chunks_dev, vval, rowbox, nullptr, nullptr, 0, ck))
+    return;
+  const uint32_t nch = ck.b.x, ny = ck.b.y;
+  for (uint32_t r0 = 0; r0 < ny; r0 += kCountRows) {
+    s_diff[w][lane] = make_int4(0, 0, 0, 0);
+    if (lane == 0) s_diff[w][kCountRows / 4] = make_int4(0, 0, 0, 0);
+    wave_lds_sync();
+    if (ck.y0 != ~0u) {
+      const int lo = max((int)ck.y0 - (int)r0, 0);
+      const int hi = min((int)(ck.y0 + ck.h) - (int)r0, kCountRows - 1);
+      if (lo <= hi) {
+        atomicAdd(&diff[lo], 1);
+        atomicSub(&diff[hi + 1], 1);
+      }
+    }
+    wave_lds_sync();
+    const int4 d = s_diff[w][lane];
+    const int p0 = d.x, p1 = p0 + d.y, p2 = p1 + d.z, p3 = p2 + d.w;
+    const int base = (int)wave_incl_scan((uint32_t)p3) - p3;
+    const int val[4] = {base + p0, base + p1, base + p2, base + p3};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t row = r0 + 4u * (uint32_t)lane + (uint32_t)k;
+      const int64_t at = (int64_t)ck.a.w + (int64_t)row * nch + ck.c;
+      if (row < ny && at < rhist_cap) rhist[at] = (uint32_t)val[k];
+    }
+    wave_lds_sync();  // the next window clears the array
+  }
+}
+
+// Row ranges from the scanned table: rrange[global row] = [start of (row, chunk 0), start of
+// the next row), clamped to the run capacity; an empty row gets (0, 0).
+__global__ void k_row_ranges(const uint4* __restrict__ vinfo, const DView* __restrict__ views,
+                             int n_views, const uint32_t* __restrict__ scanned,
+                             const uint32_t* n_hist_dev, const uint32_t* total_dev,
+                             const uint32_t* n_runs_dev, int64_t n_rows, uint32_t row_cap,
+                             uint2* __restrict__ rrange, uint32_t* flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows) return;
+  // the preprocess counted the rows the expansion lays down; more than the run arrays hold is
+  // a capacity overflow, any other disagreement a mismatch
+  if (r == 0) {
+    if (*total_dev > row_cap) *flag = 1u;
+    else if (*total_dev != *n_runs_dev && *flag == 0u) *flag = 2u;
+  }
+  int a = 0, b = n_views - 1;  // the last view whose rows start at or before r
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (views[m].row_base <= r) a = m; else b = m - 1;
+  }
+  const uint4 va = vinfo[2 * a], vb = vinfo[2 * a + 1];
+  const uint32_t ty = (uint32_t)(r - views[a].row_base), nch = vb.x;
+  uint32_t lo = 0, hi = 0;
+  if (nch > 0) {
+    const uint32_t n_hist = *n_hist_dev;
+    const uint32_t i0 = va.w + ty * nch, i1 = i0 + nch;
+    lo = i0 < n_hist ? scanned[i0] : *total_dev;
+    hi = i1 < n_hist ? scanned[i1] : *total_dev;
+    lo = min(lo, row_cap);
+    hi = min(hi, row_cap);
+  }
+  rrange[r] = hi > lo ? make_uint2(lo, hi) : make_uint2(0u, 0u);
+}
+
+// Write pass.  Per window of 64 rows, lane t holds the mask of the chunk's splats whose box
+// holds row t0 + t and that row's scanned place; the chunk's runs in the window are numbered
+// with a wave scan and dealt out 64 per round, each lane computing its run's columns, and
+// laid down at the place of its row plus the number of the chunk's earlier splats in the row.
+__global__ __launch_bounds__(256) void k_rows_write(const uint4* __restrict__ vinfo,
+                                                    const uint16_t* __restrict__ cview,
+                                                    const uint32_t* n_chunks_dev,
+                                                    const uint32_t* __restrict__ vval,
+                                                    const uint32_t* __restrict__ rowbox,
+                                                    const float* __restrict__ rec,
+                                                    const DView* __restrict__ views, DSettings S,
+                                                    const uint32_t* __restrict__ scanned,
+                                                    int64_t rhist_cap, int64_t row_cap,
+                                                    uint2* __restrict__ runs, uint32_t* flag) {
+  __shared__ uint32_t s_rows[4][64], s_first[4][64];
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64], s_lim[4][64];
-  __shared__ int32_t s_x0[4][64], s_x1[4][64], s_y0[4][64], s_w[4][64], s_h[4][64], s_rb[4][64];
+  __shared__ int32_t s_x0[4][64], s_x1[4][64];
   __shared__ uint32_t s_slot[4][64];
+  __shared__ uint64_t s_mask[4][64];
+  __shared__ uint32_t s_place[4][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t n_vis = *n_vis_dev;
-  const int64_t first = ((int64_t)blockIdx.x * 4 + w) * 64;
-  if (first >= n_vis) return;
-  const int64_t r = first + lane;
-  const int64_t last = (n_vis - first < 64 ? n_vis : first + 64) - 1;
-  const uint32_t off0 = roff[first];
-  const uint32_t off_end = (last + 1 < n_vis) ? roff[last + 1] : *n_rows_dev;
-  uint32_t rows = 0;
-  if (r < n_vis) {
-    const uint32_t slot = vval[r];
-    const DView& V = views[(int)(slot / (uint32_t)n_per_view)];
-    const float* p = rec + (size_t)slot * kRec;
-    int x0, x1, y0, y1;
-    if (tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], V, S.tile_shift, x0, x1, y0, y1))
-      rows = (uint32_t)(y1 - y0 + 1);
+  SplatChunk ck;
+  if (!load_splat_chunk<true>(vinfo, cview, n_chunks_dev, vval, rowbox, rec, views, S.tile_shift,
+                              ck))
+    return;
+  const DView& V = views[ck.v];
+  if (ck.valid) {
+    const float* p = rec + (size_t)ck.slot * kRec;
     s_u[w][lane] = p[R_U];
     s_v[w][lane] = p[R_V];
     s_a[w][lane] = p[R_A];
@@ -419,42 +690,58 @@ __global__ __launch_bounds__(kThreads) void k_rowgen(
     s_ex[w][lane] = p[R_EX];
     s_ey[w][lane] = p[R_EY];
     s_lim[w][lane] = coverage_limit(p[R_OPT], S);
-    s_x0[w][lane] = x0;
-    s_x1[w][lane] = x1;
-    s_y0[w][lane] = y0;
-    s_w[w][lane] = V.width;
-    s_h[w][lane] = V.height;
-    s_rb[w][lane] = V.row_base;
-    s_slot[w][lane] = slot;
   }
-  uint32_t n_rows;
-  const uint32_t row0 = wave_excl_scan(rows, n_rows);
-  s_rows[w][lane] = (r < n_vis) ? row0 : n_rows;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // the row offsets were scanned from the same boxes; a disagreement is reported and nothing
-  // is written past this wave's share
-  if (off0 + n_rows != off_end && lane == 0) *flag = 2u;
-  for (uint32_t k0 = 0; k0 < n_rows; k0 += 64) {
-    const uint32_t k = k0 + lane;
-    if (k >= n_rows) continue;
-    int lo = 0, hi = 63;  // the last lane whose rows start at or before k owns row k
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_rows[w][mid] <= k) lo = mid; else hi = mid - 1;
+  s_x0[w][lane] = ck.x0;
+  s_x1[w][lane] = ck.x1;
+  s_slot[w][lane] = ck.slot;
+  const uint32_t nch = ck.b.x, ny = ck.b.y;
+  const uint32_t last = min(ck.ymax, ny - 1u);
+  for (uint32_t t0 = ck.ymin & ~63u; ck.ymin <= last && t0 <= last; t0 += 64) {
+    // masks and places of the window's rows
+    const uint32_t row = t0 + (uint32_t)lane;
+    const int64_t at = (int64_t)ck.a.w + (int64_t)row * nch + ck.c;
+    if (__ballot(row < ny && at >= rhist_cap)) {  // never with a table sized for the views
+      if (lane == 0) *flag = 1u;
+      return;
     }
-    const int ty = s_y0[w][lo] + (int)(k - s_rows[w][lo]);
-    const int span = tile_row_span(s_u[w][lo], s_v[w][lo], s_a[w][lo], s_b[w][lo], s_c[w][lo],
-                                   s_lim[w][lo], s_ex[w][lo], s_ey[w][lo], ty, S.tile_shift,
-                                   s_w[w][lo], s_h[w][lo], s_x0[w][lo], s_x1[w][lo]);
-    const uint32_t pos = off0 + k;
-    if (pos < off_end && (int64_t)pos < row_cap) {
-      rkey[pos] = (K)(s_rb[w][lo] + ty);
-      rval[pos] = make_uint2(s_slot[w][lo], span >= 0 ? (uint32_t)span : ~0u);
-    } else if ((int64_t)pos >= row_cap) {
-      *flag = 1u;
+    s_place[w][lane] = (row < ny) ? scanned[at] : 0u;
+    uint64_t mine = 0ull;
+    const uint32_t j0 = ck.ymin > t0 ? ck.ymin : t0, j1 = min(last + 1u, t0 + 64u);
+    for (uint32_t y = j0; y < j1; ++y) {
+      const uint64_t m = __ballot(y - ck.y0 <= ck.h);
+      if ((uint32_t)lane == y - t0) mine = m;
     }
+    s_mask[w][lane] = mine;
+    // this lane's rows in the window, numbered over the wave
+    const uint32_t lo = max(ck.y0, t0), hi = min(ck.y0 + ck.h, t0 + 63u);
+    const uint32_t cnt = (ck.y0 != ~0u && lo <= hi) ? hi - lo + 1u : 0u;
+    uint32_t total;
+    const uint32_t first = wave_excl_scan(cnt, total);
+    s_rows[w][lane] = first;
+    s_first[w][lane] = lo;
+    wave_lds_sync();
+    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+      const uint32_t k = k0 + (uint32_t)lane;
+      if (k < total) {
+        int a = 0, b = 63;  // the last lane whose runs start at or before k owns run k
+        while (a < b) {
+          const int m = (a + b + 1) >> 1;
+          if (s_rows[w][m] <= k) a = m; else b = m - 1;
+        }
+        const uint32_t y = s_first[w][a] + (k - s_rows[w][a]);
+        const int span = tile_row_span(s_u[w][a], s_v[w][a], s_a[w][a], s_b[w][a], s_c[w][a],
+                                       s_lim[w][a], s_ex[w][a], s_ey[w][a], (int)y, S.tile_shift,
+                                       V.width, V.height, s_x0[w][a], s_x1[w][a]);
+        const uint64_t before = a == 0 ? 0ull : (~0ull >> (64 - a));
+        const uint32_t pos =
+            s_place[w][y - t0] + (uint32_t)__popcll(s_mask[w][y - t0] & before);
+        if ((int64_t)pos < row_cap)
+          runs[pos] = make_uint2(s_slot[w][a], span >= 0 ? (uint32_t)span : ~0u);
+        else
+          *flag = 1u;
+      }
+    }
+    wave_lds_sync();  // the next window rewrites the arrays
   }
 }
 
@@ -535,17 +822,6 @@ __global__ void k_chunk_rows(const uint4* __restrict__ rinfo, int64_t chunk_cap,
   uint32_t* out = crow + (size_t)(r % kXcds) * chunk_cap;
   for (uint32_t k = threadIdx.x; k < nch && (int64_t)(first + k) < chunk_cap; k += blockDim.x)
     out[first + k] = r;
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
 }
 
 // A chunk's runs as column bounds [x0, x1] (x0 > x1: empty), and the wave's column range.
@@ -817,25 +1093,18 @@ void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slot
                n_out, scratch, st);
 }
 
-void pair_total(const uint32_t* tiles, int64_t n, uint32_t* total, void* scratch,
-                hipStream_t st) {
+void bin_totals(const uint32_t* tiles, const uint32_t* nrows, int64_t n, uint32_t* pairs,
+                uint32_t* runs, void* scratch, hipStream_t st) {
   const int64_t blocks = (n + kItems - 1) / kItems;
   if (blocks == 0) {
-    fill_u32(total, 1, 0u, st);
+    fill_u32(pairs, 1, 0u, st);
+    fill_u32(runs, 1, 0u, st);
     return;
   }
-  // block sums, then one block adds them up
-  uint32_t* sums = static_cast<uint32_t*>(scratch);
-  hipLaunchKernelGGL(k_scan_reduce<InPlain>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
-                     InPlain{tiles}, nullptr, n, sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, (int)blocks, total);
-}
-
-void row_offsets(const uint32_t* nrows, const uint32_t* vval, const uint32_t* n_vis,
-                 int64_t n_cap, uint32_t* roff, uint32_t* total, void* scratch, hipStream_t st) {
-  // the reduce pass leaves each entry's row count in `roff`; the apply pass scans it in place
-  scan_generic(InGatherKeep{nrows, vval, roff}, InPlain{roff}, OutStore{roff}, n_vis, n_cap,
-               total, scratch, st);
+  uint2* sums = static_cast<uint2*>(scratch);
+  hipLaunchKernelGGL(k_sum2_blocks, dim3((unsigned)blocks), dim3(kThreads), 0, st, tiles, nrows, n,
+                     sums);
+  hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(1024), 0, st, sums, (int)blocks, pairs, runs);
 }
 
 // The table of the smaller workgroups is the larger one: it serves either.
@@ -897,32 +1166,50 @@ int radix_sort(uint16_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n
   return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, false, scratch, st);
 }
 
-template <typename K>
-void rowgen_t(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
-              int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
-              const DView* views, DSettings S, K* rkey, uint2* rval, uint32_t* flag,
-              hipStream_t st) {
-  const int64_t waves = (n_vis_cap + 63) / 64;
-  const int64_t blocks = (waves + 3) / 4;
-  if (blocks == 0) return;
-  hipLaunchKernelGGL(k_rowgen<K>, dim3((unsigned)blocks), dim3(kThreads), 0, st, rec, vval, roff,
-                     n_vis, n_rows, row_cap, n_slots_per_view, views, S, rkey, rval, flag);
+static int bits_of(int64_t n) {  // bits of keys below n
+  int b = 0;
+  while (b < 32 && ((int64_t)1 << b) < n) ++b;
+  return b;
 }
 
-void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint32_t* rkey, uint2* rval, uint32_t* flag,
-            hipStream_t st) {
-  rowgen_t<uint32_t>(rec, vval, roff, n_vis, n_vis_cap, n_rows, row_cap, n_slots_per_view, views,
-                     S, rkey, rval, flag, st);
+int group_by_view(uint32_t* vkey[2], uint32_t* vval[2], int vb, const uint32_t* n_vis,
+                  int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange, void* scratch,
+                  hipStream_t st) {
+  // keys go to the buffer that held the depth keys; the values start from the depth order
+  uint16_t* key[2] = {reinterpret_cast<uint16_t*>(vkey[vb]), reinterpret_cast<uint16_t*>(vkey[vb ^ 1])};
+  uint32_t* val[2] = {vval[vb], vval[vb ^ 1]};
+  if (n_cap > 0)
+    hipLaunchKernelGGL(k_view_keys, dim3((unsigned)((n_cap + 255) / 256)), dim3(256), 0, st,
+                       vval[vb], n_vis, n_cap, n_per_view, key[0]);
+  const int b = radix_sort(key, val, n_vis, n_cap, bits_of(n_views), false, scratch, st);
+  tile_ranges(key[b], n_vis, n_cap, n_views, vrange, st);
+  return b == 0 ? vb : vb ^ 1;
 }
 
-void rowgen(const float* rec, const uint32_t* vval, const uint32_t* roff, const uint32_t* n_vis,
-            int64_t n_vis_cap, const uint32_t* n_rows, int64_t row_cap, int n_slots_per_view,
-            const DView* views, DSettings S, uint16_t* rkey, uint2* rval, uint32_t* flag,
-            hipStream_t st) {
-  rowgen_t<uint16_t>(rec, vval, roff, n_vis, n_vis_cap, n_rows, row_cap, n_slots_per_view, views,
-                     S, rkey, rval, flag, st);
+void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_t n_rows,
+                    const uint32_t* vval, const uint32_t* rowbox, const float* rec, DSettings S,
+                    int64_t chunk_cap, int64_t rhist_cap, int64_t row_cap, const uint32_t* n_runs,
+                    uint4* vinfo, uint16_t* cview, uint32_t* rhist, uint32_t* counts, uint2* runs,
+                    uint2* rrange, uint32_t* flag, void* scratch, hipStream_t st) {
+  // counts: [0] chunks, [1] table entries, [2] runs laid down
+  hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, st, vrange, n_views, views, vinfo,
+                     (uint32_t)std::min<int64_t>(rhist_cap, UINT32_MAX), counts);
+  hipLaunchKernelGGL(k_chunk_views, dim3((unsigned)n_views), dim3(256), 0, st, vinfo, chunk_cap,
+                     cview);
+  const int64_t blocks = (chunk_cap + 3) / 4;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_rows_count, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
+                       counts + 0, vval, rowbox, rhist, rhist_cap);
+  scan_generic(InPlain{rhist}, InPlain{rhist}, OutStore{rhist}, counts + 1, rhist_cap, counts + 2,
+               scratch, st);
+  if (n_rows > 0)
+    hipLaunchKernelGGL(k_row_ranges, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st,
+                       vinfo, views, n_views, rhist, counts + 1, counts + 2, n_runs, n_rows,
+                       (uint32_t)std::min<int64_t>(row_cap, UINT32_MAX), rrange, flag);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_rows_write, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
+                       counts + 0, vval, rowbox, rec, views, S, rhist, rhist_cap, row_cap, runs,
+                       flag);
 }
 
 void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,

@@ -85,6 +85,22 @@ def test_masked_render_and_gradients(renderer, wl):
     assert np.array_equal(g["densify"][:, 2], run.listed_views().astype(np.float32))
 
 
+def test_mask_after_unmasked_render(renderer):
+    """A masked forward right after an unmasked one of the same scene (the same buffers): the
+    removed Gaussians leave no count of the unmasked call behind (the binning's pair and run
+    totals agree, so sync() reports nothing) and the image matches the masked oracle."""
+    sc = scenes.make_workload(0)
+    mask = scenes.make_mask(sc)
+    GpuRun(renderer, sc).forward()
+    renderer.sync()
+    run = MaskedRun(renderer, sc, mask).forward()
+    renderer.sync()
+    with masked_oracle(sc, sc.views[0], mask) as fr:
+        rep = parity.check_image(run.images()[0], fr, 1e-4)
+    log(f"w0 masked after unmasked: max_err={rep['max_err']:.2e} failures={rep['n_failures']}")
+    assert rep["n_failures"] == 0 and rep["n_unverified"] <= 0.002 * rep["n"]
+
+
 def test_densify_sums_over_batched_views(renderer):
     sc = scenes.make_workload(2)
     views = [sc.views[0], sc.views[1]]
