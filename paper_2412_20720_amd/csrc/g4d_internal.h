@@ -30,20 +30,13 @@ void bin_totals(const uint32_t* tiles, const uint32_t* rowbox, int64_t n, uint32
                 uint32_t* runs, void* scratch, hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
-// n_cap).  Ping-pongs between buffers 0 and 1; returns the index holding the result.  Keys of
-// 32 or 16 bits (the tile ids of a batch with fewer than 2^16 tiles move as 16-bit keys).
-// `wide` takes workgroups of 8,192 items instead of 4,096 (long sorts: longer digit runs in
-// the scatter; short ones keep more workgroups).  The scratch size serves either.
+// n_cap), 8 bits per pass in workgroups of 4,096 items.  Ping-pongs between buffers 0 and 1;
+// returns the index holding the result.
 size_t radix_scratch_bytes(int64_t n_cap);
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, bool wide, void* scratch, hipStream_t st);
+               int bits, void* scratch, hipStream_t st);
 int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, bool wide, void* scratch, hipStream_t st);
-// The same with 8-byte values (workgroups of 4,096 items).
-int radix_sort(uint32_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st);
-int radix_sort(uint16_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st);
+               int bits, void* scratch, hipStream_t st);
 
 // Regroups the depth-sorted visible slots (vkey / vval buffer vb) by view with one stable pass
 // on the view index; returns the buffer that holds them and writes vrange[v] = [first, end) of
@@ -74,8 +67,8 @@ void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_
 // words) receive the chunks of each XCD, the table entries and the pairs written.  A pair count
 // other than *n_pairs sets *flag = 2 (unless set).
 void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,
-            const uint2* runs, int64_t chunk_cap,
-            int64_t hist_cap, int64_t pair_cap, const uint32_t* n_pairs, uint4* rinfo,
+            const uint2* runs, int64_t chunk_cap, int64_t hist_cap, int64_t pair_cap,
+            const uint32_t* n_pairs, uint4* rinfo,
             uint32_t* crow, uint32_t* hist, uint32_t* counts, uint32_t* pval, uint2* ranges,
             uint32_t* flag, void* scratch, hipStream_t st);
 
@@ -88,9 +81,6 @@ void tile_ranges(const uint32_t* key, const uint32_t* n_dev, int64_t cap, int64_
                  uint2* ranges, hipStream_t st);
 void tile_ranges(const uint16_t* key, const uint32_t* n_dev, int64_t cap, int64_t n_keys,
                  uint2* ranges, hipStream_t st);
-
-// *out = min(*n, cap) on the device.
-void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st);
 
 // Derive camera centres and Jacobian clamps of the views on the device.
 void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st);

@@ -643,7 +643,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     int vb;
     {
       Stage t(ctx, 2, st);
-      vb = radix_sort(vk, vv, cnt + 0, slots, 32, false, ctx->sort_tmp.p, st);
+      vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
     }
     ctx->vis_buf = vb;
     {

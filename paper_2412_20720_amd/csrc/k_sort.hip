@@ -21,12 +21,9 @@ constexpr int kItems = kScanItems;              // 16 items per thread
 constexpr int kPerThread = kItems / kThreads;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-// Items per workgroup of a radix pass (a multiple of 4 x 64).  Measured on the 300k/16-view
-// workload with 32-bit tile keys (35.7M pairs, 14-bit tile ids): 4096 sorts the tiles in
-// 0.632 ms, 2048 in 0.649, 8192 in 0.797 (two workgroups per CU for its 70 KB of LDS);
-// splitting the 14 bits evenly (7 + 7) instead of 8 + 6 gains nothing (0.636).  With 16-bit
-// keys (26.1M pairs, 15-bit ids): 4096 in 0.398 ms, 2048 in 0.422, 8192 in 0.513; the depth
-// sort (1.8M slots, 32-bit keys) takes 0.149, 0.143 and 0.201 ms.
+// Items per workgroup of a radix pass (a multiple of 4 x 64).  The depth sort of the
+// 300k-Gaussian, 16-view workload (1.8M slots, 32-bit keys) takes 0.149 ms at 4096,
+// 0.143 at 2048 and 0.201 at 8192.
 #ifndef G4D_RADIX_ITEMS
 #define G4D_RADIX_ITEMS 4096
 #endif
@@ -227,17 +224,6 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 // stable scatter.  Each wave owns a contiguous 1024-item run of its block; ranks inside a
 // wave come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
-// NT threads per workgroup, 16 items per thread: 256 (4096 items), or 512 for long sorts, whose
-// scatter then writes runs of one digit about twice as long (8192 items over 256 digits) with
-// two workgroups still resident per CU.  Tile sort of the 300k-Gaussian, 16-view workload
-// (26.1M pairs, 16-bit keys): 0.399 ms at 256 threads, 0.368-0.375 at 512, 0.477 at 384
-// (three workgroups per CU, shorter runs), 0.442 at 768 and 0.399 at 1024 (one workgroup per
-// CU, which serializes its load, rank and write phases).
-#ifndef G4D_WIDE_THREADS
-#define G4D_WIDE_THREADS 512
-#endif
-constexpr int kWideThreads = G4D_WIDE_THREADS;
-
 template <typename K, int NT>
 __global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ key,
                                                    const uint32_t* n_dev, int shift,
@@ -1058,9 +1044,6 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out) {
-  if (threadIdx.x == 0) *out = min(*n, cap);
-}
 
 __global__ void k_view_setup(DView* views, int n_views, float m) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1107,7 +1090,6 @@ void bin_totals(const uint32_t* tiles, const uint32_t* nrows, int64_t n, uint32_
   hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(1024), 0, st, sums, (int)blocks, pairs, runs);
 }
 
-// The table of the smaller workgroups is the larger one: it serves either.
 size_t radix_scratch_bytes(int64_t n_cap) {
   const int64_t blocks = (n_cap + kRadixItems - 1) / kRadixItems;
   const int64_t table = blocks * kRadix;
@@ -1138,32 +1120,14 @@ int radix_sort_nt(K* key[2], V* val[2], const uint32_t* n_dev, int64_t n_cap, in
   return cur;
 }
 
-template <typename K, typename V>
-int radix_sort_t(K* key[2], V* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-                 bool wide, void* scratch, hipStream_t st) {
-  if (wide) return radix_sort_nt<K, kWideThreads, V>(key, val, n_dev, n_cap, bits, scratch, st);
-  return radix_sort_nt<K, kThreads, V>(key, val, n_dev, n_cap, bits, scratch, st);
-}
-
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               bool wide, void* scratch, hipStream_t st) {
-  return radix_sort_t<uint32_t>(key, val, n_dev, n_cap, bits, wide, scratch, st);
+               void* scratch, hipStream_t st) {
+  return radix_sort_nt<uint32_t, kThreads, uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
 }
 
 int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               bool wide, void* scratch, hipStream_t st) {
-  return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, wide, scratch, st);
-}
-
-// 8-byte values move through the 256-thread workgroups (their LDS staging doubles).
-int radix_sort(uint32_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
                void* scratch, hipStream_t st) {
-  return radix_sort_t<uint32_t>(key, val, n_dev, n_cap, bits, false, scratch, st);
-}
-
-int radix_sort(uint16_t* key[2], uint2* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  return radix_sort_t<uint16_t>(key, val, n_dev, n_cap, bits, false, scratch, st);
+  return radix_sort_nt<uint16_t, kThreads, uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
 }
 
 static int bits_of(int64_t n) {  // bits of keys below n
@@ -1181,7 +1145,7 @@ int group_by_view(uint32_t* vkey[2], uint32_t* vval[2], int vb, const uint32_t* 
   if (n_cap > 0)
     hipLaunchKernelGGL(k_view_keys, dim3((unsigned)((n_cap + 255) / 256)), dim3(256), 0, st,
                        vval[vb], n_vis, n_cap, n_per_view, key[0]);
-  const int b = radix_sort(key, val, n_vis, n_cap, bits_of(n_views), false, scratch, st);
+  const int b = radix_sort(key, val, n_vis, n_cap, bits_of(n_views), scratch, st);
   tile_ranges(key[b], n_vis, n_cap, n_views, vrange, st);
   return b == 0 ? vb : vb ^ 1;
 }
@@ -1271,9 +1235,6 @@ void tile_ids_of(const uint2* ranges, int64_t n_tiles, int64_t n, uint32_t* ids,
                      ids);
 }
 
-void clamp_count(const uint32_t* n, uint32_t cap, uint32_t* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_clamp_count, dim3(1), dim3(64), 0, st, n, cap, out);
-}
 
 void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st) {
   hipLaunchKernelGGL(k_view_setup, dim3((n_views + 63) / 64), dim3(64), 0, st, views, n_views,
