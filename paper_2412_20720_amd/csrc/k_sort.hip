@@ -508,55 +508,33 @@ __global__ void k_chunk_views(const uint4* __restrict__ vinfo, int64_t chunk_cap
 // lane its splat's box rows [y0, y0 + h] (an empty lane: y0 = ~0u, h = 0).
 struct SplatChunk {
   uint4 a, b;  // vinfo of the view
-  uint32_t v, c, slot, y0, h, ymin, ymax;
-  bool valid;
-  int x0, x1;
+  uint32_t c, y0, h;
 };
 
-// Chunk g: its view (scalar), its splats and their box rows; with the records also the box
-// columns (tile_rect on the record, as the preprocess listed them).
-template <bool REC>
+// Chunk g: its view (scalar) and its splats' box rows.
 __device__ __forceinline__ bool load_splat_chunk(const uint4* __restrict__ vinfo,
                                                  const uint16_t* __restrict__ cview,
                                                  const uint32_t* n_chunks_dev,
                                                  const uint32_t* __restrict__ vval,
                                                  const uint32_t* __restrict__ rowbox,
-                                                 const float* __restrict__ rec,
-                                                 const DView* __restrict__ views, int shift,
                                                  SplatChunk& ck) {
   const int lane = threadIdx.x & 63;
   const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
   if (g >= *n_chunks_dev) return false;
-  ck.v = __builtin_amdgcn_readfirstlane((uint32_t)cview[g]);
-  ck.a = vinfo[2 * ck.v];
-  ck.b = vinfo[2 * ck.v + 1];
+  const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)cview[g]);
+  ck.a = vinfo[2 * v];
+  ck.b = vinfo[2 * v + 1];
   ck.c = g - ck.a.z;
   const uint32_t e = ck.c * 64u + (uint32_t)lane;
-  ck.valid = e < ck.a.y;
-  ck.slot = ck.valid ? vval[ck.a.x + e] : 0u;
   ck.y0 = ~0u;
   ck.h = 0u;
-  ck.x0 = 0;
-  ck.x1 = -1;
-  uint32_t y1 = 0u;
-  if (ck.valid) {
-    const uint32_t rb = rowbox[ck.slot];
+  if (e < ck.a.y) {
+    const uint32_t rb = rowbox[vval[ck.a.x + e]];
     if (rb != ~0u) {
       ck.y0 = rb >> 16;
-      y1 = rb & 0xFFFFu;
-      ck.h = y1 - ck.y0;
-    }
-    if (REC) {
-      const float* p = rec + (size_t)ck.slot * kRec;
-      int x0, x1, y0, yy1;
-      if (tile_rect(p[R_U], p[R_V], p[R_EX], p[R_EY], views[ck.v], shift, x0, x1, y0, yy1)) {
-        ck.x0 = x0;
-        ck.x1 = x1;
-      }
+      ck.h = (rb & 0xFFFFu) - ck.y0;
     }
   }
-  ck.ymin = __builtin_amdgcn_readfirstlane(wave_min_u32(ck.y0));
-  ck.ymax = __builtin_amdgcn_readfirstlane(wave_max_u32(y1));
   return true;
 }
 
@@ -575,8 +553,7 @@ __global__ __launch_bounds__(256) void k_rows_count(const uint4* __restrict__ vi
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int* diff = reinterpret_cast<int*>(&s_diff[w][0]);
   SplatChunk ck;
-  if (!load_splat_chunk<false>(vinfo, cview, n_chunks_dev, vval, rowbox, nullptr, nullptr, 0, ck))
-    return;
+  if (!load_splat_chunk(vinfo, cview, n_chunks_dev, vval, rowbox, ck)) return;
   const uint32_t nch = ck.b.x, ny = ck.b.y;
   for (uint32_t r0 = 0; r0 < ny; r0 += kCountRows) {
     s_diff[w][lane] = make_int4(0, 0, 0, 0);
@@ -639,90 +616,123 @@ __global__ void k_row_ranges(const uint4* __restrict__ vinfo, const DView* __res
   rrange[r] = hi > lo ? make_uint2(lo, hi) : make_uint2(0u, 0u);
 }
 
+// Position of the r-th set bit of m (r < popcount(m)).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t r) {
+  uint32_t x = (uint32_t)m;
+  int base = 0;
+  uint32_t c = (uint32_t)__popc(x);
+  if (r >= c) {
+    r -= c;
+    x = (uint32_t)(m >> 32);
+    base = 32;
+  }
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) {
+    c = (uint32_t)__popc(x & ((1u << w) - 1u));
+    if (r >= c) {
+      r -= c;
+      x >>= w;
+      base += w;
+    }
+  }
+  return base;
+}
+
 // Write pass.  Per window of 64 rows, lane t holds the mask of the chunk's splats whose box
-// holds row t0 + t and that row's scanned place; the chunk's runs in the window are numbered
-// with a wave scan and dealt out 64 per round, each lane computing its run's columns, and
-// laid down at the place of its row plus the number of the chunk's earlier splats in the row.
+// holds row t0 + t and that row's scanned place.  The chunk's runs in the window are numbered
+// row by row (a wave scan of the rows' counts) and dealt out 64 per round: the lane with run k
+// finds its row and its rank r in the row, the splat as the r-th set bit of the row's mask,
+// computes the run's columns and stores it at the row's place + r, so that consecutive lanes
+// mostly fill consecutive entries of one row's list.
 __global__ __launch_bounds__(256) void k_rows_write(const uint4* __restrict__ vinfo,
                                                     const uint16_t* __restrict__ cview,
                                                     const uint32_t* n_chunks_dev,
                                                     const uint32_t* __restrict__ vval,
-                                                    const uint32_t* __restrict__ rowbox,
                                                     const float* __restrict__ rec,
                                                     const DView* __restrict__ views, DSettings S,
                                                     const uint32_t* __restrict__ scanned,
                                                     int64_t rhist_cap, int64_t row_cap,
                                                     uint2* __restrict__ runs, uint32_t* flag) {
-  __shared__ uint32_t s_rows[4][64], s_first[4][64];
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64], s_lim[4][64];
   __shared__ int32_t s_x0[4][64], s_x1[4][64];
   __shared__ uint32_t s_slot[4][64];
   __shared__ uint64_t s_mask[4][64];
-  __shared__ uint32_t s_place[4][64];
+  __shared__ uint32_t s_place[4][64], s_rfirst[4][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  SplatChunk ck;
-  if (!load_splat_chunk<true>(vinfo, cview, n_chunks_dev, vval, rowbox, rec, views, S.tile_shift,
-                              ck))
-    return;
-  const DView& V = views[ck.v];
-  if (ck.valid) {
-    const float* p = rec + (size_t)ck.slot * kRec;
-    s_u[w][lane] = p[R_U];
-    s_v[w][lane] = p[R_V];
+  const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+  if (g >= *n_chunks_dev) return;
+  const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)cview[g]);
+  const uint4 va = vinfo[2 * v], vb = vinfo[2 * v + 1];
+  const uint32_t c = g - va.z, nch = vb.x, ny = vb.y;
+  const DView& V = views[v];
+  const uint32_t e = c * 64u + (uint32_t)lane;
+  uint32_t y0 = ~0u, h = 0u, y1 = 0u, slot = 0u;
+  int x0 = 0, x1 = -1;
+  if (e < va.y) {
+    slot = vval[va.x + e];
+    const float* p = rec + (size_t)slot * kRec;
+    const float u = p[R_U], pv = p[R_V], ex = p[R_EX], ey = p[R_EY];
+    int ty0, ty1;
+    // the box the preprocess listed the splat with (the same function on the same values)
+    if (tile_rect(u, pv, ex, ey, V, S.tile_shift, x0, x1, ty0, ty1)) {
+      y0 = (uint32_t)ty0;
+      y1 = (uint32_t)ty1;
+      h = y1 - y0;
+    }
+    s_u[w][lane] = u;
+    s_v[w][lane] = pv;
     s_a[w][lane] = p[R_A];
     s_b[w][lane] = p[R_B];
     s_c[w][lane] = p[R_C];
-    s_ex[w][lane] = p[R_EX];
-    s_ey[w][lane] = p[R_EY];
+    s_ex[w][lane] = ex;
+    s_ey[w][lane] = ey;
     s_lim[w][lane] = coverage_limit(p[R_OPT], S);
   }
-  s_x0[w][lane] = ck.x0;
-  s_x1[w][lane] = ck.x1;
-  s_slot[w][lane] = ck.slot;
-  const uint32_t nch = ck.b.x, ny = ck.b.y;
-  const uint32_t last = min(ck.ymax, ny - 1u);
-  for (uint32_t t0 = ck.ymin & ~63u; ck.ymin <= last && t0 <= last; t0 += 64) {
-    // masks and places of the window's rows
+  s_x0[w][lane] = x0;
+  s_x1[w][lane] = x1;
+  s_slot[w][lane] = slot;
+  const uint32_t ymin = __builtin_amdgcn_readfirstlane(wave_min_u32(y0));
+  const uint32_t ymax = __builtin_amdgcn_readfirstlane(wave_max_u32(y1));
+  const uint32_t last = min(ymax, ny - 1u);
+  for (uint32_t t0 = ymin & ~63u; ymin <= last && t0 <= last; t0 += 64) {
+    // masks, counts and places of the window's rows (lane t: row t0 + t)
     const uint32_t row = t0 + (uint32_t)lane;
-    const int64_t at = (int64_t)ck.a.w + (int64_t)row * nch + ck.c;
+    const int64_t at = (int64_t)va.w + (int64_t)row * nch + c;
     if (__ballot(row < ny && at >= rhist_cap)) {  // never with a table sized for the views
       if (lane == 0) *flag = 1u;
       return;
     }
-    s_place[w][lane] = (row < ny) ? scanned[at] : 0u;
+    const uint32_t place = (row < ny) ? scanned[at] : 0u;
     uint64_t mine = 0ull;
-    const uint32_t j0 = ck.ymin > t0 ? ck.ymin : t0, j1 = min(last + 1u, t0 + 64u);
+    const uint32_t j0 = ymin > t0 ? ymin : t0, j1 = min(last + 1u, t0 + 64u);
     for (uint32_t y = j0; y < j1; ++y) {
-      const uint64_t m = __ballot(y - ck.y0 <= ck.h);
+      const uint64_t m = __ballot(y - y0 <= h);
       if ((uint32_t)lane == y - t0) mine = m;
     }
-    s_mask[w][lane] = mine;
-    // this lane's rows in the window, numbered over the wave
-    const uint32_t lo = max(ck.y0, t0), hi = min(ck.y0 + ck.h, t0 + 63u);
-    const uint32_t cnt = (ck.y0 != ~0u && lo <= hi) ? hi - lo + 1u : 0u;
     uint32_t total;
-    const uint32_t first = wave_excl_scan(cnt, total);
-    s_rows[w][lane] = first;
-    s_first[w][lane] = lo;
+    const uint32_t rfirst = wave_excl_scan((uint32_t)__popcll(mine), total);
+    s_mask[w][lane] = mine;
+    s_rfirst[w][lane] = rfirst;
+    s_place[w][lane] = place;
     wave_lds_sync();
     for (uint32_t k0 = 0; k0 < total; k0 += 64) {
       const uint32_t k = k0 + (uint32_t)lane;
       if (k < total) {
-        int a = 0, b = 63;  // the last lane whose runs start at or before k owns run k
+        int a = 0, b = 63;  // the last row whose runs start at or before k holds run k
         while (a < b) {
           const int m = (a + b + 1) >> 1;
-          if (s_rows[w][m] <= k) a = m; else b = m - 1;
+          if (s_rfirst[w][m] <= k) a = m; else b = m - 1;
         }
-        const uint32_t y = s_first[w][a] + (k - s_rows[w][a]);
-        const int span = tile_row_span(s_u[w][a], s_v[w][a], s_a[w][a], s_b[w][a], s_c[w][a],
-                                       s_lim[w][a], s_ex[w][a], s_ey[w][a], (int)y, S.tile_shift,
-                                       V.width, V.height, s_x0[w][a], s_x1[w][a]);
-        const uint64_t before = a == 0 ? 0ull : (~0ull >> (64 - a));
-        const uint32_t pos =
-            s_place[w][y - t0] + (uint32_t)__popcll(s_mask[w][y - t0] & before);
+        const uint32_t r = k - s_rfirst[w][a];
+        const int j = nth_set_bit(s_mask[w][a], r);
+        const int y = (int)t0 + a;
+        const int span = tile_row_span(s_u[w][j], s_v[w][j], s_a[w][j], s_b[w][j], s_c[w][j],
+                                       s_lim[w][j], s_ex[w][j], s_ey[w][j], y, S.tile_shift,
+                                       V.width, V.height, s_x0[w][j], s_x1[w][j]);
+        const uint32_t pos = s_place[w][a] + r;
         if ((int64_t)pos < row_cap)
-          runs[pos] = make_uint2(s_slot[w][a], span >= 0 ? (uint32_t)span : ~0u);
+          runs[pos] = make_uint2(s_slot[w][j], span >= 0 ? (uint32_t)span : ~0u);
         else
           *flag = 1u;
       }
@@ -1172,8 +1182,7 @@ void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_
                        (uint32_t)std::min<int64_t>(row_cap, UINT32_MAX), rrange, flag);
   if (blocks > 0)
     hipLaunchKernelGGL(k_rows_write, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
-                       counts + 0, vval, rowbox, rec, views, S, rhist, rhist_cap, row_cap, runs,
-                       flag);
+                       counts + 0, vval, rec, views, S, rhist, rhist_cap, row_cap, runs, flag);
 }
 
 void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,
