@@ -14,7 +14,7 @@ constexpr int kSortThreads = 256;
 // p[0..n) = v (a kernel, not a memset node, so that captured graphs replay it correctly).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
-// Scratch needed by scan_* for up to `n` items (bytes).
+// Scratch needed by scan_* and bin_totals for up to `n` items (bytes).
 size_t scan_scratch_bytes(int64_t n);
 
 // Stream compaction of visible slots: for every slot with tiles[slot] > 0, in slot order,
@@ -25,7 +25,7 @@ void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slot
 
 // *pairs = sum of tiles[0, n) and *runs = the rows of the boxes rowbox[0, n) (first << 16 |
 // last, ~0u: none): the (Gaussian, tile) pairs and (Gaussian, tile row) runs the preprocess
-// listed.
+// listed.  scratch: at least scan_scratch_bytes(n) bytes.
 void bin_totals(const uint32_t* tiles, const uint32_t* rowbox, int64_t n, uint32_t* pairs,
                 uint32_t* runs, void* scratch, hipStream_t st);
 

@@ -648,6 +648,9 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     ctx->vis_buf = vb;
     {
       Stage t(ctx, 3, st);
+      if (ctx->scan_tmp.cap < scan_scratch_bytes(slots))
+        return fail(ctx, G4D_EHIP, "scan scratch of %zu bytes below the %zu the totals need",
+                    ctx->scan_tmp.cap, scan_scratch_bytes(slots));
       bin_totals(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->rowbox), slots, cnt + 1, cnt + 3,
                  ctx->scan_tmp.p, st);
     }

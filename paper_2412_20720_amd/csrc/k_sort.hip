@@ -1075,8 +1075,9 @@ void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
 }
 
+// One uint2 per block of kItems items: the scans use its first word, bin_totals both.
 size_t scan_scratch_bytes(int64_t n) {
-  return sizeof(uint32_t) * (size_t)((n + kItems - 1) / kItems + 1);
+  return sizeof(uint2) * (size_t)((n + kItems - 1) / kItems + 1);
 }
 
 void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
