@@ -380,10 +380,11 @@ g4d_status g4d_autotune(g4d_ctx *ctx, const g4d_gaussians *g, const g4d_view *vi
                         void *stream);
 
 /* Pipeline stages timed by g4d_profile (index: name). */
-#define G4D_NUM_STAGES 11
+#define G4D_NUM_STAGES 8
 /* Stage timing with HIP events recorded on the call's stream around each kernel group:
- *   0 preprocess, 1 compact, 2 depth_sort, 3 row_offsets, 4 row_gen, 5 row_sort,
- *   6 expand, 7 raster_fwd, 8 clear_grad, 9 raster_bwd, 10 preprocess_bwd.
+ *   0 preprocess, 1 depth_sort (each view's listed slots), 2 splat_rows (splats to
+ *   per-tile-row runs), 3 row_tiles (runs to the tile lists), 4 raster_fwd, 5 clear_grad,
+ *   6 raster_bwd, 7 preprocess_bwd.
  * enable = 1 starts recording for later calls, 0 stops.  If ms / launches are not NULL
  * (host arrays of G4D_NUM_STAGES), the context's device is synchronized, every recorded
  * interval is added in and the totals since the last reset are returned; reset = 1 then

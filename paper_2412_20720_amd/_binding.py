@@ -25,7 +25,7 @@ EXPORTED = ["g4d_default_settings", "g4d_create", "g4d_destroy", "g4d_last_error
             "g4d_get_pairs", "g4d_render_step_noalloc"]
 G4D_STEP_GRAPH = 1
 G4D_NOALLOC_SCRATCH_BYTES = 64 << 20
-G4D_NUM_STAGES = 11
+G4D_NUM_STAGES = 8
 G4D_MAX_CHANNELS = 36
 
 

@@ -14,36 +14,27 @@ constexpr int kSortThreads = 256;
 // p[0..n) = v (a kernel, not a memset node, so that captured graphs replay it correctly).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
-// Scratch needed by scan_* and bin_totals for up to `n` items (bytes).
+// Scratch needed by scan_* for up to `n` items (bytes).
 size_t scan_scratch_bytes(int64_t n);
 
-// Stream compaction of visible slots: for every slot with tiles[slot] > 0, in slot order,
-// writes (depth key, slot) to (out_key, out_val); the count goes to *n_out (device).
-void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
-                     uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
-                     hipStream_t st);
-
-// *pairs = sum of tiles[0, n) and *runs = the rows of the boxes rowbox[0, n) (first << 16 |
-// last, ~0u: none): the (Gaussian, tile) pairs and (Gaussian, tile row) runs the preprocess
-// listed.  scratch: at least scan_scratch_bytes(n) bytes.
-void bin_totals(const uint32_t* tiles, const uint32_t* rowbox, int64_t n, uint32_t* pairs,
-                uint32_t* runs, void* scratch, hipStream_t st);
-
-// Stable LSD radix sort of (key, val) pairs on key bits [0, bits), *n_dev items (capacity
-// n_cap), 8 bits per pass in workgroups of 4,096 items.  Ping-pongs between buffers 0 and 1;
-// returns the index holding the result.
-size_t radix_scratch_bytes(int64_t n_cap);
-int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, void* scratch, hipStream_t st);
-int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap,
-               int bits, void* scratch, hipStream_t st);
-
-// Regroups the depth-sorted visible slots (vkey / vval buffer vb) by view with one stable pass
-// on the view index; returns the buffer that holds them and writes vrange[v] = [first, end) of
-// view v's slots.
-int group_by_view(uint32_t* vkey[2], uint32_t* vval[2], int vb, const uint32_t* n_vis,
-                  int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange, void* scratch,
-                  hipStream_t st);
+// Sorts each view's listed slots by depth into (key, val) buffer 0 (the result's index,
+// returned): (depth key, slot) grouped by view (slot / n_per_view, n_cap slots
+// in all), each view's slots in ascending key order and slot order among equal keys, its range
+// in vrange[v] = [first, end) and the count of all of them in *n_vis.  A stable LSD radix
+// sort inside each view's segment, 8 bits per pass, four passes in workgroups of up to 4,096
+// items of one view; each pass counts digits, scans each view's counts (a workgroup per view)
+// and scatters.  The first pass reads dkey directly (workgroups of 4,096 slots of one view),
+// taking the listed slots from the preprocess's masks per view and wave of 64 Gaussians
+// (vmask[v * n_wc + wave] bit l: slot v * n_per_view + 64 wave + l is listed), so no
+// compaction precedes it; the views' places come from the masks' counts.  Its first kernel (one workgroup)
+// also adds up the preprocess's n_wsum per-wave pair and run counts wsum into totals[0]
+// (pairs) and totals[2] (runs), each held at 2^32 - 1, and sets totals[4] = 1 if either
+// reaches 2^31 (0 otherwise).  scratch: depth_sort_scratch_bytes(n_cap, n_views) bytes.
+size_t depth_sort_scratch_bytes(int64_t n_cap, int n_views);
+int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc, uint32_t* key[2], uint32_t* val[2], uint32_t* n_vis,
+                       int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange,
+                       const uint2* wsum, int64_t n_wsum, uint32_t* totals, void* scratch,
+                       hipStream_t st);
 
 // The runs of every view's splats (vval grouped by view, depth order within a view), grouped
 // by global tile row with each row's runs in depth order: runs = (slot, span) with span =
@@ -75,13 +66,6 @@ void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, in
 // ids[i] = the tile whose range holds pair i, for i < n.
 void tile_ids_of(const uint2* ranges, int64_t n_tiles, int64_t n, uint32_t* ids, hipStream_t st);
 
-// ranges[k] = [first, last+1) of key k's items in a sorted key array (keys >= n_keys are
-// skipped; absent keys get (0, 0)).
-void tile_ranges(const uint32_t* key, const uint32_t* n_dev, int64_t cap, int64_t n_keys,
-                 uint2* ranges, hipStream_t st);
-void tile_ranges(const uint16_t* key, const uint32_t* n_dev, int64_t cap, int64_t n_keys,
-                 uint2* ranges, hipStream_t st);
-
 // Derive camera centres and Jacobian clamps of the views on the device.
 void view_setup(DView* views, int n_views, float jac_margin, hipStream_t st);
 
@@ -97,9 +81,12 @@ struct GradPtrs {
   float *mask, *densify;  // optional: straight-through dL/dM; [N][3] densification statistics
 };
 
+// Per wave of 64 Gaussians (n_wc = ceil(n / 256) * 4 of them), optional: wsum[wave] = the
+// (Gaussian, tile) pairs and (Gaussian, tile row) runs it listed, each held at 2^31, and
+// vmask[v * n_wc + wave] = the mask of its lanes whose Gaussian is listed in view v.
 void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
                         float* rec, uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey,
-                        hipStream_t st);
+                        uint2* wsum, uint64_t* vmask, hipStream_t st);
 void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
                            float* mean4, float* scale4, float* rot_l, float* rot_r,
                            float* opacity, float* sh, hipStream_t st);

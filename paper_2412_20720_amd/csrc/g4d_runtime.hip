@@ -73,12 +73,12 @@ struct SavedKey {
 struct g4d_ctx {
   int device = 0;
   std::string err;
-  DevBuf views, tile_base, rec, tiles, rowbox, dkey, vk[2], vv[2], vrange, vinfo, cview, rhist, runs,
-      rrange, rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last, px_evals,
-      grad2d, counters;
+  DevBuf views, tile_base, rec, tiles, rowbox, dkey, wsum, vmask, vk[2], vv[2], vrange, vinfo, cview,
+      rhist, runs, rrange, rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last,
+      px_evals, grad2d, counters;
   DevBuf fn, fnorm, flow, dfn;     // extra channels
   DevBuf skybg;                    // per-pixel sky background
-  uint32_t* h_counters = nullptr;  // pinned: visible, pairs, flag, runs
+  uint32_t* h_counters = nullptr;  // pinned: visible, pairs, flag, runs, -, 2^31 reached
   DView* h_views = nullptr;        // pinned staging
   int32_t* h_tile_base = nullptr;  // pinned staging
   hipEvent_t staging_done = nullptr;
@@ -173,8 +173,8 @@ g4d_status ensure(g4d_ctx* ctx, DevBuf& b, size_t bytes, double grow = 1.0) {
 }
 
 const char* const kStageNames[G4D_NUM_STAGES] = {
-    "preprocess", "compact", "depth_sort", "bin_totals", "group_views", "splat_rows",
-    "row_tiles", "raster_fwd", "clear_grad", "raster_bwd", "preprocess_bwd"};
+    "preprocess", "depth_sort", "splat_rows", "row_tiles", "raster_fwd", "clear_grad",
+    "raster_bwd", "preprocess_bwd"};
 
 hipEvent_t take_event(g4d_ctx* c) {
   if (!c->ev_free.empty()) {
@@ -388,7 +388,8 @@ g4d_status upload_views(g4d_ctx* ctx, const g4d_view* views, int n_views, const 
 
 g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
                           const g4d_settings* s, hipStream_t st, bool zero_records = false,
-                          const CompactPtrs* cp = nullptr) {
+                          const CompactPtrs* cp = nullptr, uint2* wsum = nullptr,
+                          uint64_t* vmask = nullptr) {
   const int64_t slots = (int64_t)g->n * n_views;
   g4d_status r;
   if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
@@ -403,7 +404,7 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
     preprocess_forward(gp, P<DView>(ctx->views), n_views,
                        device_settings(s, ctx->count_evals && ctx->count_cutoff),
                        P<float>(ctx->rec), P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->rowbox),
-                       P<uint32_t>(ctx->dkey), st);
+                       P<uint32_t>(ctx->dkey), wsum, vmask, st);
   }
   G4D_HIP(hipGetLastError());
   return G4D_OK;
@@ -465,7 +466,7 @@ static g4d_status new_context(g4d_ctx** out, int device) {
   g4d_ctx* ctx = new g4d_ctx;
   ctx->device = device;
   if (hipSetDevice(device) != hipSuccess ||
-      hipHostMalloc((void**)&ctx->h_counters, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_counters, 8 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_views, sizeof(DView) * G4D_MAX_VIEWS, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_tile_base, sizeof(int32_t) * (G4D_MAX_VIEWS + 1), hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming) != hipSuccess ||
@@ -513,6 +514,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   if (ctx->graph_ctx) g4d_destroy(ctx->graph_ctx);
   if (ctx->na) g4d_destroy(ctx->na);
   DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->rowbox, &ctx->dkey,
+                    &ctx->wsum, &ctx->vmask,
                     &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->vrange,
                     &ctx->vinfo, &ctx->cview, &ctx->rhist, &ctx->runs, &ctx->rrange,
                     &ctx->rinfo, &ctx->crow, &ctx->hist, &ctx->pval,
@@ -586,12 +588,13 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   const int n_ext = n_ext_of(ch);
   if ((r = ensure(ctx, ctx->counters, 32 * sizeof(uint32_t))) != G4D_OK) return r;
   // [0] visible, [1] pairs the preprocess counted, [2] overflow / mismatch flag, [3] runs the
-  // preprocess counted, [4] clamped batches of the last counted backward, [6..15] the tile
+  // preprocess counted, [4] clamped batches of the last counted backward, [5] pairs or runs
+  // reached 2^31, [6..15] the tile
   // expansion's chunks per XCD, table entries and pairs written, [16..18] the row expansion's
   // chunks, table entries and runs written
   uint32_t* cnt = P<uint32_t>(ctx->counters);
   ctx->counted_bwd = false;
-  fill_u32(cnt, 4, 0u, st);
+  fill_u32(cnt, 6, 0u, st);
   if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->ranges, sizeof(uint2) * ctx->n_tiles, 1.1)) != G4D_OK) return r;
@@ -603,7 +606,12 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
 
   int64_t n_vis = 0, n_pairs = 0, run_grid = 0;
   if (slots > 0) {
-    if ((r = run_preprocess(ctx, g, n_views, &s_run, st, false, cp)) != G4D_OK) return r;
+    const int64_t n_wc = ((int64_t)g->n + 255) / 256 * 4;  // waves of the preprocess
+    if ((r = ensure(ctx, ctx->wsum, sizeof(uint2) * n_wc, 1.1)) != G4D_OK) return r;
+    if ((r = ensure(ctx, ctx->vmask, sizeof(uint64_t) * n_wc * n_views, 1.1)) != G4D_OK) return r;
+    if ((r = run_preprocess(ctx, g, n_views, &s_run, st, false, cp, P<uint2>(ctx->wsum),
+                            P<uint64_t>(ctx->vmask))) != G4D_OK)
+      return r;
     if (ch && ch->n_features > 0) {
       if ((r = ensure(ctx, ctx->fn, sizeof(float) * (size_t)g->n * ch->n_features, 1.1)) != G4D_OK)
         return r;
@@ -632,38 +640,23 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     if ((r = ensure(ctx, ctx->scan_tmp, scan_scratch_bytes(std::max(slots, ctx->rhist_cap)),
                     1.1)) != G4D_OK)
       return r;
-    if ((r = ensure(ctx, ctx->sort_tmp, radix_scratch_bytes(slots), 1.1)) != G4D_OK) return r;
-    {
-      Stage t(ctx, 1, st);
-      compact_visible(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->dkey), slots,
-                      P<uint32_t>(ctx->vk[0]), P<uint32_t>(ctx->vv[0]), cnt + 0, ctx->scan_tmp.p, st);
-    }
+    if ((r = ensure(ctx, ctx->sort_tmp, depth_sort_scratch_bytes(slots, n_views), 1.1)) != G4D_OK)
+      return r;
     uint32_t* vk[2] = {P<uint32_t>(ctx->vk[0]), P<uint32_t>(ctx->vk[1])};
     uint32_t* vv[2] = {P<uint32_t>(ctx->vv[0]), P<uint32_t>(ctx->vv[1])};
     int vb;
     {
-      Stage t(ctx, 2, st);
-      vb = radix_sort(vk, vv, cnt + 0, slots, 32, ctx->sort_tmp.p, st);
+      Stage t(ctx, 1, st);
+      vb = depth_sort_by_view(P<uint32_t>(ctx->dkey), P<uint64_t>(ctx->vmask), n_wc, vk, vv,
+                              cnt + 0, slots, n_views,
+                              (uint32_t)g->n, P<uint2>(ctx->vrange), P<uint2>(ctx->wsum), n_wc,
+                              cnt + 1, ctx->sort_tmp.p, st);
     }
     ctx->vis_buf = vb;
-    {
-      Stage t(ctx, 3, st);
-      if (ctx->scan_tmp.cap < scan_scratch_bytes(slots))
-        return fail(ctx, G4D_EHIP, "scan scratch of %zu bytes below the %zu the totals need",
-                    ctx->scan_tmp.cap, scan_scratch_bytes(slots));
-      bin_totals(P<uint32_t>(ctx->tiles), P<uint32_t>(ctx->rowbox), slots, cnt + 1, cnt + 3,
-                 ctx->scan_tmp.p, st);
-    }
-    int gb;
-    {
-      Stage t(ctx, 4, st);
-      gb = group_by_view(vk, vv, vb, cnt + 0, slots, n_views, (uint32_t)g->n,
-                         P<uint2>(ctx->vrange), ctx->sort_tmp.p, st);
-    }
     G4D_HIP(hipGetLastError());
     auto run_rows = [&]() {
-      Stage t(ctx, 5, st);
-      splats_to_rows(P<uint2>(ctx->vrange), n_views, P<DView>(ctx->views), ctx->n_rows, vv[gb],
+      Stage t(ctx, 2, st);
+      splats_to_rows(P<uint2>(ctx->vrange), n_views, P<DView>(ctx->views), ctx->n_rows, vv[vb],
                      P<uint32_t>(ctx->rowbox), P<float>(ctx->rec), DS, row_chunks,
                      ctx->rhist_cap, ctx->row_cap, cnt + 3, P<uint4>(ctx->vinfo),
                      P<uint16_t>(ctx->cview), P<uint32_t>(ctx->rhist), cnt + 16,
@@ -680,7 +673,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       // not idle while the host reads the counts.  Should the runs exceed that capacity, the
       // list grows and the row expansion runs again.
       const bool early = ctx->row_cap > 0;
-      G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      G4D_HIP(hipMemcpyAsync(ctx->h_counters, cnt, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       G4D_HIP(hipEventRecord(ctx->counts_ready, st));
       if (early) run_rows();
       G4D_HIP(hipEventSynchronize(ctx->counts_ready));
@@ -688,8 +681,8 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
       n_pairs = ctx->h_counters[1];
       const int64_t n_runs = ctx->h_counters[3];
       // list positions are 32-bit signed in the raster kernels
-      if (n_pairs > (int64_t)INT32_MAX)
-        return fail(ctx, G4D_ECAPACITY, "%lld pairs exceed 2^31-1", (long long)n_pairs);
+      if (ctx->h_counters[5] || n_pairs > (int64_t)INT32_MAX || n_runs > (int64_t)INT32_MAX)
+        return fail(ctx, G4D_ECAPACITY, "the (Gaussian, tile) pairs or row runs exceed 2^31-1");
       if (ctx->arena && (n_pairs > ctx->pair_cap || n_runs > ctx->row_cap))
         return fail(ctx, G4D_ECAPACITY,
                     "%lld (Gaussian, tile) pairs in %lld row runs exceed the %lld pairs and %lld "
@@ -707,7 +700,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     }
     if (run_grid > 0) {
       {
-        Stage t(ctx, 6, st);
+        Stage t(ctx, 3, st);
         expand(P<uint2>(ctx->rrange), (int)ctx->n_rows, P<DView>(ctx->views), n_views,
                ctx->n_tiles, P<uint2>(ctx->runs), (run_grid + 63) / 64 + ctx->n_rows,
                ctx->hist_cap, ctx->pair_cap, cnt + 1, P<uint4>(ctx->rinfo), P<uint32_t>(ctx->crow),
@@ -718,7 +711,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     }
   }
   if (run_grid <= 0) {
-    Stage t(ctx, 6, st);
+    Stage t(ctx, 3, st);
     fill_u32(P<uint32_t>(ctx->ranges), 2 * ctx->n_tiles, 0u, st);
   }
   if (sky) {
@@ -752,7 +745,7 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     a.out_ch = out_ch;
   }
   {
-    Stage t(ctx, 7, st);
+    Stage t(ctx, 4, st);
     raster_forward(a, st);
   }
   G4D_HIP(hipGetLastError());
@@ -826,7 +819,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   const size_t grad2d_cap = ctx->grad2d.cap;
   if ((r = ensure(ctx, ctx->grad2d, sizeof(float) * kGrad2d * slots, 1.1)) != G4D_OK) return r;
   {
-    Stage t(ctx, 8, st);
+    Stage t(ctx, 5, st);
     if (!ctx->grad2d_zero || ctx->grad2d.cap != grad2d_cap)
       fill_u32(P<uint32_t>(ctx->grad2d), (int64_t)(ctx->grad2d.cap / sizeof(uint32_t)), 0u, st);
   }
@@ -866,14 +859,14 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
       a.dL_ch = dL_dch;
       a.dfn = P<float>(ctx->dfn);
     }
-    Stage t(ctx, 9, st);
+    Stage t(ctx, 6, st);
     raster_backward(a, st);
     G4D_HIP(hipGetLastError());
   }
   GradPtrs gp{out->mean4, out->scale4, out->rot_l,  out->rot_r,
               out->opacity, out->sh,  out->mask, out->densify};
   {
-    Stage t(ctx, 10, st);
+    Stage t(ctx, 7, st);
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
                         P<float>(ctx->rec), P<float>(ctx->grad2d), gp, st);
     G4D_HIP(hipGetLastError());
@@ -1092,11 +1085,14 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
   take(na->tiles, sizeof(uint32_t) * slots);
   take(na->rowbox, sizeof(uint32_t) * slots);
   take(na->dkey, sizeof(uint32_t) * slots);
+  const int64_t n_wc = (slots / std::max(n_views, 1) + 255) / 256 * 4;
+  take(na->wsum, sizeof(uint2) * n_wc);
+  take(na->vmask, sizeof(uint64_t) * n_wc * n_views);
   for (int b = 0; b < 2; ++b) {
     take(na->vk[b], sizeof(uint32_t) * slots);
     take(na->vv[b], sizeof(uint32_t) * slots);
   }
-  take(na->sort_tmp, radix_scratch_bytes(slots));
+  take(na->sort_tmp, depth_sort_scratch_bytes(slots, n_views));
   take(na->vrange, sizeof(uint2) * n_views);
   take(na->vinfo, 2 * sizeof(uint4) * n_views);
   take(na->cview, sizeof(uint16_t) * ((slots + 63) / 64 + n_views));

@@ -18,6 +18,15 @@ namespace {
 // out 64 per round, and each lane adds its row's run of tile columns to the row owner's count
 // in LDS.  A wave so takes about (rows of its splats) / 64 rounds per view instead of the rows of
 // its largest splat, and the count uses the very function the key generation writes with.
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, o, 64), hi = __shfl_xor((uint32_t)(x >> 32), o, 64);
+    x += ((uint64_t)hi << 32) | lo;
+  }
+  return x;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -31,7 +40,9 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, float* __restrict__ rec,
     uint32_t* __restrict__ tiles, uint32_t* __restrict__ rowbox, uint32_t* __restrict__ dkey,
-    const float* __restrict__ mask, float mask_thr, CompactPtrs cp) {
+    uint2* __restrict__ wsum, uint64_t* __restrict__ vmask, const float* __restrict__ mask,
+    float mask_thr,
+    CompactPtrs cp) {
   constexpr int NSH = (DT + 1) * (DS + 1) * (DS + 1) * 3;
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64], s_lim[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64];
@@ -39,6 +50,8 @@ __global__ __launch_bounds__(256) void k_preprocess(
   __shared__ uint32_t s_row0[4][64], s_cnt[4][64];
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wave = blockIdx.x * 4 + w;
+  const size_t n_wc = (size_t)gridDim.x * 4;
   const bool in_range = gi < n;
   // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
   const bool live = in_range && !(mask && !(mask[gi] > mask_thr));
@@ -47,7 +60,12 @@ __global__ __launch_bounds__(256) void k_preprocess(
       tiles[(size_t)v * n + gi] = 0u;
       rowbox[(size_t)v * n + gi] = ~0u;
     }
-  if (__ballot(live) == 0ull) return;  // the whole wave: the lanes below work together
+  if (__ballot(live) == 0ull) {  // the whole wave: the lanes below work together
+    if (wsum && lane == 0) wsum[wave] = make_uint2(0u, 0u);
+    if (vmask)
+      for (int v = lane; v < n_views; v += 64) vmask[(size_t)v * n_wc + wave] = 0ull;
+    return;
+  }
   // Lanes past the end read the last Gaussian (unconditional loads of read-only data, which
   // the compiler may repeat per view instead of holding 4DSH coefficients in registers); only
   // live lanes list anything.
@@ -79,6 +97,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
   const bool alive = live && fin;
   Geom g;
   geom_forward(qlr, qrr, sc4, g);
+  uint64_t n_pairs = 0, n_runs = 0;  // listed by this lane
   for (int v = 0; v < n_views; ++v) {
     const DView& V = views[v];
     const size_t slot = (size_t)v * n + gi;
@@ -145,6 +164,20 @@ __global__ __launch_bounds__(256) void k_preprocess(
       // the tile rows of its box, first << 16 | last, for the row binning
       rowbox[slot] = cnt > 0 ? ((uint32_t)y0 << 16) | (uint32_t)y1 : ~0u;
     }
+    n_pairs += cnt;
+    n_runs += cnt > 0 ? (uint32_t)(y1 - y0 + 1) : 0u;
+    if (vmask) {
+      const uint64_t listed = __ballot(cnt > 0);
+      if (lane == 0) vmask[(size_t)v * n_wc + wave] = listed;
+    }
+  }
+  // the wave's pairs and runs (held at 2^31, which no valid total reaches)
+  if (wsum) {
+    n_pairs = wave_sum_u64(n_pairs);
+    n_runs = wave_sum_u64(n_runs);
+    if (lane == 0)
+      wsum[wave] = make_uint2((uint32_t)min(n_pairs, 0x80000000ull),
+                              (uint32_t)min(n_runs, 0x80000000ull));
   }
 }
 
@@ -323,19 +356,20 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
 
 template <int DS, int DT>
 void launch_fwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S, float* rec,
-                uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, hipStream_t st) {
+                uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, uint2* wsum, uint64_t* vmask,
+                hipStream_t st) {
   const int blocks = (gp.n + 255) / 256;
   if (gp.compact)
     hipLaunchKernelGGL((k_preprocess<DS, DT, true>), dim3(blocks), dim3(256), 0, st, gp.n, n_views,
                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, views, S, rec, tiles,
-                       rowbox, dkey, nullptr, 0.f, *gp.compact);
+                       rowbox, dkey, wsum, vmask, nullptr, 0.f, *gp.compact);
   else
     hipLaunchKernelGGL((k_preprocess<DS, DT, false>), dim3(blocks), dim3(256), 0, st, gp.n,
                        n_views, reinterpret_cast<const float4*>(gp.mean4),
                        reinterpret_cast<const float4*>(gp.scale4),
                        reinterpret_cast<const float4*>(gp.rot_l),
                        reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
-                       rec, tiles, rowbox, dkey, gp.mask, gp.mask_thr, CompactPtrs{});
+                       rec, tiles, rowbox, dkey, wsum, vmask, gp.mask, gp.mask_thr, CompactPtrs{});
 }
 
 template <int DS, int DT>
@@ -395,11 +429,12 @@ void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings 
 
 template <int DS>
 void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S, float* rec,
-                    uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, hipStream_t st) {
+                    uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey, uint2* wsum,
+                    uint64_t* vmask, hipStream_t st) {
   switch (gp.t_degree) {
-    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
-    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
-    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, rowbox, dkey, st); break;
+    case 0: launch_fwd<DS, 0>(gp, views, nv, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
+    case 1: launch_fwd<DS, 1>(gp, views, nv, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
+    default: launch_fwd<DS, 2>(gp, views, nv, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
   }
 }
 
@@ -418,13 +453,13 @@ void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 
 void preprocess_forward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
                         float* rec, uint32_t* tiles, uint32_t* rowbox, uint32_t* dkey,
-                        hipStream_t st) {
+                        uint2* wsum, uint64_t* vmask, hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {
-    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
-    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
-    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
-    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, rowbox, dkey, st); break;
+    case 0: dispatch_fwd_t<0>(gp, views, n_views, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
+    case 1: dispatch_fwd_t<1>(gp, views, n_views, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
+    case 2: dispatch_fwd_t<2>(gp, views, n_views, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
+    default: dispatch_fwd_t<3>(gp, views, n_views, S, rec, tiles, rowbox, dkey, wsum, vmask, st); break;
   }
 }
 

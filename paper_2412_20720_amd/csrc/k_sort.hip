@@ -1,16 +1,17 @@
-// Binning kernels: stream compaction of visible (view, Gaussian) slots, device-wide scans, an
-// LDS-staged wavefront LSD radix sort, range detection and the row binning.
+// Binning kernels: stream compaction of visible (view, Gaussian) slots, device-wide scans, a
+// per-view LDS-staged wavefront LSD radix sort by depth, and the row binning.
 //
 // Binning follows the tile-based rasterizer the paper adopts (Sec. 3.2): every splat is
 // listed in each screen tile its reach ellipse touches, and each tile's list is ordered by
 // camera depth, front to back (Sec. 3.1 composites the splats in depth order).  Here the
-// depth order is made once per visible splat (a 32-bit depth sort of the compacted slots); the
-// splats' runs of tiles per tile row are then emitted in depth order, sorted stably by tile
-// row alone and expanded into the tile lists, so each tile's list inherits the depth order
-// (ties keep the slot order, i.e. the Gaussian index).
+// depth order is made once per visible splat (a 32-bit sort of each view's compacted slots);
+// each view's splats are then transposed, in depth order, into runs of tile columns per tile
+// row, and the runs into the tile lists, each by a count pass, one scan and a write pass, so
+// each tile's list inherits the depth order (ties keep the slot order, i.e. the Gaussian index).
 #include <hip/hip_runtime.h>
 #include <algorithm>
 
+#include "../../include/g4d.h"
 #include "g4d_internal.h"
 
 namespace g4d {
@@ -22,8 +23,8 @@ constexpr int kPerThread = kItems / kThreads;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 // Items per workgroup of a radix pass (a multiple of 4 x 64).  The depth sort of the
-// 300k-Gaussian, 16-view workload (1.8M slots, 32-bit keys) takes 0.149 ms at 4096,
-// 0.143 at 2048 and 0.201 at 8192.
+// 300k-Gaussian, 16-view workload (1.8M slots, 32-bit keys) took 0.149 ms at 4096,
+// 0.143 at 2048 and 0.201 at 8192 as one sort over all views.
 #ifndef G4D_RADIX_ITEMS
 #define G4D_RADIX_ITEMS 4096
 #endif
@@ -66,10 +67,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total,
 // Generic three-phase exclusive scan: per-block sums, a one-block scan of the sums, and a
 // per-block scan that hands (index, exclusive prefix, value) to an output functor.
 // ------------------------------------------------------------------------------------------
-struct InFlag {
-  const uint32_t* p;
-  __device__ uint32_t operator()(int64_t i) const { return p[i] > 0u ? 1u : 0u; }
-};
 struct InPlain {
   const uint32_t* p;
   __device__ uint32_t operator()(int64_t i) const { return p[i]; }
@@ -77,17 +74,6 @@ struct InPlain {
 struct OutStore {
   uint32_t* out;
   __device__ void operator()(int64_t i, uint32_t excl, uint32_t) const { out[i] = excl; }
-};
-struct OutCompact {
-  const uint32_t* dkey;
-  uint32_t* okey;
-  uint32_t* oval;
-  __device__ void operator()(int64_t i, uint32_t excl, uint32_t v) const {
-    if (v) {
-      okey[excl] = dkey[i];
-      oval[excl] = (uint32_t)i;
-    }
-  }
 };
 
 __device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_host) {
@@ -220,32 +206,249 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 }
 
 // ------------------------------------------------------------------------------------------
-// Radix sort pass: digit histogram per block, scan of the (digit, block) table, and a
-// stable scatter.  Each wave owns a contiguous 1024-item run of its block; ranks inside a
-// wave come from ballot-based digit matching, so equal digits keep their input order.
+// Depth sort within each view.  The compacted visible slots come in slot order and slots are
+// view-major (slot = view * N + Gaussian), so each view's splats already lie together; a
+// stable LSD radix sort of the depth keys inside each view's segment (8 bits per pass) leaves
+// them grouped by view, in depth order, slot order among equal keys.  A radix workgroup takes
+// up to kRadixItems items of one view.  A pass counts digits per workgroup, turns each view's
+// counts into scatter offsets with one workgroup per view (the scan starts at the view's first
+// slot) and scatters.  Each wave owns a contiguous 1024-item run of its workgroup; ranks
+// inside a wave come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
-template <typename K, int NT>
-__global__ __launch_bounds__(NT) void k_radix_hist(const K* __restrict__ key,
-                                                   const uint32_t* n_dev, int shift,
-                                                   uint32_t mask, uint32_t* hist, int nblocks) {
-  constexpr int NW = NT / 64, ITEMS = NT * kRadixPerThread;
-  __shared__ uint32_t wh[NW][kRadix];
+
+// Per view v: its listed slots' place [lo, hi) in the sorted list, from the preprocess's
+// listing masks per view and wave of 64 Gaussians, vmask[v * n_wc + wave] (lo = the listed
+// slots of the views before it); *n_vis = all of them; vfirst[v] = the view's first radix
+// workgroup of the later passes; per such workgroup b < bcap: binfo[b] = (first item, items,
+// the view's first workgroup, the view's workgroups), items = 0 past the last workgroup.  Also
+// adds up the preprocess's per-wave pair and run counts (see depth_sort_by_view).
+__global__ __launch_bounds__(1024) void k_view_segments(const uint64_t* __restrict__ vmask,
+                                                        int64_t n_wc, int n_views,
+                                                        uint32_t* n_vis,
+                                                        uint2* __restrict__ vrange,
+                                                        uint4* __restrict__ binfo, int64_t bcap,
+                                                        uint32_t* __restrict__ vfirst,
+                                                        const uint2* __restrict__ wsum,
+                                                        int64_t n_wsum, uint32_t* totals) {
+  __shared__ uint32_t s_len[G4D_MAX_VIEWS], s_lo[G4D_MAX_VIEWS], s_fb[G4D_MAX_VIEWS];
+  __shared__ uint32_t s_w[16], s_n[16];
+  __shared__ uint64_t s_p[16], s_r[16];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wh[0][0])[d] = 0;
-  __syncthreads();
-  const int64_t n = *n_dev;
-  const int64_t base = (int64_t)blockIdx.x * ITEMS + w * (ITEMS / NW);
-#pragma unroll 4
-  for (int r = 0; r < kRadixPerThread; ++r) {
-    const int64_t i = base + r * 64 + lane;
-    if (i < n) atomicAdd(&wh[w][((uint32_t)key[i] >> shift) & mask], 1u);
+  if (wsum) {
+    uint64_t p = 0, r = 0;
+    for (int64_t i = threadIdx.x; i < n_wsum; i += 4 * 1024) {
+      uint2 c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        c[u] = i + u * 1024 < n_wsum ? wsum[i + u * 1024] : make_uint2(0u, 0u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        p += c[u].x;
+        r += c[u].y;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      p += ((uint64_t)__shfl_xor((uint32_t)(p >> 32), o, 64) << 32) | __shfl_xor((uint32_t)p, o, 64);
+      r += ((uint64_t)__shfl_xor((uint32_t)(r >> 32), o, 64) << 32) | __shfl_xor((uint32_t)r, o, 64);
+    }
+    if (lane == 0) {
+      s_p[w] = p;
+      s_r[w] = r;
+    }
+  }
+  // listed slots per view: a wave per view, four 16-byte loads (eight masks) in flight per lane
+  // (n_wc is a multiple of 4, so each view's masks start 32-byte aligned)
+  for (int v = w; v < n_views; v += 16) {
+    const ulonglong2* c = reinterpret_cast<const ulonglong2*>(vmask + (size_t)v * (size_t)n_wc);
+    const int64_t n2 = n_wc / 2;
+    uint32_t t = 0;
+    for (int64_t i = lane; i < n2; i += 4 * 64) {
+      ulonglong2 m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) m[u] = i + u * 64 < n2 ? c[i + u * 64] : make_ulonglong2(0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t += (uint32_t)(__popcll(m[u].x) + __popcll(m[u].y));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) s_len[v] = t;
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += NT) {
-    uint32_t t = 0;
+  if (wsum && threadIdx.x == 0) {
+    uint64_t p = 0, r = 0;
+    for (int k = 0; k < 16; ++k) {
+      p += s_p[k];
+      r += s_r[k];
+    }
+    totals[0] = (uint32_t)min(p, (uint64_t)UINT32_MAX);
+    totals[2] = (uint32_t)min(r, (uint64_t)UINT32_MAX);
+    totals[4] = (p >= 0x80000000ull || r >= 0x80000000ull) ? 1u : 0u;
+  }
+  const int v = threadIdx.x;
+  uint32_t len = 0, nb = 0;
+  if (v < n_views) {
+    len = s_len[v];
+    nb = (len + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
+  }
+  const uint32_t inc = wave_incl_scan(nb), inc_n = wave_incl_scan(len);
+  if (lane == 63) {
+    s_w[w] = inc;
+    s_n[w] = inc_n;
+  }
+  __syncthreads();
+  uint32_t pre = 0, total = 0, pre_n = 0, total_n = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) t += wh[k][d];
-    hist[(int64_t)d * nblocks + blockIdx.x] = t;
+  for (int k = 0; k < 16; ++k) {
+    pre += (k < w) ? s_w[k] : 0u;
+    total += s_w[k];
+    pre_n += (k < w) ? s_n[k] : 0u;
+    total_n += s_n[k];
+  }
+  if (v < n_views) {
+    const uint32_t lo = pre_n + inc_n - len;
+    vrange[v] = make_uint2(lo, lo + len);
+    s_lo[v] = lo;
+    s_fb[v] = pre + inc - nb;
+    vfirst[v] = pre + inc - nb;
+  }
+  if (threadIdx.x == 0) *n_vis = total_n;
+  __syncthreads();
+  for (int u = w; u < n_views; u += 16) {
+    const uint32_t ulo = s_lo[u], ulen = s_len[u], fb = s_fb[u];
+    const uint32_t unb = (ulen + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
+    for (uint32_t j = (uint32_t)lane; j < unb; j += 64) {
+      const uint32_t first = j * (uint32_t)kRadixItems;
+      if ((int64_t)(fb + j) < bcap)
+        binfo[fb + j] = make_uint4(ulo + first, min((uint32_t)kRadixItems, ulen - first), fb,
+                                   unb);
+    }
+  }
+  for (int64_t b = (int64_t)total + threadIdx.x; b < bcap; b += 1024)
+    binfo[b] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The items of a radix workgroup.  The first pass reads the preprocess's arrays themselves:
+// workgroup b covers kRadixItems slots of view b / nb1, its items the listed ones (key = the
+// depth key, value = the slot), found from the listing masks: vmask[view * n_wc + c] has bit l
+// set if slot view * N + 64 c + l is listed.  The later passes take binfo[b] = (first item,
+// items, ...).
+struct SegItems {
+  uint32_t first, end, vbase;  // vbase: the view's first slot (first pass)
+  __device__ bool load(bool first_pass, const uint4* __restrict__ binfo, uint32_t nb1,
+                       uint32_t n_per_view) {
+    if (first_pass) {
+      const uint32_t v = blockIdx.x / nb1, j = blockIdx.x - v * nb1;
+      vbase = v * n_per_view;
+      first = vbase + j * (uint32_t)kRadixItems;
+      end = min(first + (uint32_t)kRadixItems, vbase + n_per_view);
+    } else {
+      const uint4 bi = binfo[blockIdx.x];
+      first = bi.x;
+      end = bi.x + bi.y;
+      vbase = 0;
+    }
+    return end > first;
+  }
+  // First pass: the listing mask of the 64 slots from slot0 (a multiple of 64 past vbase);
+  // 0 past the workgroup's end.
+  __device__ uint64_t mask(const uint64_t* __restrict__ vmask, uint64_t row,
+                           uint32_t slot0) const {
+    return slot0 < end ? vmask[row + ((slot0 - vbase) >> 6)] : 0ull;
+  }
+};
+
+// Digit counts of one workgroup's items: table[256 b + d] for workgroup b and digit d.
+template <bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_seg_hist(const uint32_t* __restrict__ key,
+                                                       const uint64_t* __restrict__ vmask,
+                                                       int64_t n_wc,
+                                                       const uint4* __restrict__ binfo,
+                                                       uint32_t nb1, uint32_t n_per_view,
+                                                       int shift, uint32_t* __restrict__ table) {
+  constexpr int NW = kThreads / 64;
+  static_assert(kThreads == kRadix, "one thread per digit");
+  __shared__ uint32_t wh[NW][kRadix];
+  SegItems it;
+  if (!it.load(FIRST, binfo, nb1, n_per_view)) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < NW * kRadix; d += kThreads) (&wh[0][0])[d] = 0;
+  __syncthreads();
+  const uint32_t end = it.end;
+  const uint32_t base = it.first + (uint32_t)w * (kRadixItems / NW);
+  const uint64_t row = FIRST ? (uint64_t)(blockIdx.x / nb1) * (uint64_t)n_wc : 0;
+#pragma unroll 4
+  for (int r = 0; r < kRadixPerThread; ++r) {
+    const uint32_t i = base + (uint32_t)(r * 64 + lane);
+    const bool valid = FIRST ? ((it.mask(vmask, row, base + (uint32_t)(r * 64)) >> lane) & 1ull)
+                             : i < end;
+    if (valid) atomicAdd(&wh[w][(key[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  const int d = threadIdx.x;
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) t += wh[k][d];
+  table[(uint32_t)kRadix * blockIdx.x + (uint32_t)d] = t;
+}
+
+// One workgroup per view turns the view's counts into scatter offsets: each digit's total over
+// the view's workgroups, an exclusive scan over the digits from the view's first place in the
+// sorted list, and per workgroup the counts of the digit in the view's earlier ones.  Four
+// threads per digit, each over a quarter of the view's workgroups with eight loads in flight.
+// The first pass's workgroups: nb1 per view (nb1 > 0).
+constexpr int kScanThreads = 4 * kRadix;
+__global__ __launch_bounds__(kScanThreads) void k_seg_scan(const uint2* __restrict__ vrange,
+                                                           const uint4* __restrict__ binfo,
+                                                           const uint32_t* __restrict__ vfirst,
+                                                           uint32_t nb1,
+                                                           uint32_t* __restrict__ table) {
+  __shared__ uint32_t s_part[4][kRadix], s_base[kRadix], lds4[4];
+  const uint32_t v = blockIdx.x;
+  const uint2 r = vrange[v];
+  if (r.y == r.x) return;
+  const uint32_t fb = nb1 ? v * nb1 : vfirst[v];
+  const uint32_t nb = nb1 ? nb1 : binfo[fb].w;
+  const int d = threadIdx.x & (kRadix - 1), q = threadIdx.x / kRadix;
+  const uint32_t per = (nb + 3u) / 4u;
+  const uint32_t j0 = min((uint32_t)q * per, nb), j1 = min(j0 + per, nb);
+  uint32_t* col = table + (uint32_t)kRadix * fb + (uint32_t)d;
+  uint32_t part = 0;
+  for (uint32_t j = j0; j < j1; j += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = (j + u < j1) ? col[(uint32_t)kRadix * (j + u)] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part += c[u];
+  }
+  s_part[q][d] = part;
+  __syncthreads();
+  uint32_t tot = 0, inc = 0;
+  if (q == 0) {  // waves 0-3: the exclusive scan of the digit totals
+    tot = s_part[0][d] + s_part[1][d] + s_part[2][d] + s_part[3][d];
+    inc = wave_incl_scan(tot);
+    if ((d & 63) == 63) lds4[d >> 6] = inc;
+  }
+  __syncthreads();
+  if (q == 0) {
+    uint32_t pre = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pre += (k < (d >> 6)) ? lds4[k] : 0u;
+    s_base[d] = r.x + pre + inc - tot;
+  }
+  __syncthreads();
+  uint32_t run = s_base[d];
+  for (int k = 0; k < q; ++k) run += s_part[k][d];
+  for (uint32_t j = j0; j < j1; j += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = (j + u < j1) ? col[(uint32_t)kRadix * (j + u)] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j + u < j1) {
+        col[(uint32_t)kRadix * (j + u)] = run;
+        run += c[u];
+      }
   }
 }
 
@@ -260,36 +463,56 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
   return peers;
 }
 
-template <typename K, int NT, typename V>
-__global__ __launch_bounds__(NT) void k_radix_scatter(
-    const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
-    V* __restrict__ vout, const uint32_t* n_dev, int shift, uint32_t mask,
-    const uint32_t* __restrict__ hist, int nblocks) {
-  constexpr int NW = NT / 64, ITEMS = NT * kRadixPerThread;
-  static_assert(NT >= kRadix, "one thread per digit");
+template <bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_seg_scatter(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    const uint64_t* __restrict__ vmask, int64_t n_wc, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint4* __restrict__ binfo, uint32_t nb1,
+    uint32_t n_per_view, int shift, const uint32_t* __restrict__ table) {
+  constexpr int NW = kThreads / 64;
+  static_assert(kThreads >= kRadix, "one thread per digit");
   __shared__ uint32_t wcount[NW][kRadix];
   __shared__ uint32_t bstart[kRadix];
   __shared__ uint32_t goff[kRadix];
-  __shared__ K sk[ITEMS];
-  __shared__ V sv[ITEMS];
+  __shared__ uint32_t sk[kRadixItems];
+  __shared__ uint32_t sv[kRadixItems];
   __shared__ uint32_t lds4[4];
-  const int64_t n = *n_dev;
-  const int64_t bbase = (int64_t)blockIdx.x * ITEMS;
-  if (bbase >= n) return;
+  SegItems it;
+  if (!it.load(FIRST, binfo, nb1, n_per_view)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = threadIdx.x; d < NW * kRadix; d += NT) (&wcount[0][0])[d] = 0;
+  for (int d = threadIdx.x; d < NW * kRadix; d += kThreads) (&wcount[0][0])[d] = 0;
   __syncthreads();
-  const int64_t base = bbase + w * (ITEMS / NW);
+  const uint32_t end = it.end;
+  const uint32_t base = it.first + (uint32_t)w * (kRadixItems / NW);
   const uint64_t lt = lanemask_lt();
-  uint32_t k[kRadixPerThread], rank[kRadixPerThread];
-  V v[kRadixPerThread];
+  // The wave's items as dense rounds of 64: in the first pass its listed slots, packed in
+  // slot order into its quarter of sk (which the ranking frees before the LDS sort uses it).
+  uint32_t n_w;  // the wave's items (uniform)
+  uint32_t* stage = sk + w * (kRadixItems / NW);
+  if constexpr (FIRST) {
+    const uint64_t row = (uint64_t)(blockIdx.x / nb1) * (uint64_t)n_wc;
+    n_w = 0;
+#pragma unroll 4
+    for (int r = 0; r < kRadixPerThread; ++r) {
+      const uint32_t slot0 = base + (uint32_t)(r * 64);
+      const uint64_t m = it.mask(vmask, row, slot0);
+      if ((m >> lane) & 1ull) stage[n_w + (uint32_t)__popcll(m & lt)] = slot0 + (uint32_t)lane;
+      n_w += (uint32_t)__popcll(m);
+    }
+    wave_lds_sync();
+  } else {
+    n_w = end > base ? min(end - base, (uint32_t)(kRadixItems / NW)) : 0u;
+  }
+  uint32_t k[kRadixPerThread], v[kRadixPerThread], rank[kRadixPerThread];
 #pragma unroll
   for (int r = 0; r < kRadixPerThread; ++r) {
-    const int64_t i = base + r * 64 + lane;
-    const bool valid = i < n;
-    k[r] = valid ? (uint32_t)kin[i] : 0u;
-    v[r] = valid ? vin[i] : V{};
-    const uint32_t d = (k[r] >> shift) & mask;
+    if ((uint32_t)(r * 64) >= n_w) break;  // uniform: the wave's items are done
+    const uint32_t e = (uint32_t)(r * 64 + lane);
+    const bool valid = e < n_w;
+    const uint32_t i = FIRST ? (valid ? stage[e] : 0u) : base + e;
+    k[r] = valid ? kin[i] : 0u;
+    v[r] = valid ? (FIRST ? i : vin[i]) : 0u;
+    const uint32_t d = (k[r] >> shift) & (kRadix - 1);
     const uint64_t peers = match_digit(d, __ballot(valid));
     const uint32_t before = wcount[w][d];
     rank[r] = before + (uint32_t)__popcll(peers & lt);
@@ -298,10 +521,10 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // Per-digit totals, exclusive prefix over waves (in place) and over digits (bstart): the
-  // first 256 threads hold one digit each.
+  // Per-digit totals, exclusive prefix over waves (in place) and over digits (bstart): a
+  // thread per digit.
   uint32_t tot = 0;
-  if (threadIdx.x < kRadix) {
+  {
     const int d = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
@@ -309,35 +532,34 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(
       wcount[q][d] = tot;
       tot += c;
     }
-    goff[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+    goff[d] = table[(uint32_t)kRadix * blockIdx.x + (uint32_t)d];
   }
-  const uint32_t inc = wave_incl_scan(tot);  // waves past the digits scan zeros
-  if (lane == 63 && w < 4) lds4[w] = inc;
+  const uint32_t inc = wave_incl_scan(tot);
+  if (lane == 63) lds4[w] = inc;
   __syncthreads();
-  if (threadIdx.x < kRadix) {
+  {
     uint32_t pre = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) pre += (q < w) ? lds4[q] : 0u;
     bstart[threadIdx.x] = pre + inc - tot;
   }
+  const uint32_t cnt = lds4[0] + lds4[1] + lds4[2] + lds4[3];  // the workgroup's items
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRadixPerThread; ++r) {
-    const int64_t i = base + r * 64 + lane;
-    if (i < n) {
-      const uint32_t d = (k[r] >> shift) & mask;
+    if ((uint32_t)(r * 64 + lane) < n_w) {
+      const uint32_t d = (k[r] >> shift) & (kRadix - 1);
       const uint32_t pos = bstart[d] + wcount[w][d] + rank[r];
-      sk[pos] = (K)k[r];
+      sk[pos] = k[r];
       sv[pos] = v[r];
     }
   }
   __syncthreads();
-  const int cnt = (int)((n - bbase) < ITEMS ? (n - bbase) : ITEMS);
-  for (int p = threadIdx.x; p < cnt; p += NT) {
-    const uint32_t kk = (uint32_t)sk[p];
-    const uint32_t d = (kk >> shift) & mask;
-    const uint32_t dst = goff[d] + ((uint32_t)p - bstart[d]);
-    kout[dst] = (K)kk;
+  for (uint32_t p = threadIdx.x; p < cnt; p += kThreads) {
+    const uint32_t kk = sk[p];
+    const uint32_t d = (kk >> shift) & (kRadix - 1);
+    const uint32_t dst = goff[d] + (p - bstart[d]);
+    kout[dst] = kk;
     vout[dst] = sv[p];
   }
 }
@@ -380,75 +602,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 // Rows of a packed row box (first << 16 | last; ~0u: none).
 __device__ __forceinline__ uint32_t box_rows(uint32_t rb) {
   return rb == ~0u ? 0u : (rb & 0xFFFFu) - (rb >> 16) + 1u;
-}
-
-// Block sums of the tile counts and of the box rows (16 items per thread), then one block adds
-// them up.
-__global__ __launch_bounds__(kThreads) void k_sum2_blocks(const uint32_t* __restrict__ a,
-                                                          const uint32_t* __restrict__ b,
-                                                          int64_t n, uint2* __restrict__ sums) {
-  __shared__ uint32_t s_a[4], s_b[4];
-  const int64_t base = (int64_t)blockIdx.x * kItems;
-  uint32_t sa = 0, sb = 0;
-#pragma unroll
-  for (int r = 0; r < kPerThread; ++r) {
-    const int64_t i = base + r * kThreads + threadIdx.x;
-    if (i < n) {
-      sa += a[i];
-      sb += box_rows(b[i]);
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sa += __shfl_xor(sa, o, 64);
-    sb += __shfl_xor(sb, o, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    s_a[w] = sa;
-    s_b[w] = sb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    sums[blockIdx.x] = make_uint2(s_a[0] + s_a[1] + s_a[2] + s_a[3], s_b[0] + s_b[1] + s_b[2] + s_b[3]);
-}
-
-__global__ __launch_bounds__(1024) void k_sum2_final(const uint2* __restrict__ sums, int count,
-                                                     uint32_t* ta, uint32_t* tb) {
-  __shared__ uint32_t s_a[16], s_b[16];
-  uint32_t sa = 0, sb = 0;
-  for (int i = threadIdx.x; i < count; i += 1024) {
-    sa += sums[i].x;
-    sb += sums[i].y;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sa += __shfl_xor(sa, o, 64);
-    sb += __shfl_xor(sb, o, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    s_a[w] = sa;
-    s_b[w] = sb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t A = 0, B = 0;
-    for (int k = 0; k < 16; ++k) {
-      A += s_a[k];
-      B += s_b[k];
-    }
-    *ta = A;
-    *tb = B;
-  }
-}
-
-// View index of each visible slot: the key of the regrouping pass.
-__global__ void k_view_keys(const uint32_t* __restrict__ vval, const uint32_t* n_dev, int64_t cap,
-                            uint32_t n_per_view, uint16_t* __restrict__ keys) {
-  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) keys[i] = (uint16_t)(vval[i] / n_per_view);
 }
 
 // Per view v (one workgroup of 256 threads, a thread per view): its splats [lo, lo + len) in
@@ -1016,39 +1169,6 @@ __global__ void k_tile_ids(const uint2* __restrict__ ranges, int64_t n_tiles, in
 // Tile boundaries in the sorted keys, four keys per thread (one 16-byte load; the neighbours
 // on either side come from the caches).
 // Four keys per thread (one 4-key vector load), compared with their neighbours.
-template <typename K> struct Key4;
-template <> struct Key4<uint32_t> { using T = uint4; };
-template <> struct Key4<uint16_t> { using T = ushort4; };
-
-template <typename K>
-__global__ void k_ranges(const K* __restrict__ key, const uint32_t* n_dev, int64_t cap,
-                         int64_t n_tiles, uint2* ranges) {
-  const int64_t n = (int64_t)*n_dev < cap ? (int64_t)*n_dev : cap;
-  const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-  if (i0 >= n) return;
-  uint32_t k[6];  // key[i0 - 1 .. i0 + 4]
-  if (i0 + 4 <= n) {
-    const typename Key4<K>::T q = *reinterpret_cast<const typename Key4<K>::T*>(key + i0);
-    k[1] = q.x;
-    k[2] = q.y;
-    k[3] = q.z;
-    k[4] = q.w;
-  } else {
-    for (int j = 0; j < 4; ++j) k[1 + j] = (i0 + j < n) ? (uint32_t)key[i0 + j] : 0u;
-  }
-  k[0] = i0 > 0 ? (uint32_t)key[i0 - 1] : 0u;
-  k[5] = i0 + 4 < n ? (uint32_t)key[i0 + 4] : 0u;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t i = i0 + j;
-    if (i >= n) break;
-    const uint32_t kk = k[1 + j];
-    if ((int64_t)kk >= n_tiles) continue;  // dummy tile
-    if (i == 0 || k[j] != kk) ranges[kk].x = (uint32_t)i;
-    if (i == n - 1 || k[2 + j] != kk) ranges[kk].y = (uint32_t)(i + 1);
-  }
-}
-
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1075,90 +1195,49 @@ void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
 }
 
-// One uint2 per block of kItems items: the scans use its first word, bin_totals both.
 size_t scan_scratch_bytes(int64_t n) {
-  return sizeof(uint2) * (size_t)((n + kItems - 1) / kItems + 1);
+  return sizeof(uint32_t) * (size_t)((n + kItems - 1) / kItems + 1);
 }
 
-void compact_visible(const uint32_t* tiles, const uint32_t* dkey, int64_t n_slots,
-                     uint32_t* out_key, uint32_t* out_val, uint32_t* n_out, void* scratch,
-                     hipStream_t st) {
-  scan_generic(InFlag{tiles}, InFlag{tiles}, OutCompact{dkey, out_key, out_val}, nullptr, n_slots,
-               n_out, scratch, st);
+size_t depth_sort_scratch_bytes(int64_t n_cap, int n_views) {
+  const int64_t bcap = (n_cap + kRadixItems - 1) / kRadixItems + n_views;
+  return sizeof(uint32_t) * (size_t)(bcap * kRadix) + sizeof(uint4) * (size_t)bcap +
+         sizeof(uint32_t) * (size_t)G4D_MAX_VIEWS;
 }
 
-void bin_totals(const uint32_t* tiles, const uint32_t* nrows, int64_t n, uint32_t* pairs,
-                uint32_t* runs, void* scratch, hipStream_t st) {
-  const int64_t blocks = (n + kItems - 1) / kItems;
-  if (blocks == 0) {
-    fill_u32(pairs, 1, 0u, st);
-    fill_u32(runs, 1, 0u, st);
-    return;
-  }
-  uint2* sums = static_cast<uint2*>(scratch);
-  hipLaunchKernelGGL(k_sum2_blocks, dim3((unsigned)blocks), dim3(kThreads), 0, st, tiles, nrows, n,
-                     sums);
-  hipLaunchKernelGGL(k_sum2_final, dim3(1), dim3(1024), 0, st, sums, (int)blocks, pairs, runs);
-}
-
-size_t radix_scratch_bytes(int64_t n_cap) {
-  const int64_t blocks = (n_cap + kRadixItems - 1) / kRadixItems;
-  const int64_t table = blocks * kRadix;
-  return sizeof(uint32_t) * (size_t)(table + 16) + scan_scratch_bytes(table);
-}
-
-template <typename K, int NT, typename V>
-int radix_sort_nt(K* key[2], V* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-                  void* scratch, hipStream_t st) {
-  constexpr int64_t ITEMS = (int64_t)NT * kRadixPerThread;
-  const int64_t blocks = (n_cap + ITEMS - 1) / ITEMS;
-  if (blocks == 0 || bits <= 0) return 0;
-  uint32_t* hist = static_cast<uint32_t*>(scratch);
-  void* scan_tmp = hist + blocks * kRadix + 16;
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
-    const int nb = (bits - shift) < kRadixBits ? (bits - shift) : kRadixBits;
-    const uint32_t mask = (1u << nb) - 1u;
-    hipLaunchKernelGGL((k_radix_hist<K, NT>), dim3((unsigned)blocks), dim3(NT), 0, st, key[cur],
-                       n_dev, shift, mask, hist, (int)blocks);
-    scan_generic(InPlain{hist}, InPlain{hist}, OutStore{hist}, nullptr, blocks * kRadix, nullptr,
-                 scan_tmp, st);
-    hipLaunchKernelGGL((k_radix_scatter<K, NT, V>), dim3((unsigned)blocks), dim3(NT), 0, st,
-                       key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], n_dev, shift, mask, hist,
-                       (int)blocks);
+int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc, uint32_t* key[2], uint32_t* val[2], uint32_t* n_vis,
+                       int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange,
+                       const uint2* wsum, int64_t n_wsum, uint32_t* totals, void* scratch,
+                       hipStream_t st) {
+  if (n_views <= 0 || n_per_view == 0) return 0;
+  // every view's workgroups: at most n / kRadixItems + 1 per view
+  const int64_t bcap = (n_cap + kRadixItems - 1) / kRadixItems + n_views;
+  uint32_t* table = static_cast<uint32_t*>(scratch);
+  uint4* binfo = reinterpret_cast<uint4*>(table + bcap * kRadix);
+  uint32_t* vfirst = reinterpret_cast<uint32_t*>(binfo + bcap);
+  hipLaunchKernelGGL(k_view_segments, dim3(1), dim3(1024), 0, st, vmask, n_wc, n_views, n_vis,
+                     vrange, binfo, bcap, vfirst, wsum, n_wsum, totals);
+  // first pass: the listed slots of each view, straight from the preprocess's arrays
+  const uint32_t nb1 = (n_per_view + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
+  const unsigned grid1 = (unsigned)n_views * nb1;  // at most bcap
+  hipLaunchKernelGGL(k_seg_hist<true>, dim3(grid1), dim3(kThreads), 0, st, dkey, vmask, n_wc,
+                     binfo, nb1, n_per_view, 0, table);
+  hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)n_views), dim3(kScanThreads), 0, st, vrange,
+                     binfo, vfirst, nb1, table);
+  hipLaunchKernelGGL(k_seg_scatter<true>, dim3(grid1), dim3(kThreads), 0, st, dkey, nullptr,
+                     vmask, n_wc, key[1], val[1], binfo, nb1, n_per_view, 0, table);
+  int cur = 1;
+  for (int shift = kRadixBits; shift < 32; shift += kRadixBits) {
+    hipLaunchKernelGGL(k_seg_hist<false>, dim3((unsigned)bcap), dim3(kThreads), 0, st, key[cur],
+                       nullptr, (int64_t)0, binfo, 0u, n_per_view, shift, table);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)n_views), dim3(kScanThreads), 0, st, vrange,
+                       binfo, vfirst, 0u, table);
+    hipLaunchKernelGGL(k_seg_scatter<false>, dim3((unsigned)bcap), dim3(kThreads), 0, st,
+                       key[cur], val[cur], nullptr, (int64_t)0, key[cur ^ 1], val[cur ^ 1], binfo,
+                       0u, n_per_view, shift, table);
     cur ^= 1;
   }
   return cur;
-}
-
-int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  return radix_sort_nt<uint32_t, kThreads, uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
-}
-
-int radix_sort(uint16_t* key[2], uint32_t* val[2], const uint32_t* n_dev, int64_t n_cap, int bits,
-               void* scratch, hipStream_t st) {
-  return radix_sort_nt<uint16_t, kThreads, uint32_t>(key, val, n_dev, n_cap, bits, scratch, st);
-}
-
-static int bits_of(int64_t n) {  // bits of keys below n
-  int b = 0;
-  while (b < 32 && ((int64_t)1 << b) < n) ++b;
-  return b;
-}
-
-int group_by_view(uint32_t* vkey[2], uint32_t* vval[2], int vb, const uint32_t* n_vis,
-                  int64_t n_cap, int n_views, uint32_t n_per_view, uint2* vrange, void* scratch,
-                  hipStream_t st) {
-  // keys go to the buffer that held the depth keys; the values start from the depth order
-  uint16_t* key[2] = {reinterpret_cast<uint16_t*>(vkey[vb]), reinterpret_cast<uint16_t*>(vkey[vb ^ 1])};
-  uint32_t* val[2] = {vval[vb], vval[vb ^ 1]};
-  if (n_cap > 0)
-    hipLaunchKernelGGL(k_view_keys, dim3((unsigned)((n_cap + 255) / 256)), dim3(256), 0, st,
-                       vval[vb], n_vis, n_cap, n_per_view, key[0]);
-  const int b = radix_sort(key, val, n_vis, n_cap, bits_of(n_views), scratch, st);
-  tile_ranges(key[b], n_vis, n_cap, n_views, vrange, st);
-  return b == 0 ? vb : vb ^ 1;
 }
 
 void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_t n_rows,
@@ -1216,26 +1295,6 @@ void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, in
   hipLaunchKernelGGL(k_expand_write, dim3(blocks), dim3(256), 0, st, rinfo, crow, chunk_cap,
                      counts, runs, hist, hist_cap, (uint32_t)std::min<int64_t>(pair_cap, 1 << 29),
                      pval, flag);
-}
-
-template <typename K>
-void tile_ranges_t(const K* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
-                   uint2* ranges, hipStream_t st) {
-  fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
-  const int64_t blocks = (pair_cap + 1023) / 1024;  // four keys per thread
-  if (blocks == 0) return;
-  hipLaunchKernelGGL(k_ranges<K>, dim3((unsigned)blocks), dim3(256), 0, st, pkey, n_pairs,
-                     pair_cap, n_tiles, ranges);
-}
-
-void tile_ranges(const uint32_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
-                 uint2* ranges, hipStream_t st) {
-  tile_ranges_t<uint32_t>(pkey, n_pairs, pair_cap, n_tiles, ranges, st);
-}
-
-void tile_ranges(const uint16_t* pkey, const uint32_t* n_pairs, int64_t pair_cap, int64_t n_tiles,
-                 uint2* ranges, hipStream_t st) {
-  tile_ranges_t<uint16_t>(pkey, n_pairs, pair_cap, n_tiles, ranges, st);
 }
 
 void tile_ids_of(const uint2* ranges, int64_t n_tiles, int64_t n, uint32_t* ids, hipStream_t st) {

@@ -290,7 +290,7 @@ class Renderer:
         if stages is None:
             mask = 0xFFFFFFFF
         else:
-            names = [B.lib().g4d_stage_name(k).decode() for k in range(B.G4D_NUM_STAGES)]
+            names = _stage_names()
             mask = 0
             for s in stages:
                 mask |= 1 << names.index(s)
@@ -298,13 +298,26 @@ class Renderer:
 
     def profile(self, enable: bool, collect: bool = True, reset: bool = True):
         """Stage timing (HIP events on the call's stream): returns {stage: (ms, launches)}."""
-        ms = (C.c_double * B.G4D_NUM_STAGES)()
-        n = (C.c_int64 * B.G4D_NUM_STAGES)()
+        # room for more stages than the header declares, so that a library built with more
+        # stages cannot write past the arrays
+        ms = (C.c_double * 64)()
+        n = (C.c_int64 * 64)()
         B.check(B.lib().g4d_profile(self._ctx, int(enable), ms if collect else None,
                                     n if collect else None, int(reset)), self._ctx)
         if not collect:
             return None
-        return {B.lib().g4d_stage_name(k).decode(): (ms[k], n[k]) for k in range(B.G4D_NUM_STAGES)}
+        return {name: (ms[k], n[k]) for k, name in enumerate(_stage_names())}
+
+
+def _stage_names():
+    """The library's stage names, in index order (it names no stage past the last)."""
+    names = []
+    while len(names) < 64:
+        name = B.lib().g4d_stage_name(len(names)).decode()
+        if not name:
+            break
+        names.append(name)
+    return names
 
 
 def _after_forward(r: Renderer, forward, backward, views) -> None:
