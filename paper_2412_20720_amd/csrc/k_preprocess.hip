@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
   const bool alive = live && fin;
   Geom g;
   geom_forward(qlr, qrr, sc4, g);
-  uint64_t n_pairs = 0, n_runs = 0;  // listed by this lane
+  uint32_t n_pairs = 0, n_runs = 0;  // listed by this lane, held at 2^31
   for (int v = 0; v < n_views; ++v) {
     const DView& V = views[v];
     const size_t slot = (size_t)v * n + gi;
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(256) void k_preprocess(
       // the tile rows of its box, first << 16 | last, for the row binning
       rowbox[slot] = cnt > 0 ? ((uint32_t)y0 << 16) | (uint32_t)y1 : ~0u;
     }
-    n_pairs += cnt;
-    n_runs += cnt > 0 ? (uint32_t)(y1 - y0 + 1) : 0u;
+    n_pairs = min(n_pairs + cnt, 0x80000000u);  // (cnt < 2^31: tile ids are below 2^31)
+    n_runs = min(n_runs + (cnt > 0 ? (uint32_t)(y1 - y0 + 1) : 0u), 0x80000000u);
     if (vmask) {
       const uint64_t listed = __ballot(cnt > 0);
       if (lane == 0) vmask[(size_t)v * n_wc + wave] = listed;
@@ -173,11 +173,9 @@ __global__ __launch_bounds__(256) void k_preprocess(
   }
   // the wave's pairs and runs (held at 2^31, which no valid total reaches)
   if (wsum) {
-    n_pairs = wave_sum_u64(n_pairs);
-    n_runs = wave_sum_u64(n_runs);
+    const uint64_t p = wave_sum_u64(n_pairs), q = wave_sum_u64(n_runs);
     if (lane == 0)
-      wsum[wave] = make_uint2((uint32_t)min(n_pairs, 0x80000000ull),
-                              (uint32_t)min(n_runs, 0x80000000ull));
+      wsum[wave] = make_uint2((uint32_t)min(p, 0x80000000ull), (uint32_t)min(q, 0x80000000ull));
   }
 }
 

@@ -216,118 +216,6 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 // inside a wave come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
 
-// Per view v: its listed slots' place [lo, hi) in the sorted list, from the preprocess's
-// listing masks per view and wave of 64 Gaussians, vmask[v * n_wc + wave] (lo = the listed
-// slots of the views before it); *n_vis = all of them; vfirst[v] = the view's first radix
-// workgroup of the later passes; per such workgroup b < bcap: binfo[b] = (first item, items,
-// the view's first workgroup, the view's workgroups), items = 0 past the last workgroup.  Also
-// adds up the preprocess's per-wave pair and run counts (see depth_sort_by_view).
-__global__ __launch_bounds__(1024) void k_view_segments(const uint64_t* __restrict__ vmask,
-                                                        int64_t n_wc, int n_views,
-                                                        uint32_t* n_vis,
-                                                        uint2* __restrict__ vrange,
-                                                        uint4* __restrict__ binfo, int64_t bcap,
-                                                        uint32_t* __restrict__ vfirst,
-                                                        const uint2* __restrict__ wsum,
-                                                        int64_t n_wsum, uint32_t* totals) {
-  __shared__ uint32_t s_len[G4D_MAX_VIEWS], s_lo[G4D_MAX_VIEWS], s_fb[G4D_MAX_VIEWS];
-  __shared__ uint32_t s_w[16], s_n[16];
-  __shared__ uint64_t s_p[16], s_r[16];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wsum) {
-    uint64_t p = 0, r = 0;
-    for (int64_t i = threadIdx.x; i < n_wsum; i += 4 * 1024) {
-      uint2 c[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        c[u] = i + u * 1024 < n_wsum ? wsum[i + u * 1024] : make_uint2(0u, 0u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        p += c[u].x;
-        r += c[u].y;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      p += ((uint64_t)__shfl_xor((uint32_t)(p >> 32), o, 64) << 32) | __shfl_xor((uint32_t)p, o, 64);
-      r += ((uint64_t)__shfl_xor((uint32_t)(r >> 32), o, 64) << 32) | __shfl_xor((uint32_t)r, o, 64);
-    }
-    if (lane == 0) {
-      s_p[w] = p;
-      s_r[w] = r;
-    }
-  }
-  // listed slots per view: a wave per view, four 16-byte loads (eight masks) in flight per lane
-  // (n_wc is a multiple of 4, so each view's masks start 32-byte aligned)
-  for (int v = w; v < n_views; v += 16) {
-    const ulonglong2* c = reinterpret_cast<const ulonglong2*>(vmask + (size_t)v * (size_t)n_wc);
-    const int64_t n2 = n_wc / 2;
-    uint32_t t = 0;
-    for (int64_t i = lane; i < n2; i += 4 * 64) {
-      ulonglong2 m[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) m[u] = i + u * 64 < n2 ? c[i + u * 64] : make_ulonglong2(0, 0);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) t += (uint32_t)(__popcll(m[u].x) + __popcll(m[u].y));
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if (lane == 0) s_len[v] = t;
-  }
-  __syncthreads();
-  if (wsum && threadIdx.x == 0) {
-    uint64_t p = 0, r = 0;
-    for (int k = 0; k < 16; ++k) {
-      p += s_p[k];
-      r += s_r[k];
-    }
-    totals[0] = (uint32_t)min(p, (uint64_t)UINT32_MAX);
-    totals[2] = (uint32_t)min(r, (uint64_t)UINT32_MAX);
-    totals[4] = (p >= 0x80000000ull || r >= 0x80000000ull) ? 1u : 0u;
-  }
-  const int v = threadIdx.x;
-  uint32_t len = 0, nb = 0;
-  if (v < n_views) {
-    len = s_len[v];
-    nb = (len + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
-  }
-  const uint32_t inc = wave_incl_scan(nb), inc_n = wave_incl_scan(len);
-  if (lane == 63) {
-    s_w[w] = inc;
-    s_n[w] = inc_n;
-  }
-  __syncthreads();
-  uint32_t pre = 0, total = 0, pre_n = 0, total_n = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    pre += (k < w) ? s_w[k] : 0u;
-    total += s_w[k];
-    pre_n += (k < w) ? s_n[k] : 0u;
-    total_n += s_n[k];
-  }
-  if (v < n_views) {
-    const uint32_t lo = pre_n + inc_n - len;
-    vrange[v] = make_uint2(lo, lo + len);
-    s_lo[v] = lo;
-    s_fb[v] = pre + inc - nb;
-    vfirst[v] = pre + inc - nb;
-  }
-  if (threadIdx.x == 0) *n_vis = total_n;
-  __syncthreads();
-  for (int u = w; u < n_views; u += 16) {
-    const uint32_t ulo = s_lo[u], ulen = s_len[u], fb = s_fb[u];
-    const uint32_t unb = (ulen + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
-    for (uint32_t j = (uint32_t)lane; j < unb; j += 64) {
-      const uint32_t first = j * (uint32_t)kRadixItems;
-      if ((int64_t)(fb + j) < bcap)
-        binfo[fb + j] = make_uint4(ulo + first, min((uint32_t)kRadixItems, ulen - first), fb,
-                                   unb);
-    }
-  }
-  for (int64_t b = (int64_t)total + threadIdx.x; b < bcap; b += 1024)
-    binfo[b] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 // The items of a radix workgroup.  The first pass reads the preprocess's arrays themselves:
 // workgroup b covers kRadixItems slots of view b / nb1, its items the listed ones (key = the
 // depth key, value = the slot), found from the listing masks: vmask[view * n_wc + c] has bit l
@@ -359,16 +247,19 @@ struct SegItems {
 };
 
 // Digit counts of one workgroup's items: table[256 b + d] for workgroup b and digit d.
+// In the first pass also bcount[b] = the workgroup's listed slots.
 template <bool FIRST>
 __global__ __launch_bounds__(kThreads) void k_seg_hist(const uint32_t* __restrict__ key,
                                                        const uint64_t* __restrict__ vmask,
                                                        int64_t n_wc,
                                                        const uint4* __restrict__ binfo,
                                                        uint32_t nb1, uint32_t n_per_view,
-                                                       int shift, uint32_t* __restrict__ table) {
+                                                       int shift, uint32_t* __restrict__ table,
+                                                       uint32_t* __restrict__ bcount) {
   constexpr int NW = kThreads / 64;
   static_assert(kThreads == kRadix, "one thread per digit");
   __shared__ uint32_t wh[NW][kRadix];
+  __shared__ uint32_t s_tot[NW];
   SegItems it;
   if (!it.load(FIRST, binfo, nb1, n_per_view)) return;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -390,25 +281,29 @@ __global__ __launch_bounds__(kThreads) void k_seg_hist(const uint32_t* __restric
 #pragma unroll
   for (int k = 0; k < NW; ++k) t += wh[k][d];
   table[(uint32_t)kRadix * blockIdx.x + (uint32_t)d] = t;
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) s_tot[w] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t n = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) n += s_tot[k];
+      bcount[blockIdx.x] = n;
+    }
+  }
 }
 
-// One workgroup per view turns the view's counts into scatter offsets: each digit's total over
-// the view's workgroups, an exclusive scan over the digits from the view's first place in the
-// sorted list, and per workgroup the counts of the digit in the view's earlier ones.  Four
-// threads per digit, each over a quarter of the view's workgroups with eight loads in flight.
-// The first pass's workgroups: nb1 per view (nb1 > 0).
+// A view's digit counts (its nb workgroups from fb, table[256 b + d]) become scatter offsets:
+// each digit's total over the workgroups, an exclusive scan over the digits from `start` (the
+// view's first place in the sorted list), and per workgroup the counts of the digit in the
+// view's earlier ones.  A workgroup of four threads per digit, each over a quarter of the
+// workgroups with eight loads in flight; every thread of the workgroup calls it.
 constexpr int kScanThreads = 4 * kRadix;
-__global__ __launch_bounds__(kScanThreads) void k_seg_scan(const uint2* __restrict__ vrange,
-                                                           const uint4* __restrict__ binfo,
-                                                           const uint32_t* __restrict__ vfirst,
-                                                           uint32_t nb1,
-                                                           uint32_t* __restrict__ table) {
+__device__ void view_digit_scan(uint32_t* __restrict__ table, uint32_t fb, uint32_t nb,
+                                uint32_t start) {
   __shared__ uint32_t s_part[4][kRadix], s_base[kRadix], lds4[4];
-  const uint32_t v = blockIdx.x;
-  const uint2 r = vrange[v];
-  if (r.y == r.x) return;
-  const uint32_t fb = nb1 ? v * nb1 : vfirst[v];
-  const uint32_t nb = nb1 ? nb1 : binfo[fb].w;
   const int d = threadIdx.x & (kRadix - 1), q = threadIdx.x / kRadix;
   const uint32_t per = (nb + 3u) / 4u;
   const uint32_t j0 = min((uint32_t)q * per, nb), j1 = min(j0 + per, nb);
@@ -434,7 +329,7 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const uint2* __restri
     uint32_t pre = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) pre += (k < (d >> 6)) ? lds4[k] : 0u;
-    s_base[d] = r.x + pre + inc - tot;
+    s_base[d] = start + pre + inc - tot;
   }
   __syncthreads();
   uint32_t run = s_base[d];
@@ -450,6 +345,114 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_scan(const uint2* __restri
         run += c[u];
       }
   }
+}
+
+// Later passes: one workgroup per view, its workgroups from vfirst / binfo.
+__global__ __launch_bounds__(kScanThreads) void k_seg_scan(const uint2* __restrict__ vrange,
+                                                           const uint4* __restrict__ binfo,
+                                                           const uint32_t* __restrict__ vfirst,
+                                                           uint32_t* __restrict__ table) {
+  const uint32_t v = blockIdx.x;
+  const uint2 r = vrange[v];
+  if (r.y == r.x) return;
+  const uint32_t fb = vfirst[v];
+  view_digit_scan(table, fb, binfo[fb].w, r.x);
+}
+
+// First pass, one workgroup per view v: the listed slots of the views up to v from the first
+// histogram's per-workgroup counts (bcount, nb1 workgroups per view) give the view's place
+// [lo, lo + len) in the sorted list (lo = the listed slots of the views before it, written to
+// vrange[v]) and its workgroups of the later passes (vfirst[v]; binfo[b] = (first item, items,
+// the view's first workgroup, the view's workgroups)).  The last view also writes *n_vis and
+// clears binfo past the last workgroup (items = 0, up to bcap); the first adds up the
+// preprocess's per-wave pair and run counts (see depth_sort_by_view).  Then the view's
+// first-pass counts become scatter offsets.
+__global__ __launch_bounds__(kScanThreads) void k_first_scan(
+    const uint32_t* __restrict__ bcount, uint32_t nb1, int n_views, uint32_t* n_vis,
+    uint2* __restrict__ vrange, uint32_t* __restrict__ vfirst, uint4* __restrict__ binfo,
+    int64_t bcap, const uint2* __restrict__ wsum, int64_t n_wsum, uint32_t* totals,
+    uint32_t* __restrict__ table) {
+  __shared__ uint32_t s_len[G4D_MAX_VIEWS], s_a[16], s_b[16];
+  __shared__ uint64_t s_p[16], s_r[16];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t v = blockIdx.x;
+  for (int u = w; u <= (int)v; u += 16) {  // a wave per view
+    const uint32_t* c = bcount + (size_t)u * nb1;
+    uint32_t t = 0;
+    for (uint32_t j = (uint32_t)lane; j < nb1; j += 64) t += c[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) s_len[u] = t;
+  }
+  const bool sums = v == 0 && wsum;
+  if (sums) {
+    uint64_t p = 0, r = 0;
+    for (int64_t i = threadIdx.x; i < n_wsum; i += kScanThreads) {
+      const uint2 c = wsum[i];
+      p += c.x;
+      r += c.y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      p += ((uint64_t)__shfl_xor((uint32_t)(p >> 32), o, 64) << 32) | __shfl_xor((uint32_t)p, o, 64);
+      r += ((uint64_t)__shfl_xor((uint32_t)(r >> 32), o, 64) << 32) | __shfl_xor((uint32_t)r, o, 64);
+    }
+    if (lane == 0) {
+      s_p[w] = p;
+      s_r[w] = r;
+    }
+  }
+  __syncthreads();
+  // lo and the first workgroup: sums over the views before v (a thread per view)
+  uint32_t a = 0, b = 0;
+  if (threadIdx.x < v) {
+    a = s_len[threadIdx.x];
+    b = (a + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (lane == 0) {
+    s_a[w] = a;
+    s_b[w] = b;
+  }
+  __syncthreads();
+  uint32_t lo = 0, fb = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    lo += s_a[k];
+    fb += s_b[k];
+  }
+  const uint32_t len = s_len[v];
+  const uint32_t nb = (len + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
+  if (threadIdx.x == 0) {
+    vrange[v] = make_uint2(lo, lo + len);
+    vfirst[v] = fb;
+  }
+  for (uint32_t j = threadIdx.x; j < nb; j += kScanThreads) {
+    const uint32_t first = j * (uint32_t)kRadixItems;
+    if ((int64_t)(fb + j) < bcap)
+      binfo[fb + j] = make_uint4(lo + first, min((uint32_t)kRadixItems, len - first), fb, nb);
+  }
+  if (v == (uint32_t)n_views - 1u) {
+    if (threadIdx.x == 0) *n_vis = lo + len;
+    for (int64_t k = (int64_t)(fb + nb) + threadIdx.x; k < bcap; k += kScanThreads)
+      binfo[k] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  if (sums && threadIdx.x == 0) {
+    uint64_t p = 0, r = 0;
+    for (int k = 0; k < 16; ++k) {
+      p += s_p[k];
+      r += s_r[k];
+    }
+    totals[0] = (uint32_t)min(p, (uint64_t)UINT32_MAX);
+    totals[2] = (uint32_t)min(r, (uint64_t)UINT32_MAX);
+    totals[4] = (p >= 0x80000000ull || r >= 0x80000000ull) ? 1u : 0u;
+  }
+  if (len == 0) return;
+  view_digit_scan(table, v * nb1, nb1, lo);
 }
 
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid) {
@@ -604,15 +607,17 @@ __device__ __forceinline__ uint32_t box_rows(uint32_t rb) {
   return rb == ~0u ? 0u : (rb & 0xFFFFu) - (rb >> 16) + 1u;
 }
 
-// Per view v (one workgroup of 256 threads, a thread per view): its splats [lo, lo + len) in
-// the regrouped list, its chunks of 64 splats, the index of its first chunk, and the base of
+// Per view v (one workgroup of 1024 threads, a thread per view): its splats [lo, lo + len) in
+// the depth-sorted list, its chunks of 64 splats, the index of its first chunk, and the base of
 // its (row, chunk) count table: vinfo[2v] = (lo, len, first chunk, table base),
-// vinfo[2v + 1] = (chunks, tiles_y, row_base, 0).  totals = (chunks, table entries).
-__global__ __launch_bounds__(256) void k_view_table(const uint2* __restrict__ vrange, int n_views,
-                                                    const DView* __restrict__ views,
-                                                    uint4* __restrict__ vinfo, uint32_t rhist_cap,
-                                                    uint32_t* totals) {
-  __shared__ uint32_t s_c[4], s_h[4];
+// vinfo[2v + 1] = (chunks, tiles_y, row_base, 0); totals = (chunks, table entries); then
+// cview[chunk] = its view for every chunk below chunk_cap (a wave per view).
+__global__ __launch_bounds__(1024) void k_view_table(const uint2* __restrict__ vrange, int n_views,
+                                                     const DView* __restrict__ views,
+                                                     uint4* __restrict__ vinfo, uint32_t rhist_cap,
+                                                     uint32_t* totals, int64_t chunk_cap,
+                                                     uint16_t* __restrict__ cview) {
+  __shared__ uint32_t s_c[16], s_h[16], s_first[G4D_MAX_VIEWS], s_nch[G4D_MAX_VIEWS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int v = threadIdx.x;
   uint32_t lo = 0, len = 0, nch = 0, ny = 0, rb = 0;
@@ -631,30 +636,31 @@ __global__ __launch_bounds__(256) void k_view_table(const uint2* __restrict__ vr
     s_h[w] = ih;
   }
   __syncthreads();
-  uint32_t pc = 0, ph = 0;
-  for (int k = 0; k < w; ++k) {
-    pc += s_c[k];
-    ph += s_h[k];
+  uint32_t pc = 0, ph = 0, tc = 0, th = 0;
+  for (int k = 0; k < 16; ++k) {
+    pc += (k < w) ? s_c[k] : 0u;
+    ph += (k < w) ? s_h[k] : 0u;
+    tc += s_c[k];
+    th += s_h[k];
   }
   if (v < n_views) {
     vinfo[2 * v] = make_uint4(lo, len, pc + ic - nch, ph + ih - hs);
     vinfo[2 * v + 1] = make_uint4(nch, ny, rb, 0u);
+    s_first[v] = pc + ic - nch;
+    s_nch[v] = nch;
   }
   if (threadIdx.x == 0) {
-    totals[0] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    totals[0] = tc;
     // (the table capacity covers every view's chunks; the clamp only keeps a broken count
     // from taking the scan past it)
-    totals[1] = min(s_h[0] + s_h[1] + s_h[2] + s_h[3], rhist_cap);
+    totals[1] = min(th, rhist_cap);
   }
-}
-
-// cview[chunk] = its view (one workgroup per view).
-__global__ void k_chunk_views(const uint4* __restrict__ vinfo, int64_t chunk_cap,
-                              uint16_t* __restrict__ cview) {
-  const uint32_t v = blockIdx.x;
-  const uint32_t first = vinfo[2 * v].z, nch = vinfo[2 * v + 1].x;
-  for (uint32_t k = threadIdx.x; k < nch && (int64_t)(first + k) < chunk_cap; k += blockDim.x)
-    cview[first + k] = (uint16_t)v;
+  __syncthreads();
+  for (int u = w; u < n_views; u += 16) {
+    const uint32_t first = s_first[u], n = s_nch[u];
+    for (uint32_t k = (uint32_t)lane; k < n && (int64_t)(first + k) < chunk_cap; k += 64)
+      cview[first + k] = (uint16_t)u;
+  }
 }
 
 // A chunk of a view's splats: the view's table entries, the chunk within the view, and per
@@ -1202,7 +1208,7 @@ size_t scan_scratch_bytes(int64_t n) {
 size_t depth_sort_scratch_bytes(int64_t n_cap, int n_views) {
   const int64_t bcap = (n_cap + kRadixItems - 1) / kRadixItems + n_views;
   return sizeof(uint32_t) * (size_t)(bcap * kRadix) + sizeof(uint4) * (size_t)bcap +
-         sizeof(uint32_t) * (size_t)G4D_MAX_VIEWS;
+         sizeof(uint32_t) * (size_t)(G4D_MAX_VIEWS + bcap);
 }
 
 int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc, uint32_t* key[2], uint32_t* val[2], uint32_t* n_vis,
@@ -1215,23 +1221,24 @@ int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc
   uint32_t* table = static_cast<uint32_t*>(scratch);
   uint4* binfo = reinterpret_cast<uint4*>(table + bcap * kRadix);
   uint32_t* vfirst = reinterpret_cast<uint32_t*>(binfo + bcap);
-  hipLaunchKernelGGL(k_view_segments, dim3(1), dim3(1024), 0, st, vmask, n_wc, n_views, n_vis,
-                     vrange, binfo, bcap, vfirst, wsum, n_wsum, totals);
-  // first pass: the listed slots of each view, straight from the preprocess's arrays
+  uint32_t* bcount = vfirst + G4D_MAX_VIEWS;
+  // first pass: the listed slots of each view, straight from the preprocess's arrays; its scan
+  // also places the views and lays out the later passes' workgroups
   const uint32_t nb1 = (n_per_view + (uint32_t)kRadixItems - 1u) / (uint32_t)kRadixItems;
   const unsigned grid1 = (unsigned)n_views * nb1;  // at most bcap
   hipLaunchKernelGGL(k_seg_hist<true>, dim3(grid1), dim3(kThreads), 0, st, dkey, vmask, n_wc,
-                     binfo, nb1, n_per_view, 0, table);
-  hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)n_views), dim3(kScanThreads), 0, st, vrange,
-                     binfo, vfirst, nb1, table);
+                     binfo, nb1, n_per_view, 0, table, bcount);
+  hipLaunchKernelGGL(k_first_scan, dim3((unsigned)n_views), dim3(kScanThreads), 0, st, bcount,
+                     nb1, n_views, n_vis, vrange, vfirst, binfo, bcap, wsum, n_wsum, totals,
+                     table);
   hipLaunchKernelGGL(k_seg_scatter<true>, dim3(grid1), dim3(kThreads), 0, st, dkey, nullptr,
                      vmask, n_wc, key[1], val[1], binfo, nb1, n_per_view, 0, table);
   int cur = 1;
   for (int shift = kRadixBits; shift < 32; shift += kRadixBits) {
     hipLaunchKernelGGL(k_seg_hist<false>, dim3((unsigned)bcap), dim3(kThreads), 0, st, key[cur],
-                       nullptr, (int64_t)0, binfo, 0u, n_per_view, shift, table);
+                       nullptr, (int64_t)0, binfo, 0u, n_per_view, shift, table, nullptr);
     hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)n_views), dim3(kScanThreads), 0, st, vrange,
-                       binfo, vfirst, 0u, table);
+                       binfo, vfirst, table);
     hipLaunchKernelGGL(k_seg_scatter<false>, dim3((unsigned)bcap), dim3(kThreads), 0, st,
                        key[cur], val[cur], nullptr, (int64_t)0, key[cur ^ 1], val[cur ^ 1], binfo,
                        0u, n_per_view, shift, table);
@@ -1246,10 +1253,8 @@ void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_
                     uint4* vinfo, uint16_t* cview, uint32_t* rhist, uint32_t* counts, uint2* runs,
                     uint2* rrange, uint32_t* flag, void* scratch, hipStream_t st) {
   // counts: [0] chunks, [1] table entries, [2] runs laid down
-  hipLaunchKernelGGL(k_view_table, dim3(1), dim3(256), 0, st, vrange, n_views, views, vinfo,
-                     (uint32_t)std::min<int64_t>(rhist_cap, UINT32_MAX), counts);
-  hipLaunchKernelGGL(k_chunk_views, dim3((unsigned)n_views), dim3(256), 0, st, vinfo, chunk_cap,
-                     cview);
+  hipLaunchKernelGGL(k_view_table, dim3(1), dim3(1024), 0, st, vrange, n_views, views, vinfo,
+                     (uint32_t)std::min<int64_t>(rhist_cap, UINT32_MAX), counts, chunk_cap, cview);
   const int64_t blocks = (chunk_cap + 3) / 4;
   if (blocks > 0)
     hipLaunchKernelGGL(k_rows_count, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
