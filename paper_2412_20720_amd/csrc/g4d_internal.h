@@ -38,27 +38,44 @@ int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc
 
 // The runs of every view's splats (vval grouped by view, depth order within a view), grouped
 // by global tile row with each row's runs in depth order: runs = (slot, span) with span =
-// (first column << 16) | last column, or ~0u for a row the ellipse misses; rrange = each
-// row's [first, end) ((0, 0) if empty).  chunk_cap >= visible / 64 + n_views and rhist_cap >=
-// max tiles_y * chunk_cap bound the chunk grid and the count table; rowbox = each slot's tile
+// (first column << 16) | last column, or ~0u for a row the ellipse misses; each row's range
+// follows from the scanned count table (RowRuns).  chunk_cap >= visible / 64 + n_views and rhist_cap >=
+// max_tiles_y * chunk_cap bound the chunk grid and the count table (max_tiles_y: the largest
+// view's tile rows; the table's scan covers max_tiles_y * chunk_cap entries); rowbox = each slot's tile
 // rows (first << 16 | last, ~0u: none); vinfo holds 2 n_views entries, cview chunk_cap; counts
-// (3 words) receive the chunks, the table entries and the runs laid down.
-// More runs than row_cap set *flag = 1, a total other than *n_runs *flag = 2.
-void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_t n_rows,
-                    const uint32_t* vval, const uint32_t* rowbox, const float* rec, DSettings S,
-                    int64_t chunk_cap, int64_t rhist_cap, int64_t row_cap, const uint32_t* n_runs,
-                    uint4* vinfo, uint16_t* cview, uint32_t* rhist, uint32_t* counts, uint2* runs,
-                    uint2* rrange, uint32_t* flag, void* scratch, hipStream_t st);
+// (3 words) receive the chunks, the table entries and the runs laid down.  Runs past row_cap
+// are not written and set *flag = 1.
+void splats_to_rows(const uint2* vrange, int n_views, const DView* views,
+                    int64_t max_tiles_y, const uint32_t* vval, const uint32_t* rowbox,
+                    const float* rec, DSettings S, int64_t chunk_cap, int64_t rhist_cap,
+                    int64_t row_cap, uint4* vinfo, uint16_t* cview, uint32_t* rhist,
+                    uint32_t* counts, uint2* runs, uint32_t* flag, void* scratch,
+                    hipStream_t st);
 
-// Expansion of the row-grouped runs into the tile lists: rrange = each tile row's runs
-// (runs = their (slot, span)), pval = every tile's slots in depth order,
+// Where the runs of each tile row lie after splats_to_rows: its view table, the scanned count
+// table, the device counts of table entries and runs laid down (its counts[1], counts[2]), the
+// runs the preprocess counted, and the run capacity.
+struct RowRuns {
+  const uint4* vinfo;
+  const uint32_t* scanned;
+  const uint32_t* n_hist;
+  const uint32_t* total;
+  const uint32_t* n_runs;
+  uint32_t row_cap;
+};
+
+// Expansion of the row-grouped runs into the tile lists: rr = where each tile row's runs lie
+// (runs = their (slot, span); a run total past the run capacity sets *flag = 1, one other
+// than the preprocess's count *flag = 2), pval = every tile's slots in depth order,
 // ranges = [first, end) per tile ((0, 0) if empty).  chunk_cap >= runs / 64 + n_rows and
-// hist_cap >= max tiles_x * ceil(runs / 64) + n_tiles bound the chunk grid and the count
-// table; rinfo holds 2 n_rows entries, crow 8 chunk_cap (a chunk list per XCD); counts (10
+// hist_cap >= max_tiles_x * ceil(runs / 64) + n_tiles bound the chunk grid and the count
+// table (max_tiles_x: the largest view's tile columns; the table's scan covers at most
+// max_tiles_x * chunk_cap entries); rinfo holds 2 n_rows entries, crow 8 chunk_cap (a chunk list per XCD); counts (10
 // words) receive the chunks of each XCD, the table entries and the pairs written.  A pair count
 // other than *n_pairs sets *flag = 2 (unless set).
-void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,
-            const uint2* runs, int64_t chunk_cap, int64_t hist_cap, int64_t pair_cap,
+void expand(const RowRuns& rr, int n_rows, const DView* views, int n_views, int64_t n_tiles,
+            int64_t max_tiles_x, const uint2* runs, int64_t chunk_cap, int64_t hist_cap,
+            int64_t pair_cap,
             const uint32_t* n_pairs, uint4* rinfo,
             uint32_t* crow, uint32_t* hist, uint32_t* counts, uint32_t* pval, uint2* ranges,
             uint32_t* flag, void* scratch, hipStream_t st);

@@ -74,7 +74,7 @@ struct g4d_ctx {
   int device = 0;
   std::string err;
   DevBuf views, tile_base, rec, tiles, rowbox, dkey, wsum, vmask, vk[2], vv[2], vrange, vinfo, cview,
-      rhist, runs, rrange, rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last,
+      rhist, runs, rinfo, crow, hist, pval, scan_tmp, sort_tmp, ranges, px_T, px_last,
       px_evals, grad2d, counters;
   DevBuf fn, fnorm, flow, dfn;     // extra channels
   DevBuf skybg;                    // per-pixel sky background
@@ -516,7 +516,7 @@ g4d_status g4d_destroy(g4d_ctx* ctx) {
   DevBuf* bufs[] = {&ctx->views, &ctx->tile_base, &ctx->rec, &ctx->tiles, &ctx->rowbox, &ctx->dkey,
                     &ctx->wsum, &ctx->vmask,
                     &ctx->vk[0], &ctx->vk[1], &ctx->vv[0], &ctx->vv[1], &ctx->vrange,
-                    &ctx->vinfo, &ctx->cview, &ctx->rhist, &ctx->runs, &ctx->rrange,
+                    &ctx->vinfo, &ctx->cview, &ctx->rhist, &ctx->runs,
                     &ctx->rinfo, &ctx->crow, &ctx->hist, &ctx->pval,
                     &ctx->scan_tmp,
                     &ctx->sort_tmp, &ctx->ranges, &ctx->px_T, &ctx->px_last, &ctx->px_evals,
@@ -598,7 +598,6 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
   if ((r = ensure(ctx, ctx->px_T, sizeof(float) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->px_last, sizeof(int32_t) * ctx->n_pixels, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->ranges, sizeof(uint2) * ctx->n_tiles, 1.1)) != G4D_OK) return r;
-  if ((r = ensure(ctx, ctx->rrange, sizeof(uint2) * ctx->n_rows, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->rinfo, 2 * sizeof(uint4) * ctx->n_rows, 1.1)) != G4D_OK) return r;
   if (ctx->count_evals &&
       (r = ensure(ctx, ctx->px_evals, sizeof(uint32_t) * ctx->n_pixels, 1.1)) != G4D_OK)
@@ -656,11 +655,11 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     G4D_HIP(hipGetLastError());
     auto run_rows = [&]() {
       Stage t(ctx, 2, st);
-      splats_to_rows(P<uint2>(ctx->vrange), n_views, P<DView>(ctx->views), ctx->n_rows, vv[vb],
-                     P<uint32_t>(ctx->rowbox), P<float>(ctx->rec), DS, row_chunks,
-                     ctx->rhist_cap, ctx->row_cap, cnt + 3, P<uint4>(ctx->vinfo),
+      splats_to_rows(P<uint2>(ctx->vrange), n_views, P<DView>(ctx->views), ctx->max_tiles_y,
+                     vv[vb], P<uint32_t>(ctx->rowbox), P<float>(ctx->rec), DS, row_chunks,
+                     ctx->rhist_cap, ctx->row_cap, P<uint4>(ctx->vinfo),
                      P<uint16_t>(ctx->cview), P<uint32_t>(ctx->rhist), cnt + 16,
-                     P<uint2>(ctx->runs), P<uint2>(ctx->rrange), cnt + 2, ctx->scan_tmp.p, st);
+                     P<uint2>(ctx->runs), cnt + 2, ctx->scan_tmp.p, st);
     };
     if (ctx->capturing) {
       // counts stay on the device; grids cover the capacities
@@ -701,8 +700,10 @@ static g4d_status forward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_v
     if (run_grid > 0) {
       {
         Stage t(ctx, 3, st);
-        expand(P<uint2>(ctx->rrange), (int)ctx->n_rows, P<DView>(ctx->views), n_views,
-               ctx->n_tiles, P<uint2>(ctx->runs), (run_grid + 63) / 64 + ctx->n_rows,
+        const RowRuns rr{P<uint4>(ctx->vinfo), P<uint32_t>(ctx->rhist), cnt + 17, cnt + 18,
+                         cnt + 3, (uint32_t)std::min<int64_t>(ctx->row_cap, UINT32_MAX)};
+        expand(rr, (int)ctx->n_rows, P<DView>(ctx->views), n_views,
+               ctx->n_tiles, ctx->max_tiles_x, P<uint2>(ctx->runs), (run_grid + 63) / 64 + ctx->n_rows,
                ctx->hist_cap, ctx->pair_cap, cnt + 1, P<uint4>(ctx->rinfo), P<uint32_t>(ctx->crow),
                P<uint32_t>(ctx->hist), cnt + 6, P<uint32_t>(ctx->pval), P<uint2>(ctx->ranges),
                cnt + 2, ctx->scan_tmp.p, st);
@@ -1098,7 +1099,6 @@ static g4d_status carve_scratch(g4d_ctx* ctx, g4d_ctx* na, unsigned char* base, 
   take(na->cview, sizeof(uint16_t) * ((slots + 63) / 64 + n_views));
   take(na->rhist, sizeof(uint32_t) * rhist);
   take(na->ranges, sizeof(uint2) * n_tiles);
-  take(na->rrange, sizeof(uint2) * n_rows);
   take(na->rinfo, 2 * sizeof(uint4) * n_rows);
   take(na->px_T, sizeof(float) * n_pixels);
   take(na->px_last, sizeof(int32_t) * n_pixels);

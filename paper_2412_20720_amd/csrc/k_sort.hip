@@ -741,38 +741,22 @@ __global__ __launch_bounds__(256) void k_rows_count(const uint4* __restrict__ vi
   }
 }
 
-// Row ranges from the scanned table: rrange[global row] = [start of (row, chunk 0), start of
-// the next row), clamped to the run capacity; an empty row gets (0, 0).
-__global__ void k_row_ranges(const uint4* __restrict__ vinfo, const DView* __restrict__ views,
-                             int n_views, const uint32_t* __restrict__ scanned,
-                             const uint32_t* n_hist_dev, const uint32_t* total_dev,
-                             const uint32_t* n_runs_dev, int64_t n_rows, uint32_t row_cap,
-                             uint2* __restrict__ rrange, uint32_t* flag) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_rows) return;
-  // the preprocess counted the rows the expansion lays down; more than the run arrays hold is
-  // a capacity overflow, any other disagreement a mismatch
-  if (r == 0) {
-    if (*total_dev > row_cap) *flag = 1u;
-    else if (*total_dev != *n_runs_dev && *flag == 0u) *flag = 2u;
-  }
-  int a = 0, b = n_views - 1;  // the last view whose rows start at or before r
-  while (a < b) {
-    const int m = (a + b + 1) >> 1;
-    if (views[m].row_base <= r) a = m; else b = m - 1;
-  }
-  const uint4 va = vinfo[2 * a], vb = vinfo[2 * a + 1];
+// Runs of global tile row r (in view a) from the scanned (row, chunk) table: [start of (row,
+// chunk 0), start of the next row), clamped to the run capacity; an empty row gets (0, 0).
+__device__ __forceinline__ uint2 row_range(const RowRuns& rr, const DView* __restrict__ views,
+                                           int a, int r) {
+  const uint4 va = rr.vinfo[2 * a], vb = rr.vinfo[2 * a + 1];
   const uint32_t ty = (uint32_t)(r - views[a].row_base), nch = vb.x;
   uint32_t lo = 0, hi = 0;
   if (nch > 0) {
-    const uint32_t n_hist = *n_hist_dev;
+    const uint32_t n_hist = *rr.n_hist, total = *rr.total;
     const uint32_t i0 = va.w + ty * nch, i1 = i0 + nch;
-    lo = i0 < n_hist ? scanned[i0] : *total_dev;
-    hi = i1 < n_hist ? scanned[i1] : *total_dev;
-    lo = min(lo, row_cap);
-    hi = min(hi, row_cap);
+    lo = i0 < n_hist ? rr.scanned[i0] : total;
+    hi = i1 < n_hist ? rr.scanned[i1] : total;
+    lo = min(lo, rr.row_cap);
+    hi = min(hi, rr.row_cap);
   }
-  rrange[r] = hi > lo ? make_uint2(lo, hi) : make_uint2(0u, 0u);
+  return hi > lo ? make_uint2(lo, hi) : make_uint2(0u, 0u);
 }
 
 // Position of the r-th set bit of m (r < popcount(m)).
@@ -906,17 +890,24 @@ __global__ __launch_bounds__(256) void k_rows_write(const uint4* __restrict__ vi
 constexpr int kXcds = 8;
 
 // Per tile row r (one workgroup walks all rows): its runs [lo, lo + len) in the sorted run
-// list, its chunks of 64 runs and the index of its first chunk among the chunks of its XCD,
-// and the base of its (column, chunk) count table: rinfo[2r] = (lo, len, first chunk, table
-// base), rinfo[2r + 1] = (chunks, tiles_x, first tile id, 0).  totals = (chunks of XCD 0..7,
-// table entries).
-__global__ __launch_bounds__(1024) void k_row_table(const uint2* __restrict__ rrange, int n_rows,
+// list (row_range), its chunks of 64 runs and the index of its first chunk among the chunks of
+// its XCD, and the base of its (column, chunk) count table: rinfo[2r] = (lo, len, first
+// chunk, table base), rinfo[2r + 1] = (chunks, tiles_x, first tile id, 0).  totals = (chunks
+// of XCD 0..7, table entries).  The preprocess counted the runs the splats -> rows pass lays
+// down: more than the run arrays hold sets *flag = 1 (a capacity overflow), any other
+// disagreement *flag = 2 (unless set).
+__global__ __launch_bounds__(1024) void k_row_table(RowRuns rr, int n_rows,
                                                     const DView* __restrict__ views, int n_views,
                                                     uint4* __restrict__ rinfo, uint32_t hist_cap,
-                                                    uint32_t* totals) {
+                                                    uint32_t* totals, uint32_t* flag) {
   __shared__ uint32_t s_c[16][kXcds], s_h[16];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int x = threadIdx.x % kXcds;  // every 1024-row group starts at a multiple of 8
+  if (threadIdx.x == 0) {
+    const uint32_t total = *rr.total;
+    if (total > rr.row_cap) *flag = 1u;
+    else if (total != *rr.n_runs && *flag == 0u) *flag = 2u;
+  }
   uint32_t carry_c = 0, carry_h = 0;
   for (int base = 0; base < n_rows; base += 1024) {
     const int r = base + threadIdx.x;
@@ -930,7 +921,7 @@ __global__ __launch_bounds__(1024) void k_row_table(const uint2* __restrict__ rr
       const DView& V = views[a];
       nx = (uint32_t)V.tiles_x;
       tile0 = (uint32_t)(V.tile_base + (r - V.row_base) * V.tiles_x);
-      const uint2 g = rrange[r];
+      const uint2 g = row_range(rr, views, a, r);
       lo = g.x;
       len = g.y - g.x;
       nch = (len + 63u) >> 6;
@@ -1247,11 +1238,12 @@ int depth_sort_by_view(const uint32_t* dkey, const uint64_t* vmask, int64_t n_wc
   return cur;
 }
 
-void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_t n_rows,
-                    const uint32_t* vval, const uint32_t* rowbox, const float* rec, DSettings S,
-                    int64_t chunk_cap, int64_t rhist_cap, int64_t row_cap, const uint32_t* n_runs,
-                    uint4* vinfo, uint16_t* cview, uint32_t* rhist, uint32_t* counts, uint2* runs,
-                    uint2* rrange, uint32_t* flag, void* scratch, hipStream_t st) {
+void splats_to_rows(const uint2* vrange, int n_views, const DView* views,
+                    int64_t max_tiles_y, const uint32_t* vval, const uint32_t* rowbox,
+                    const float* rec, DSettings S, int64_t chunk_cap, int64_t rhist_cap,
+                    int64_t row_cap, uint4* vinfo, uint16_t* cview, uint32_t* rhist,
+                    uint32_t* counts, uint2* runs, uint32_t* flag, void* scratch,
+                    hipStream_t st) {
   // counts: [0] chunks, [1] table entries, [2] runs laid down
   hipLaunchKernelGGL(k_view_table, dim3(1), dim3(1024), 0, st, vrange, n_views, views, vinfo,
                      (uint32_t)std::min<int64_t>(rhist_cap, UINT32_MAX), counts, chunk_cap, cview);
@@ -1259,19 +1251,17 @@ void splats_to_rows(const uint2* vrange, int n_views, const DView* views, int64_
   if (blocks > 0)
     hipLaunchKernelGGL(k_rows_count, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
                        counts + 0, vval, rowbox, rhist, rhist_cap);
-  scan_generic(InPlain{rhist}, InPlain{rhist}, OutStore{rhist}, counts + 1, rhist_cap, counts + 2,
-               scratch, st);
-  if (n_rows > 0)
-    hipLaunchKernelGGL(k_row_ranges, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st,
-                       vinfo, views, n_views, rhist, counts + 1, counts + 2, n_runs, n_rows,
-                       (uint32_t)std::min<int64_t>(row_cap, UINT32_MAX), rrange, flag);
+  // the table holds at most (largest tiles_y) x chunks entries: the scan's grid covers that
+  // bound rather than the buffer, which an earlier call with smaller tiles may have grown
+  scan_generic(InPlain{rhist}, InPlain{rhist}, OutStore{rhist}, counts + 1,
+               std::min(rhist_cap, max_tiles_y * chunk_cap), counts + 2, scratch, st);
   if (blocks > 0)
     hipLaunchKernelGGL(k_rows_write, dim3((unsigned)blocks), dim3(256), 0, st, vinfo, cview,
                        counts + 0, vval, rec, views, S, rhist, rhist_cap, row_cap, runs, flag);
 }
 
-void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, int64_t n_tiles,
-            const uint2* runs, int64_t chunk_cap,
+void expand(const RowRuns& rr, int n_rows, const DView* views, int n_views, int64_t n_tiles,
+            int64_t max_tiles_x, const uint2* runs, int64_t chunk_cap,
             int64_t hist_cap, int64_t pair_cap, const uint32_t* n_pairs, uint4* rinfo,
             uint32_t* crow, uint32_t* hist, uint32_t* counts, uint32_t* pval, uint2* ranges,
             uint32_t* flag, void* scratch, hipStream_t st) {
@@ -1281,8 +1271,8 @@ void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, in
     fill_u32(reinterpret_cast<uint32_t*>(ranges), 2 * n_tiles, 0u, st);
     return;
   }
-  hipLaunchKernelGGL(k_row_table, dim3(1), dim3(1024), 0, st, rrange, n_rows, views, n_views,
-                     rinfo, (uint32_t)std::min<int64_t>(hist_cap, UINT32_MAX), counts);
+  hipLaunchKernelGGL(k_row_table, dim3(1), dim3(1024), 0, st, rr, n_rows, views, n_views,
+                     rinfo, (uint32_t)std::min<int64_t>(hist_cap, UINT32_MAX), counts, flag);
   hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)n_rows), dim3(256), 0, st, rinfo, chunk_cap,
                      crow);
   // per XCD enough workgroups to fill its CUs, each striding over that XCD's chunks
@@ -1290,8 +1280,9 @@ void expand(const uint2* rrange, int n_rows, const DView* views, int n_views, in
   const unsigned blocks = (unsigned)(kXcds * per_xcd);
   hipLaunchKernelGGL(k_expand_count, dim3(blocks), dim3(256), 0, st, rinfo, crow, chunk_cap,
                      counts, runs, hist, hist_cap);
-  scan_generic(InPlain{hist}, InPlain{hist}, OutStore{hist}, counts + kXcds, hist_cap,
-               counts + kXcds + 1, scratch, st);
+  // at most (largest tiles_x) x chunks entries (see splats_to_rows)
+  scan_generic(InPlain{hist}, InPlain{hist}, OutStore{hist}, counts + kXcds,
+               std::min(hist_cap, max_tiles_x * chunk_cap), counts + kXcds + 1, scratch, st);
   hipLaunchKernelGGL(k_expand_ranges, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st,
                      rinfo, views, n_views, hist, counts + kXcds, counts + kXcds + 1, n_pairs,
                      n_tiles, (uint32_t)std::min<int64_t>(pair_cap, 1 << 29), ranges, flag);
