@@ -426,8 +426,8 @@ __device__ __forceinline__ bool ellipse_band_xrange(float a, float b, float c, f
 
 // Tile columns of tile row `ty` that hold a pixel centre the splat's cutoff ellipse (slightly
 // widened) can reach, clipped to [tx0, tx1]: returns (first << 16) | last, or -1 if none.
-// Not inlined, so that the preprocess (which counts the pairs) and the key generation (which
-// writes them) run the very same instructions and always agree.
+// Not inlined, so that the preprocess (which counts the pairs) and the splats -> rows write
+// (which lays the runs of columns down) run the very same instructions and always agree.
 __device__ __noinline__ int tile_row_span(float u, float v, float a, float b, float c, float lim,
                                           float ex, float ey, int ty, int shift, int width,
                                           int height, int tx0, int tx1) {

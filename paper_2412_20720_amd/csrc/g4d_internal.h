@@ -8,11 +8,19 @@
 
 namespace g4d {
 
+// Flags in the high bits of a listed slot's tile count: the color channel was held at
+// color_min (its gradient is zero).
+constexpr uint32_t kClampR = 1u << 29, kClampG = 1u << 30, kClampB = 1u << 31;
+constexpr uint32_t kTileCountMask = (1u << 29) - 1u;
+
 constexpr int kScanItems = 4096;  // items per workgroup in scans and radix-sort passes
 constexpr int kSortThreads = 256;
 
 // p[0..n) = v (a kernel, not a memset node, so that captured graphs replay it correctly).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+// dst[0..n) = src[0..n) & mask.
+void copy_masked_u32(uint32_t* dst, const uint32_t* src, int64_t n, uint32_t mask,
+                     hipStream_t st);
 
 // Scratch needed by scan_* for up to `n` items (bytes).
 size_t scan_scratch_bytes(int64_t n);
@@ -98,6 +106,8 @@ struct GradPtrs {
   float *mask, *densify;  // optional: straight-through dL/dM; [N][3] densification statistics
 };
 
+// tiles[slot] = the slot's tile count (below 2^29: a tile has at least 64 pixels) with, for a
+// listed slot, kClampR / G / B set where that color channel was held at color_min.
 // Per wave of 64 Gaussians (n_wc = ceil(n / 256) * 4 of them), optional: wsum[wave] = the
 // (Gaussian, tile) pairs and (Gaussian, tile row) runs it listed, each held at 2^31, and
 // vmask[v * n_wc + wave] = the mask of its lanes whose Gaussian is listed in view v.
@@ -110,9 +120,10 @@ void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs
 // Adjoint of the preprocess: reads the listing counts, the forward's records (their stored
 // colors decide the color clamp) and the screen-space gradient slots, writes every parameter
 // gradient once and leaves the slots zero.
+// tiles: the forward's per-slot tile counts with their clamp flags (kClamp*).
 void preprocess_backward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
-                         const uint32_t* tiles, const float* rec, float* grad2d,
-                         const GradPtrs& out, hipStream_t st);
+                         const uint32_t* tiles, float* grad2d, const GradPtrs& out,
+                         hipStream_t st);
 
 struct RasterArgs {
   const float* rec;

@@ -1,7 +1,7 @@
 // Host runtime behind the C ABI of include/g4d.h: argument checks, per-batch planning (tile
 // grids and pixel offsets of every view), device scratch management and the launch sequence
-//   view setup -> preprocess -> compaction -> depth sort -> pair offsets -> key generation
-//   -> tile sort -> tile ranges -> raster            (forward)
+//   view setup -> preprocess -> depth sort per view -> splats to tile-row runs -> runs to
+//   tile lists and ranges -> raster                  (forward)
 //   raster backward -> preprocess backward           (backward)
 // All arithmetic of the render happens in the kernels; the host only does integer planning.
 #include <hip/hip_runtime.h>
@@ -556,9 +556,9 @@ g4d_status g4d_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_view* 
   if (records)
     G4D_HIP(hipMemcpyAsync(records, ctx->rec.p, sizeof(float) * kRec * slots,
                            hipMemcpyDeviceToDevice, st));
-  if (tiles)
-    G4D_HIP(hipMemcpyAsync(tiles, ctx->tiles.p, sizeof(uint32_t) * slots, hipMemcpyDeviceToDevice,
-                           st));
+  if (tiles)  // the counts without the clamp flags the backward reads
+    copy_masked_u32(reinterpret_cast<uint32_t*>(tiles), P<uint32_t>(ctx->tiles), slots,
+                    kTileCountMask, st);
   return G4D_OK;
 }
 
@@ -869,7 +869,7 @@ static g4d_status backward_impl(g4d_ctx* ctx, const g4d_gaussians* g, const g4d_
   {
     Stage t(ctx, 7, st);
     preprocess_backward(gauss_ptrs(g), P<DView>(ctx->views), n_views, DS, P<uint32_t>(ctx->tiles),
-                        P<float>(ctx->rec), P<float>(ctx->grad2d), gp, st);
+                        P<float>(ctx->grad2d), gp, st);
     G4D_HIP(hipGetLastError());
   }
   ctx->grad2d_zero = true;

@@ -17,7 +17,8 @@ namespace {
 // of tiles (of the reach box), the rows of the 64 splats are numbered by a wave scan and dealt
 // out 64 per round, and each lane adds its row's run of tile columns to the row owner's count
 // in LDS.  A wave so takes about (rows of its splats) / 64 rounds per view instead of the rows of
-// its largest splat, and the count uses the very function the key generation writes with.
+// its largest splat, and the count uses the very function the splats -> rows write lays the
+// runs down with.
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -106,10 +107,14 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const bool vis = alive && view_forward(g, mean, V, S, f) && reach2(op * f.pt, S) > 0.f;
     float opt = 0.f, ex = 0.f, ey = 0.f;
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
-    uint32_t rows = 0;
+    uint32_t rows = 0, clamped = 0;
     if (vis) {
       opt = op * f.pt;
       color_forward<DS, DT>(shc, S, f);
+      // channels held at color_min (their gradient is zero), for the adjoint
+      clamped = (f.color[0] == S.color_min ? kClampR : 0u) |
+                (f.color[1] == S.color_min ? kClampG : 0u) |
+                (f.color[2] == S.color_min ? kClampB : 0u);
       reach_extent(f, reach2(opt, S), ex, ey);
       if (tile_rect(f.u, f.v, ex, ey, V, S.tile_shift, x0, x1, y0, y1))
         rows = (uint32_t)(y1 - y0 + 1);
@@ -160,7 +165,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
       dkey[slot] = __float_as_uint(f.x[2]);
     }
     if (live) {
-      tiles[slot] = cnt;
+      tiles[slot] = cnt > 0 ? cnt | clamped : 0u;
       // the tile rows of its box, first << 16 | last, for the row binning
       rowbox[slot] = cnt > 0 ? ((uint32_t)y0 << 16) | (uint32_t)y1 : ~0u;
     }
@@ -185,9 +190,10 @@ __global__ __launch_bounds__(256) void k_preprocess(
 // propagates the slot's gradient through the 4DSH color, the EWA splat, the projection and the
 // slice to M = R S, the mean, the opacity and the coefficients, summing over the views; at the
 // end it goes through the rotors and their normalization and writes every gradient once.  The
-// clamp at color_min is read from the color the forward stored: max(color_min, raw) equals
-// color_min where the clamp was taken (at raw = color_min exactly, the kink, the derivative is
-// taken as 0), and there the color passes no gradient; so the raw color is not rebuilt.
+// clamp at color_min comes from the flags the forward set in the slot's tile count where the
+// stored color max(color_min, raw) equals color_min (at raw = color_min exactly, the kink, the
+// derivative is taken as 0): there the color passes no gradient, so the raw color is not
+// rebuilt.
 // Each slot is zeroed once read, so the slots need no clearing before the next backward.
 // ------------------------------------------------------------------------------------------
 template <int DS, int DT>
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     const float4* __restrict__ rot_l, const float4* __restrict__ rot_r,
     const float* __restrict__ opacity, const float* __restrict__ sh,
     const DView* __restrict__ views, DSettings S, const uint32_t* __restrict__ tiles,
-    const float* __restrict__ rec, float* __restrict__ grad2d, GradPtrs out) {
+    float* __restrict__ grad2d, GradPtrs out) {
   constexpr int NK = (DS + 1) * (DS + 1);
   constexpr int NSH = (DT + 1) * NK * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,22 +239,19 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
     for (int j = 0; j < nv; ++j)
       listed |= (tiles[(size_t)(v0 + j) * n + gi] != 0u ? 1u : 0u) << j;
     float4 p0 = z, p1 = z, p2 = z;
-    float pc[3] = {0.f, 0.f, 0.f};
+    uint32_t pt = 0;  // the slot's tile count with its clamp flags
     auto fetch = [&](int v) {
       const size_t sl = (size_t)v * n + gi;
       const float4* gp = reinterpret_cast<const float4*>(grad2d + sl * kGrad2d);
       p0 = gp[0];
       p1 = gp[1];
       p2 = gp[2];
-      const float* col = rec + sl * kRec + R_R;
-      pc[0] = col[0];
-      pc[1] = col[1];
-      pc[2] = col[2];
+      pt = tiles[sl];
     };
     if (listed & 1u) fetch(v0);
     for (int j = 0; j < nv; ++j) {
       const float4 q0 = p0, q1 = p1, q2 = p2;
-      const float col[3] = {pc[0], pc[1], pc[2]};
+      const uint32_t tw = pt;
       if (j + 1 < nv && ((listed >> (j + 1)) & 1u)) fetch(v0 + j + 1);
       if (!((listed >> j) & 1u)) continue;
       const int v = v0 + j;
@@ -264,9 +267,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
       ViewFwd f;
       view_forward<false>(g, mean, V, S, f);
       // ---- 4DSH color: dL/dk, and the color's share of dL/d(direction) and dL/d(dt) ----
-      const float graw[3] = {(col[0] == S.color_min) ? 0.f : q1.z,
-                             (col[1] == S.color_min) ? 0.f : q1.w,
-                             (col[2] == S.color_min) ? 0.f : q2.x};
+      const float graw[3] = {(tw & kClampR) ? 0.f : q1.z, (tw & kClampG) ? 0.f : q1.w,
+                             (tw & kClampB) ? 0.f : q2.x};
       float Y[NK], w[NK];
       sh_basis<DS>(f.dir[0], f.dir[1], f.dir[2], Y);
 #pragma unroll
@@ -415,14 +417,13 @@ void dispatch_decode_t(int n, int dt, const CompactPtrs& cp, float* mean4, float
 
 template <int DS, int DT>
 void launch_bwd(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                const uint32_t* tiles, const float* rec, float* grad2d, const GradPtrs& out,
-                hipStream_t st) {
+                const uint32_t* tiles, float* grad2d, const GradPtrs& out, hipStream_t st) {
   hipLaunchKernelGGL((k_preprocess_bwd<DS, DT>), dim3((unsigned)((gp.n + 255) / 256)), dim3(256),
                      0, st, gp.n, n_views, reinterpret_cast<const float4*>(gp.mean4),
                      reinterpret_cast<const float4*>(gp.scale4),
                      reinterpret_cast<const float4*>(gp.rot_l),
                      reinterpret_cast<const float4*>(gp.rot_r), gp.opacity, gp.sh, views, S,
-                     tiles, rec, grad2d, out);
+                     tiles, grad2d, out);
 }
 
 template <int DS>
@@ -438,12 +439,12 @@ void dispatch_fwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S
 
 template <int DS>
 void dispatch_bwd_t(const GaussPtrs& gp, const DView* views, int nv, DSettings S,
-                    const uint32_t* tiles, const float* rec, float* grad2d, const GradPtrs& out,
+                    const uint32_t* tiles, float* grad2d, const GradPtrs& out,
                     hipStream_t st) {
   switch (gp.t_degree) {
-    case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
-    case 1: launch_bwd<DS, 1>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
-    default: launch_bwd<DS, 2>(gp, views, nv, S, tiles, rec, grad2d, out, st); break;
+    case 0: launch_bwd<DS, 0>(gp, views, nv, S, tiles, grad2d, out, st); break;
+    case 1: launch_bwd<DS, 1>(gp, views, nv, S, tiles, grad2d, out, st); break;
+    default: launch_bwd<DS, 2>(gp, views, nv, S, tiles, grad2d, out, st); break;
   }
 }
 
@@ -474,14 +475,14 @@ void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs
 }
 
 void preprocess_backward(const GaussPtrs& gp, const DView* views, int n_views, DSettings S,
-                         const uint32_t* tiles, const float* rec, float* grad2d,
-                         const GradPtrs& out, hipStream_t st) {
+                         const uint32_t* tiles, float* grad2d, const GradPtrs& out,
+                         hipStream_t st) {
   if (gp.n == 0) return;
   switch (gp.sh_degree) {
-    case 0: dispatch_bwd_t<0>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
-    case 1: dispatch_bwd_t<1>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
-    case 2: dispatch_bwd_t<2>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
-    default: dispatch_bwd_t<3>(gp, views, n_views, S, tiles, rec, grad2d, out, st); break;
+    case 0: dispatch_bwd_t<0>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    case 1: dispatch_bwd_t<1>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    case 2: dispatch_bwd_t<2>(gp, views, n_views, S, tiles, grad2d, out, st); break;
+    default: dispatch_bwd_t<3>(gp, views, n_views, S, tiles, grad2d, out, st); break;
   }
 }
 

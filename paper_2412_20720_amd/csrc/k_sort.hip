@@ -1,10 +1,10 @@
-// Binning kernels: stream compaction of visible (view, Gaussian) slots, device-wide scans, a
-// per-view LDS-staged wavefront LSD radix sort by depth, and the row binning.
+// Binning kernels: device-wide scans, a per-view LDS-staged wavefront LSD radix sort of the
+// listed (view, Gaussian) slots by depth, and the row binning.
 //
 // Binning follows the tile-based rasterizer the paper adopts (Sec. 3.2): every splat is
 // listed in each screen tile its reach ellipse touches, and each tile's list is ordered by
 // camera depth, front to back (Sec. 3.1 composites the splats in depth order).  Here the
-// depth order is made once per visible splat (a 32-bit sort of each view's compacted slots);
+// depth order is made once per visible splat (a 32-bit sort of each view's listed slots);
 // each view's splats are then transposed, in depth order, into runs of tile columns per tile
 // row, and the runs into the tile lists, each by a count pass, one scan and a write pass, so
 // each tile's list inherits the depth order (ties keep the slot order, i.e. the Gaussian index).
@@ -206,14 +206,16 @@ void scan_generic(InSum in_sum, In in, Out out, const uint32_t* n_dev, int64_t n
 }
 
 // ------------------------------------------------------------------------------------------
-// Depth sort within each view.  The compacted visible slots come in slot order and slots are
-// view-major (slot = view * N + Gaussian), so each view's splats already lie together; a
-// stable LSD radix sort of the depth keys inside each view's segment (8 bits per pass) leaves
-// them grouped by view, in depth order, slot order among equal keys.  A radix workgroup takes
-// up to kRadixItems items of one view.  A pass counts digits per workgroup, turns each view's
-// counts into scatter offsets with one workgroup per view (the scan starts at the view's first
-// slot) and scatters.  Each wave owns a contiguous 1024-item run of its workgroup; ranks
-// inside a wave come from ballot-based digit matching, so equal digits keep their input order.
+// Depth sort within each view.  Slots are view-major (slot = view * N + Gaussian), so each
+// view's listed slots lie together, in slot order; a stable LSD radix sort of their depth keys
+// inside each view's segment (8 bits per pass) leaves them grouped by view, in depth order,
+// slot order among equal keys, with no compaction and no pass over all views.  The first pass
+// takes the listed slots straight from the preprocess's arrays (workgroups of kRadixItems slots
+// of one view); the later passes take up to kRadixItems listed slots of one view per
+// workgroup.  A pass counts digits per workgroup, turns each view's counts into scatter
+// offsets with one workgroup per view (starting at the view's place in the sorted list) and
+// scatters.  Each wave owns a contiguous 1024-item run of its workgroup; ranks inside a wave
+// come from ballot-based digit matching, so equal digits keep their input order.
 // ------------------------------------------------------------------------------------------
 
 // The items of a radix workgroup.  The first pass reads the preprocess's arrays themselves:
@@ -580,8 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
 // ------------------------------------------------------------------------------------------
 
 // ------------------------------------------------------------------------------------------
-// Splats to tile rows.  After the depth sort the visible slots are regrouped by view (one
-// stable pass on the view index), so that each view's splats lie together in depth order.
+// Splats to tile rows.  After the depth sort each view's splats lie together in depth order.
 // Each view's list is taken 64 splats at a time (a chunk, one wave): a count pass tallies how
 // many of the chunk's splats have each tile row of the view in their box (an LDS difference
 // array), an exclusive scan over (row, chunk) in row order gives every chunk its place in each
@@ -1166,6 +1167,12 @@ __global__ void k_tile_ids(const uint2* __restrict__ ranges, int64_t n_tiles, in
 // Tile boundaries in the sorted keys, four keys per thread (one 16-byte load; the neighbours
 // on either side come from the caches).
 // Four keys per thread (one 4-key vector load), compared with their neighbours.
+__global__ void k_copy_masked_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                  int64_t n, uint32_t mask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] & mask;
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1190,6 +1197,13 @@ __global__ void k_view_setup(DView* views, int n_views, float m) {
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+void copy_masked_u32(uint32_t* dst, const uint32_t* src, int64_t n, uint32_t mask,
+                     hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_masked_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst,
+                     src, n, mask);
 }
 
 size_t scan_scratch_bytes(int64_t n) {

@@ -4,8 +4,11 @@ tile-based rasterizer, Sec. 3.2; the depth order of Sec. 3.1's blending): the GP
 own depth keys (each visible slot in (depth, slot) order, its tiles ascending), every slot has as
 many pairs as its tile count, the tile ranges equal a recomputation from the sorted keys, and the
 listed tiles of sampled splats are exactly those whose pixel centres fall inside the splat's
-reach ellipse, up to a thin band of FP32 rounding at the border.  Run with 16-bit tile keys
-(one 1352x1014 view, 32-pixel tiles) and 32-bit keys (four views at 8-pixel tiles)."""
+reach ellipse, up to a thin band of FP32 rounding at the border.  Run on one 1352x1014 view at
+32-pixel tiles, on four views at 8-pixel tiles (more than 2^16 tiles), and on 20 small views, two
+of them facing away from the scene, with a Gaussian count that is not a multiple of the 64
+Gaussians of a listing mask or the 4,096 slots of a radix workgroup (the depth sort runs per
+view)."""
 import numpy as np
 import pytest
 
@@ -43,12 +46,33 @@ def test_sorted_pairs_and_ranges_exact(renderer, n_views, tile):
                                                            (0, 0, 0)), 0.2 + 0.2 * k)
                              for k, a in enumerate((0.7, 2.1, 4.0))][:n_views - 1]
     run = GpuRun(renderer, sc, views=views, tile_size=tile).forward()
+    check_lists_exact(renderer, run, sc, views, tile)
+
+
+def test_many_views_empty_views_ragged_count(renderer):
+    sc = scenes.subset(scenes.make_workload(1), np.arange(5000))
+    views = []
+    for k in range(18):
+        a = 2 * np.pi * k / 18
+        eye = (4 * np.sin(a), 0.3 + 0.1 * (k % 3), 4 * np.cos(a))
+        views.append(scenes.pinhole(320, 240, 60.0, scenes.look_at(eye, (0, 0, 0)), 0.05 * k))
+    away = [scenes.pinhole(320, 240, 60.0, scenes.look_at((0, 0, 4), (0, 0, 12)), 0.3),
+            scenes.pinhole(320, 240, 60.0, scenes.look_at((4, 0, 0), (12, 0, 0)), 0.6)]
+    views.insert(5, away[0])
+    views.insert(13, away[1])
+    run = GpuRun(renderer, sc, views=views, tile_size=16).forward()
+    cnt = check_lists_exact(renderer, run, sc, views, 16)
+    per_view = (cnt.reshape(len(views), -1) > 0).sum(1)
+    log(f"  listed per view: {per_view.tolist()}")
+    assert per_view[5] == 0 and per_view[13] == 0 and (np.delete(per_view, [5, 13]) > 0).all()
+
+
+def check_lists_exact(renderer, run, sc, views, tile):
+    """The checks above on the last forward; returns the tile count per slot."""
     st = renderer.stats()
     tid, slot, ranges = (t.numpy() for t in renderer.pairs())
     n_tiles = st["n_tiles"]
-    log(f"{n_views} view(s), tile {tile}: {st['n_pairs']} pairs, {n_tiles} tiles, "
-        f"{'32' if n_tiles + 1 > 65536 else '16'}-bit keys")
-    assert (n_tiles + 1 > 65536) == (n_views == 4)
+    log(f"{len(views)} view(s), tile {tile}: {st['n_pairs']} pairs, {n_tiles} tiles")
     rec, cnt = renderer.preprocess(run.g, views, run.settings)
     rec = rec.cpu().numpy().reshape(-1, 12)
     cnt = cnt.cpu().numpy().reshape(-1).astype(np.int64)
@@ -80,7 +104,7 @@ def test_sorted_pairs_and_ranges_exact(renderer, n_views, tile):
     rng = np.random.default_rng(3)
     alpha_min = 1.0 / 255.0
     n_band = 0
-    for s in rng.choice(vis, 400, replace=False):
+    for s in rng.choice(vis, min(400, len(vis)), replace=False):
         v = s // N
         base, tx, ty = grids[v]
         W, H = int(views[v]["width"]), int(views[v]["height"])
@@ -106,4 +130,6 @@ def test_sorted_pairs_and_ranges_exact(renderer, n_views, tile):
         assert inside <= listed, (s, sorted(inside - listed)[:5])
         assert listed <= maybe, (s, sorted(listed - maybe)[:5])
         n_band += len(listed - inside)
-    log(f"  tile sets of 400 splats: {n_band} listed tiles reached only within the rounding band")
+    log(f"  tile sets of {min(400, len(vis))} splats: {n_band} listed tiles reached only within "
+        f"the rounding band")
+    return cnt
