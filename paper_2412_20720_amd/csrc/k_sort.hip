@@ -572,13 +572,12 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
 // ------------------------------------------------------------------------------------------
 // Row binning.  The tiles a splat is listed in are, in each tile row of its box, one run of
 // columns (tile_row_span).  Instead of one (tile, splat) pair per tile, sorted by tile, the
-// runs are emitted (one per box row, visible splats in depth order), sorted stably by their
-// global tile row, and expanded: each row's runs are taken 64 at a time (a chunk, one wave), a
-// count pass tallies how many runs of the chunk cover each column, an exclusive scan over
-// (tile, chunk) in tile order gives every chunk its place in each tile's list, and a write
-// pass lays the slots down.  A tile's list so holds its splats in depth order (the runs enter
-// the stable row sort in depth order), exactly as a stable sort of the individual pairs by
-// tile would leave them; the sort moves one item per run instead of one per pair.
+// depth-ordered splats of each view are transposed into per-tile-row lists of runs (splats ->
+// rows) and each row's runs into the tile lists (rows -> tiles).  Each transpose is a count pass
+// over chunks of 64 items (one wave each), one exclusive scan of the (row or column, chunk)
+// count table, and a write pass; since every list takes its chunks in order and each chunk's
+// items in order, a tile's list holds its splats in depth order, exactly as a stable sort of
+// the individual pairs by tile would leave them, without sorting anything.
 // ------------------------------------------------------------------------------------------
 
 // ------------------------------------------------------------------------------------------
@@ -601,11 +600,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
   return x;
-}
-
-// Rows of a packed row box (first << 16 | last; ~0u: none).
-__device__ __forceinline__ uint32_t box_rows(uint32_t rb) {
-  return rb == ~0u ? 0u : (rb & 0xFFFFu) - (rb >> 16) + 1u;
 }
 
 // Per view v (one workgroup of 1024 threads, a thread per view): its splats [lo, lo + len) in
@@ -1164,9 +1158,6 @@ __global__ void k_tile_ids(const uint2* __restrict__ ranges, int64_t n_tiles, in
   }
 }
 
-// Tile boundaries in the sorted keys, four keys per thread (one 16-byte load; the neighbours
-// on either side come from the caches).
-// Four keys per thread (one 4-key vector load), compared with their neighbours.
 __global__ void k_copy_masked_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
                                   int64_t n, uint32_t mask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
