@@ -207,11 +207,42 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   constexpr int NSH = (DT + 1) * NK * 3;
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n) return;
-  const float4 sc = scale4[gi];
-  Geom g;
-  geom_forward(rot_l[gi], rot_r[gi], sc, g);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  // A Gaussian listed in no view (culled, masked or off screen) has every gradient exactly
+  // zero, also for parameters that are not finite (their forward culled them): it writes the
+  // zeros without reading its coefficients (most Gaussians, when few are in view).  The listing
+  // flags of the first 32 views (the first chunk of the view loop below) and of any later view
+  // are loaded, with no early exit, together with the geometry parameters, so that only the
+  // coefficient loads wait for the test.
+  const int nv0 = n_views < 32 ? n_views : 32;
+  uint32_t listed0 = 0, listed_any = 0;
+  for (int j = 0; j < nv0; ++j) listed0 |= (tiles[(size_t)j * n + gi] != 0u ? 1u : 0u) << j;
+  for (int v = 32; v < n_views; ++v) listed_any |= tiles[(size_t)v * n + gi];
+  listed_any |= listed0;
+  const float4 sc = scale4[gi], qlr = rot_l[gi], qrr = rot_r[gi];
   const float4 mean = mean4[gi];
   const float op = opacity[gi];
+  if (listed_any == 0u) {
+    if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = z;
+    if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = z;
+    if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = z;
+    if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = z;
+    if (out.opacity) out.opacity[gi] = 0.f;
+    if (out.mask) out.mask[gi] = 0.f;
+    if (out.densify) {
+      out.densify[3 * (size_t)gi + 0] = 0.f;
+      out.densify[3 * (size_t)gi + 1] = 0.f;
+      out.densify[3 * (size_t)gi + 2] = 0.f;
+    }
+    if (out.sh) {
+      float* o = out.sh + (size_t)gi * NSH;
+#pragma unroll
+      for (int k = 0; k < NSH; ++k) o[k] = 0.f;
+    }
+    return;
+  }
+  Geom g;
+  geom_forward(qlr, qrr, sc, g);
   float shc[NSH], gsh[NSH];
   const float* shp = sh + (size_t)gi * NSH;
 #pragma unroll
@@ -230,14 +261,17 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
   int nvis = 0;
   const float om = 6.283185307179586f / S.time_period;
   // Views in chunks of 32: the chunk's listing flags are loaded together, and each view's
-  // gradient slot and stored color are loaded one view ahead, so that their latency overlaps
-  // the current view's arithmetic (one wave per SIMD leaves nothing else to hide it).
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  // gradient slot and tile count (with the clamp flags) are loaded one view ahead, so that their
+  // latency overlaps the current view's arithmetic (one wave per SIMD leaves nothing else to
+  // hide it).
   for (int v0 = 0; v0 < n_views; v0 += 32) {
     const int nv = n_views - v0 < 32 ? n_views - v0 : 32;
-    uint32_t listed = 0;
-    for (int j = 0; j < nv; ++j)
-      listed |= (tiles[(size_t)(v0 + j) * n + gi] != 0u ? 1u : 0u) << j;
+    uint32_t listed = listed0;
+    if (v0 > 0) {
+      listed = 0;
+      for (int j = 0; j < nv; ++j)
+        listed |= (tiles[(size_t)(v0 + j) * n + gi] != 0u ? 1u : 0u) << j;
+    }
     float4 p0 = z, p1 = z, p2 = z;
     uint32_t pt = 0;  // the slot's tile count with its clamp flags
     auto fetch = [&](int v) {
@@ -309,27 +343,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(
       const float q[10] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, 0.f, 0.f, 0.f, q2.y};
       view_backward_geom(g, op, V, f, q, gmuc, gdt, gM, gmean, gop);
     }
-  }
-  if (nvis == 0) {
-    // listed in no view (culled, masked or off screen): every gradient is exactly zero, also
-    // for parameters that are not finite (their forward culled them)
-    if (out.mean4) reinterpret_cast<float4*>(out.mean4)[gi] = z;
-    if (out.scale4) reinterpret_cast<float4*>(out.scale4)[gi] = z;
-    if (out.rot_l) reinterpret_cast<float4*>(out.rot_l)[gi] = z;
-    if (out.rot_r) reinterpret_cast<float4*>(out.rot_r)[gi] = z;
-    if (out.opacity) out.opacity[gi] = 0.f;
-    if (out.mask) out.mask[gi] = 0.f;
-    if (out.densify) {
-      out.densify[3 * (size_t)gi + 0] = 0.f;
-      out.densify[3 * (size_t)gi + 1] = 0.f;
-      out.densify[3 * (size_t)gi + 2] = 0.f;
-    }
-    if (out.sh) {
-      float* o = out.sh + (size_t)gi * NSH;
-#pragma unroll
-      for (int k = 0; k < NSH; ++k) o[k] = 0.f;
-    }
-    return;
   }
   float gs[4], gql[4], gqr[4];
   geom_backward(g, sc, gM, gs, gql, gqr);
