@@ -47,11 +47,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _code_only(text):
+    """C++ source with its comments removed and whitespace runs collapsed, so that an edit to
+    a comment leaves the hash of the code unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def raster_source_hash():
+    """Hash of the raster kernel's code (comments excluded) that the counter summaries were
+    taken with."""
     import hashlib
     h = hashlib.sha256()
     for f in ("k_raster.hip", "g4d_device.h", "g4d_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2412_20720_amd", "csrc", f), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2412_20720_amd", "csrc", f)).read()
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

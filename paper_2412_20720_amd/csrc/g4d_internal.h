@@ -117,10 +117,10 @@ void preprocess_forward(const GaussPtrs& g, const DView* views, int n_views, DSe
 void decode_compact_params(int n, int sh_degree, int t_degree, const CompactPtrs& cp,
                            float* mean4, float* scale4, float* rot_l, float* rot_r,
                            float* opacity, float* sh, hipStream_t st);
-// Adjoint of the preprocess: reads the listing counts, the forward's records (their stored
-// colors decide the color clamp) and the screen-space gradient slots, writes every parameter
-// gradient once and leaves the slots zero.
-// tiles: the forward's per-slot tile counts with their clamp flags (kClamp*).
+// Adjoint of the preprocess: reads the forward's per-slot tile words (a nonzero word: the slot
+// is listed; kClamp*: that color channel was held at color_min, its gradient is zero) and the
+// screen-space gradient slots, writes every parameter gradient once and leaves the slots zero.
+// A Gaussian listed in no view writes zero gradients.
 void preprocess_backward(const GaussPtrs& g, const DView* views, int n_views, DSettings S,
                          const uint32_t* tiles, float* grad2d, const GradPtrs& out,
                          hipStream_t st);
