@@ -393,7 +393,8 @@ g4d_status run_preprocess(g4d_ctx* ctx, const g4d_gaussians* g, int n_views,
   const int64_t slots = (int64_t)g->n * n_views;
   g4d_status r;
   if ((r = ensure(ctx, ctx->rec, sizeof(float) * kRec * slots, 1.1)) != G4D_OK) return r;
-  if (zero_records) G4D_HIP(hipMemsetAsync(ctx->rec.p, 0, sizeof(float) * kRec * slots, st));
+  // a fill kernel rather than a memset, so that a captured graph replays the clear correctly
+  if (zero_records) fill_u32(P<uint32_t>(ctx->rec), (int64_t)kRec * slots, 0u, st);
   if ((r = ensure(ctx, ctx->tiles, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->rowbox, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
   if ((r = ensure(ctx, ctx->dkey, sizeof(uint32_t) * slots, 1.1)) != G4D_OK) return r;
