@@ -444,22 +444,56 @@ __device__ __noinline__ int tile_row_span(float u, float v, float a, float b, fl
   return c0 <= c1 ? (c0 << 16) | c1 : -1;
 }
 
+// Inclusive scan under `op` (identity id) over the 64 lanes of a wave, all lanes active.  It
+// stays in registers: DPP moves add the values 1, 2, 4 and 8 lanes below within each row of 16
+// lanes, then the last lane of rows 0 and 2 to the rows above them (row_bcast:15, rows 1 and 3)
+// and lane 31 to rows 2 and 3 (row_bcast:31).  A lane a move does not write keeps id.
+template <class Op>
+__device__ __forceinline__ uint32_t wave_scan_op(uint32_t x, uint32_t id, Op op) {
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x111, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x112, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x114, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x118, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x142, 0xa, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)x, 0x143, 0xc, 0xf, false));
+  return x;
+}
+
 // Inclusive and exclusive prefix sums over the 64 lanes of a wave (all lanes active); the
 // exclusive one also returns the wave total.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  return x;
+  return wave_scan_op(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t& total) {
   const uint32_t inc = wave_incl_scan(x);
-  total = __shfl(inc, 63, 64);
+  total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
   return inc - x;
+}
+
+// Owner of item k0 + lane in a window of 64 items (k0 a multiple of 64), where lane l holds the
+// items [first_l, first_l + count_l), numbered in lane order with no gaps: the last lane whose
+// run starts at or before the item.  Each lane whose run starts in the window marks its start
+// in the wave's 64-word LDS array `mark` with the round's stamp, and a max scan carries each
+// mark up to the next; `carry` passes the owner of the window's last item on to the next window
+// (-1 before the first window of a numbering), `stamp` is a wave-uniform counter, 1 or more,
+// that no earlier call of the wave used (the array starts at 0).  Every lane of the wave calls
+// it; for every item below the total the owner is a lane with count > 0.
+__device__ __forceinline__ int window_owner(uint32_t first, uint32_t count, uint32_t k0,
+                                            uint32_t* mark, uint32_t& stamp, int& carry) {
+  const int lane = threadIdx.x & 63;
+  if (count > 0u && first - k0 < 64u) mark[first - k0] = (stamp << 6) | (uint32_t)lane;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t m = mark[lane];
+  // owner + 1, so that 0 (no mark) is the identity of the max
+  uint32_t o = (m >> 6) == stamp ? (m & 63u) + 1u : 0u;
+  o = wave_scan_op(o, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
+  int own = max((int)o - 1, carry);
+  carry = __builtin_amdgcn_readlane(own, 63);
+  ++stamp;
+  return own < 0 ? 0 : own;
 }
 
 // Bound used for tile coverage: 1e-3 above reach2, so that FP32 rounding in the coverage test

@@ -48,12 +48,14 @@ __global__ __launch_bounds__(256) void k_preprocess(
   __shared__ float s_u[4][64], s_v[4][64], s_a[4][64], s_b[4][64], s_c[4][64], s_lim[4][64];
   __shared__ float s_ex[4][64], s_ey[4][64];
   __shared__ int32_t s_y0[4][64], s_x0[4][64], s_x1[4][64];
-  __shared__ uint32_t s_row0[4][64], s_cnt[4][64];
+  __shared__ uint32_t s_mark[4][64], s_cnt[4][64];
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wave = blockIdx.x * 4 + w;
   const size_t n_wc = (size_t)gridDim.x * 4;
   const bool in_range = gi < n;
+  s_mark[w][lane] = 0u;  // no round's stamp (window_owner)
+  uint32_t stamp = 1u;
   // volume mask (Sec. 4.3): M_hat = 0 scales S and the opacity to zero, the Gaussian is gone
   const bool live = in_range && !(mask && !(mask[gi] > mask_thr));
   if (in_range && !live)
@@ -134,18 +136,16 @@ __global__ __launch_bounds__(256) void k_preprocess(
       s_y0[w][lane] = y0;
       s_x0[w][lane] = x0;
       s_x1[w][lane] = x1;
-      s_row0[w][lane] = row0;
       s_cnt[w][lane] = 0u;
       wave_sync();
+      int carry = -1;
       for (uint32_t k0 = 0; k0 < total; k0 += 64) {
         const uint32_t k = k0 + (uint32_t)lane;
+        // the last lane whose rows start at or before k owns row k
+        const int lo = window_owner(row0, rows, k0, &s_mark[w][0], stamp, carry);
+        const uint32_t lo_row0 = (uint32_t)__shfl((int)row0, lo, 64);
         if (k < total) {
-          int lo = 0, hi = 63;  // the last lane whose rows start at or before k owns row k
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_row0[w][mid] <= k) lo = mid; else hi = mid - 1;
-          }
-          const int ty = s_y0[w][lo] + (int)(k - s_row0[w][lo]);
+          const int ty = s_y0[w][lo] + (int)(k - lo_row0);
           const int span = tile_row_span(s_u[w][lo], s_v[w][lo], s_a[w][lo], s_b[w][lo],
                                          s_c[w][lo], s_lim[w][lo], s_ex[w][lo], s_ey[w][lo], ty,
                                          S.tile_shift, V.width, V.height, s_x0[w][lo],

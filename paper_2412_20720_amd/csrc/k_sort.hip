@@ -591,15 +591,14 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
 // depth order.
 // ------------------------------------------------------------------------------------------
 
+// Minimum and maximum over the 64 lanes of a wave (all lanes active), wave-uniform.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
+  x = wave_scan_op(x, ~0u, [](uint32_t a, uint32_t b) { return min(a, b); });
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o, 64));
-  return x;
+  x = wave_scan_op(x, 0u, [](uint32_t a, uint32_t b) { return max(a, b); });
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 // Per view v (one workgroup of 1024 threads, a thread per view): its splats [lo, lo + len) in
@@ -796,10 +795,12 @@ __global__ __launch_bounds__(256) void k_rows_write(const uint4* __restrict__ vi
   __shared__ int32_t s_x0[4][64], s_x1[4][64];
   __shared__ uint32_t s_slot[4][64];
   __shared__ uint64_t s_mask[4][64];
-  __shared__ uint32_t s_place[4][64], s_rfirst[4][64];
+  __shared__ uint32_t s_place[4][64], s_rfirst[4][64], s_mark[4][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
   if (g >= *n_chunks_dev) return;
+  s_mark[w][lane] = 0u;  // no round's stamp (window_owner)
+  uint32_t stamp = 1u;
   const uint32_t v = __builtin_amdgcn_readfirstlane((uint32_t)cview[g]);
   const uint4 va = vinfo[2 * v], vb = vinfo[2 * v + 1];
   const uint32_t c = g - va.z, nch = vb.x, ny = vb.y;
@@ -849,19 +850,18 @@ __global__ __launch_bounds__(256) void k_rows_write(const uint4* __restrict__ vi
       if ((uint32_t)lane == y - t0) mine = m;
     }
     uint32_t total;
-    const uint32_t rfirst = wave_excl_scan((uint32_t)__popcll(mine), total);
+    const uint32_t n_row = (uint32_t)__popcll(mine);
+    const uint32_t rfirst = wave_excl_scan(n_row, total);
     s_mask[w][lane] = mine;
     s_rfirst[w][lane] = rfirst;
     s_place[w][lane] = place;
     wave_lds_sync();
+    int carry = -1;
     for (uint32_t k0 = 0; k0 < total; k0 += 64) {
       const uint32_t k = k0 + (uint32_t)lane;
+      // the last row whose runs start at or before k holds run k
+      const int a = window_owner(rfirst, n_row, k0, &s_mark[w][0], stamp, carry);
       if (k < total) {
-        int a = 0, b = 63;  // the last row whose runs start at or before k holds run k
-        while (a < b) {
-          const int m = (a + b + 1) >> 1;
-          if (s_rfirst[w][m] <= k) a = m; else b = m - 1;
-        }
         const uint32_t r = k - s_rfirst[w][a];
         const int j = nth_set_bit(s_mask[w][a], r);
         const int y = (int)t0 + a;
