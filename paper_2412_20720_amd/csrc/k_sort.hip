@@ -44,6 +44,11 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
+// acc + the set bits of m below this lane (v_mbcnt_lo and v_mbcnt_hi: two instructions).
+__device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t acc) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, acc));
+}
+
 
 // Exclusive scan of one value per thread over a 256-thread block; also returns the total.
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& total, uint32_t* lds4) {
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
     for (int r = 0; r < kRadixPerThread; ++r) {
       const uint32_t slot0 = base + (uint32_t)(r * 64);
       const uint64_t m = it.mask(vmask, row, slot0);
-      if ((m >> lane) & 1ull) stage[n_w + (uint32_t)__popcll(m & lt)] = slot0 + (uint32_t)lane;
+      if ((m >> lane) & 1ull) stage[rank_below(m, n_w)] = slot0 + (uint32_t)lane;
       n_w += (uint32_t)__popcll(m);
     }
     wave_lds_sync();
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
     const uint32_t d = (k[r] >> shift) & (kRadix - 1);
     const uint64_t peers = match_digit(d, __ballot(valid));
     const uint32_t before = wcount[w][d];
-    rank[r] = before + (uint32_t)__popcll(peers & lt);
+    rank[r] = rank_below(peers, before);
     __builtin_amdgcn_wave_barrier();
     if (valid && (peers & lt) == 0ull) wcount[w][d] = before + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
@@ -1110,7 +1115,6 @@ __global__ __launch_bounds__(256) void k_expand_write(const uint4* __restrict__ 
                                                       int64_t hist_cap, uint32_t pair_cap,
                                                       uint32_t* __restrict__ pval, uint32_t* flag) {
   const int lane = threadIdx.x & 63;
-  const uint64_t lt = lanemask_lt();
   // pair_cap is at most 2^29 here, so every offset below it fits the 32-bit range
   const __amdgpu_buffer_rsrc_t out =
       __builtin_amdgcn_make_buffer_rsrc(pval, 0, (int)(pair_cap * 4u), 0x00020000);
@@ -1140,7 +1144,7 @@ __global__ __launch_bounds__(256) void k_expand_write(const uint4* __restrict__ 
         const uint64_t m = __ballot(cov);
         if (m == 0ull) continue;
         const uint32_t base = __builtin_amdgcn_readlane(places, (int)(tx - t0));
-        const uint32_t pos = base + (uint32_t)__popcll(m & lt);
+        const uint32_t pos = rank_below(m, base);
         if (cov && pos < pair_cap)
           __builtin_amdgcn_raw_buffer_store_b32(ck.slot, out, (int)(pos * 4u), 0, 0);
       }
